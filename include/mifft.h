@@ -1,0 +1,191 @@
+/*
+ * mifft -- batched 1D complex-to-complex FFTs of power-of-two length on
+ * AMD Instinct MI355X (gfx950).  C ABI.
+ *
+ * What is computed (paper section "Fast Fourier Transform"):
+ *   forward, Eq. (dft):   X_k = sum_{n<N} x_n w_N^{kn},        w_N = exp(-2 pi i / N)
+ *   inverse, Eq. (idft):  x_k = (1/N) sum_{n<N} X_n w_N^{-kn}
+ * for every transform of a batch, by Cooley-Tukey / Stockham passes of
+ * radix 2..16 (section "Implementation": radix-2/4/8 stages selected on
+ * the host from N; single precision, complex-to-complex, out of place,
+ * N up to 2^11).  Both input and output are in natural order.
+ *
+ * Conventions shared by every entry point
+ *   - Data are interleaved (re, im) pairs.  FFT_C32: two float32 per element
+ *     (8 bytes, the layout of std::complex<float> / torch.complex64).
+ *     FFT_C16 / FFT_CBF16: two float16 / bfloat16 per element (4 bytes).
+ *   - Transform b of a batched plan occupies elements [b*n, (b+1)*n).
+ *   - `in` and `out` are device pointers owned by the caller, 16-byte
+ *     aligned, and must not overlap (out of place only).
+ *   - `stream` is a hipStream_t (NULL = the legacy default stream).  Every
+ *     execute call only enqueues work: it allocates nothing, synchronises
+ *     nothing and copies nothing, so it may be captured into a hipGraph.
+ *   - Status codes below; 0 is success.  The last status and a message
+ *     (including the HIP error string where HIP failed) are kept per host
+ *     thread: fft_last_error / fft_last_error_string.  Arguments are
+ *     checked before any HIP call is made.  Faults inside a kernel are
+ *     asynchronous and surface at the caller's next synchronisation.
+ *   - A plan is bound to the HIP device that was current when it was
+ *     created and is immutable afterwards, so executes of one plan on
+ *     several streams may run concurrently -- except ragged plans, whose
+ *     work counter is shared: executes of ONE ragged plan must not overlap
+ *     in time (use one plan per stream).
+ */
+#ifndef MIFFT_H
+#define MIFFT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mifft_plan_s *fft_plan;
+
+/* element types (interleaved complex) */
+enum {
+    FFT_C32 = 0,   /* float32 re, im  */
+    FFT_C16 = 1,   /* float16 re, im  */
+    FFT_CBF16 = 2  /* bfloat16 re, im */
+};
+
+/* status codes */
+enum {
+    FFT_OK = 0,
+    FFT_EINVAL_N = 1,       /* n not a power of two in [2, 2048]               */
+    FFT_EINVAL_BATCH = 2,   /* batch < 1, or the batch does not fit one launch  */
+    FFT_EINVAL_SIGN = 3,    /* sign not -1 or +1                               */
+    FFT_EINVAL_DTYPE = 4,   /* unknown dtype, or dtype not valid for the call   */
+    FFT_ENULL = 5,          /* a required pointer or plan is NULL               */
+    FFT_EOVERLAP = 6,       /* input and output byte ranges overlap             */
+    FFT_EINVAL_OFFSETS = 7, /* ragged offsets malformed                         */
+    FFT_EHIP = 8,           /* a HIP call failed (message has the HIP string)   */
+    FFT_ENOMEM = 9,         /* host or device allocation failed                 */
+    FFT_EINVAL_CONFIG = 10, /* requested kernel variant does not exist          */
+    FFT_EALIGN = 11,        /* in/out not 16-byte aligned                       */
+    FFT_EDEVICE = 12        /* current device is not a gfx950 GPU, or plan used
+                               while another device is current                  */
+};
+
+/* Description of what a plan launches (fft_plan_describe / fft_plan_query). */
+typedef struct {
+    int64_t n;          /* transform length (batched plans), 0 for ragged     */
+    int64_t batch;      /* transforms per execute                             */
+    int sign;           /* -1 forward (Eq. (dft)), +1 inverse (Eq. (idft))    */
+    int dtype;          /* FFT_C32 / FFT_C16 / FFT_CBF16                       */
+    float scale;        /* output scale: 1 (forward) or 1/n (inverse)         */
+    int ept;            /* complex elements held per thread                   */
+    int wg;             /* threads per workgroup                              */
+    int transforms_per_wg;
+    int64_t grid;       /* workgroups per execute                             */
+    int npasses;        /* Stockham passes                                    */
+    int radices[8];     /* radix of each pass, first to last                  */
+    int lds_bytes;      /* LDS per workgroup                                  */
+    int kind;           /* 0 batched, 1 ragged                                */
+    int64_t tiles;      /* ragged: work tiles                                 */
+} fft_plan_desc;
+
+/*
+ * Create a plan for `batch` transforms of length n.
+ *   n      power of two in [2, 2048] (section "Implementation": lengths up
+ *          to 2^11; lengths below 2^3 extend the paper's measured range).
+ *   batch  >= 1.
+ *   sign   -1: forward transform Eq. (dft), scale 1.
+ *          +1: inverse transform Eq. (idft), scale 1/n.
+ *   dtype  FFT_C32, FFT_C16 or FFT_CBF16.
+ * Binds to the current HIP device, allocates and fills the plan's twiddle
+ * table (blocking, on the legacy default stream).  Returns NULL on error;
+ * see fft_last_error().  The kernel variant (elements per thread and
+ * workgroup size) comes from the built-in tuned table, or from the file
+ * named by the environment variable MIFFT_TUNE_TABLE if set.
+ */
+fft_plan fft_plan_create(int64_t n, int64_t batch, int sign, int dtype);
+
+/*
+ * As fft_plan_create, forcing the kernel variant: `ept` complex elements
+ * per thread (2, 4, 8 or 16) and `wg` threads per workgroup (64, 128, 256
+ * or 512).  Used by the autotuner.  FFT_EINVAL_CONFIG if that variant is
+ * not compiled in.
+ */
+fft_plan fft_plan_create_config(int64_t n, int64_t batch, int sign, int dtype, int ept, int wg);
+
+/*
+ * Ragged batch: `count` transforms of mixed power-of-two lengths packed
+ * back to back.  `offsets` is a HOST array of count+1 int64 values, copied
+ * into the plan: offsets[0] = 0, and each length offsets[b+1]-offsets[b]
+ * is a power of two in [2, 2048]; transform b occupies elements
+ * [offsets[b], offsets[b+1]) of both input and output.  Every execute is
+ * one persistent kernel launch that pulls length-grouped work tiles from a
+ * plan-owned counter (largest transforms first) and resets the counter
+ * itself when done, so the launch can be captured into a hipGraph.
+ * Only FFT_C32.  sign as for fft_plan_create; the inverse scales each
+ * transform by 1/its length.
+ */
+fft_plan fft_plan_create_ragged(int64_t count, const int64_t *offsets, int sign, int dtype);
+
+/*
+ * As fft_plan_create_ragged with the per-length kernel variant forced:
+ * ept_by_log2n[L] (L = 1..11; entries 0 ignored) gives the elements per
+ * thread used for length 2^L, `wg` the workgroup size of the persistent
+ * launch (64..512) and `ctas_per_cu` how many workgroups per compute unit
+ * the launch holds (0: as many as fit).  Used by the autotuner.
+ */
+fft_plan fft_plan_create_ragged_config(int64_t count, const int64_t *offsets, int sign, int dtype,
+                                       const int *ept_by_log2n, int wg, int ctas_per_cu);
+
+/*
+ * Apply the plan's transform: out = plan(in).  Asynchronous on `stream`.
+ * Byte ranges: n*batch*elem_size (batched) or offsets[count]*elem_size
+ * (ragged) for both in and out.  FP16/BF16 plans behave as
+ * fft_execute_scaled with NULL exponent arrays.
+ */
+int fft_execute(fft_plan p, const void *in, void *out, void *stream);
+
+/*
+ * Apply the adjoint (conjugate transpose) of the plan's transform: the
+ * opposite sign at the SAME scale.  For a forward plan that is the
+ * unnormalised inverse sum (no 1/n); for an inverse plan it is the forward
+ * sum times 1/n.  Used as the backward pass of the differentiable FFT.
+ */
+int fft_execute_adjoint(fft_plan p, const void *in, void *out, void *stream);
+
+/*
+ * Block-floating-point execute for FFT_C16 / FFT_CBF16 plans: the logical
+ * value of transform b is stored * 2^exp[b].  `in_exp` (device int32[batch])
+ * may be NULL for all-zero input exponents.  `out_exp` (device int32[batch])
+ * receives the output exponents, chosen per transform so the stored
+ * half-precision output neither overflows nor loses range; if NULL the
+ * output is written at unit scale (values beyond the format's range become
+ * +-inf).  FFT_EINVAL_DTYPE on an FFT_C32 plan.
+ */
+int fft_execute_scaled(fft_plan p, const void *in, const int32_t *in_exp, void *out,
+                       int32_t *out_exp, void *stream);
+
+/* Free the plan and its device memory.  NULL is a no-op.  The caller must
+ * make sure no execute of this plan is still in flight. */
+void fft_plan_destroy(fft_plan p);
+
+/* Fill *d with what the plan launches.  FFT_ENULL for NULL arguments. */
+int fft_plan_describe(fft_plan p, fft_plan_desc *d);
+
+/* Host-only planning: what fft_plan_create(n, batch, sign, dtype) would
+ * launch, without touching any device.  Same argument checks and codes. */
+int fft_plan_query(int64_t n, int64_t batch, int sign, int dtype, fft_plan_desc *d);
+
+/* Device address of the plan's FP32 twiddle table tw[m] = exp(-2 pi i m/2048),
+ * m < 2048 (16 KiB), or NULL.  Read-only; owned by the plan. */
+const void *fft_plan_twiddles(fft_plan p);
+
+/* Last status / message of the calling host thread (FFT_OK / "" if none). */
+int fft_last_error(void);
+const char *fft_last_error_string(void);
+
+/* Library version string. */
+const char *fft_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MIFFT_H */

@@ -1,1 +1,13 @@
-"""mifft: batched 1D complex-to-complex FFTs of power-of-two length on MI355X (gfx950)."""
+"""mifft: batched 1D complex-to-complex FFTs of power-of-two length on MI355X (gfx950).
+
+The compute path is the C ABI of libmifft.so (include/mifft.h); this package
+only marshals arguments.  Importing the package does not load the library:
+the first plan does, and it raises if the library has not been built.
+"""
+
+
+def __getattr__(name):
+    if name in ("Plan", "RaggedPlan", "fft", "ifft", "FFTFn", "fft_differentiable", "query", "get_plan"):
+        from . import api
+        return getattr(api, name)
+    raise AttributeError(name)

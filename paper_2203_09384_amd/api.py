@@ -1,0 +1,255 @@
+"""Python binding of the mifft C ABI: plans, execute calls and the
+differentiable FFT.  Argument marshalling only -- every transform runs in
+the HIP kernels of libmifft.so; torch provides device memory and streams.
+"""
+from __future__ import annotations
+
+import ctypes
+import threading
+
+import torch
+
+from . import native
+from .native import FFT_C16, FFT_C32, FFT_CBF16, MifftError, check, check_plan, lib
+
+DTYPES = {"c32": FFT_C32, "c16": FFT_C16, "cbf16": FFT_CBF16}
+_HALF_TORCH = {FFT_C16: torch.float16, FFT_CBF16: torch.bfloat16}
+
+
+def _stream_handle(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def query(n: int, batch: int = 1, sign: int = -1, dtype: str = "c32") -> dict:
+    """Host-only planning (no device needed): what a plan would launch."""
+    d = native.PlanDesc()
+    check(lib().fft_plan_query(n, batch, sign, DTYPES[dtype], ctypes.byref(d)))
+    return d.as_dict()
+
+
+class Plan:
+    """fft_plan_create(n, batch, sign, dtype) and its execute calls.
+
+    sign -1 is the forward transform of the paper's Eq. (dft); +1 the
+    inverse of Eq. (idft) with its 1/n.  For dtype 'c32' tensors are
+    torch.complex64 of shape (..., n) with batch = numel / n; for 'c16' /
+    'cbf16' they are float16 / bfloat16 of shape (..., n, 2).
+    """
+
+    def __init__(self, n: int, batch: int, sign: int = -1, dtype: str = "c32",
+                 ept: int | None = None, wg: int | None = None):
+        L = lib()
+        self.n, self.batch, self.sign, self.dtype = int(n), int(batch), int(sign), DTYPES[dtype]
+        if ept is not None or wg is not None:
+            h = L.fft_plan_create_config(self.n, self.batch, self.sign, self.dtype,
+                                         int(ept or 0), int(wg or 0))
+        else:
+            h = L.fft_plan_create(self.n, self.batch, self.sign, self.dtype)
+        self._h = check_plan(h)
+
+    # -- marshalling -------------------------------------------------------
+    def _check_tensor(self, x, what):
+        if not x.is_cuda:
+            raise ValueError(f"{what} must be a GPU tensor")
+        if not x.is_contiguous():
+            raise ValueError(f"{what} must be contiguous")
+        if self.dtype == FFT_C32:
+            if x.dtype != torch.complex64:
+                raise ValueError(f"{what} must be complex64, got {x.dtype}")
+            if x.numel() != self.n * self.batch:
+                raise ValueError(f"{what} has {x.numel()} elements, plan needs {self.n}*{self.batch}")
+        else:
+            if x.dtype != _HALF_TORCH[self.dtype]:
+                raise ValueError(f"{what} must be {_HALF_TORCH[self.dtype]}, got {x.dtype}")
+            if x.numel() != 2 * self.n * self.batch:
+                raise ValueError(f"{what} has {x.numel()} values, plan needs 2*{self.n}*{self.batch}")
+
+    def execute(self, x, out=None, stream=None):
+        """out = plan(x); allocates `out` (torch caching allocator) if not given."""
+        self._check_tensor(x, "input")
+        if out is None:
+            out = torch.empty_like(x)
+        self._check_tensor(out, "output")
+        check(lib().fft_execute(self._h, _ptr(x), _ptr(out), _stream_handle(stream)))
+        return out
+
+    def adjoint(self, g, out=None, stream=None):
+        """out = plan^H(g): conjugate sign, same scale."""
+        self._check_tensor(g, "input")
+        if out is None:
+            out = torch.empty_like(g)
+        self._check_tensor(out, "output")
+        check(lib().fft_execute_adjoint(self._h, _ptr(g), _ptr(out), _stream_handle(stream)))
+        return out
+
+    def execute_scaled(self, x, in_exp=None, out=None, out_exp=None, stream=None):
+        """Block floating point (FP16/BF16 plans): value = stored * 2^exp[b]."""
+        self._check_tensor(x, "input")
+        if out is None:
+            out = torch.empty_like(x)
+        self._check_tensor(out, "output")
+        if out_exp is None:
+            out_exp = torch.empty(self.batch, dtype=torch.int32, device=x.device)
+        for e, nm in ((in_exp, "in_exp"), (out_exp, "out_exp")):
+            if e is not None and (e.dtype != torch.int32 or e.numel() != self.batch
+                                  or not e.is_cuda or not e.is_contiguous()):
+                raise ValueError(f"{nm} must be a contiguous int32 GPU tensor of {self.batch} values")
+        check(lib().fft_execute_scaled(self._h, _ptr(x),
+                                       _ptr(in_exp) if in_exp is not None else None,
+                                       _ptr(out), _ptr(out_exp), _stream_handle(stream)))
+        return out, out_exp
+
+    def describe(self) -> dict:
+        d = native.PlanDesc()
+        check(lib().fft_plan_describe(self._h, ctypes.byref(d)))
+        return d.as_dict()
+
+    def twiddles(self):
+        """A copy of the plan's FP32 twiddle table, exp(-2 pi i m / 2048) for
+        m < 2048, as a complex64 GPU tensor."""
+        p = lib().fft_plan_twiddles(self._h)
+        view = torch.as_tensor(_DeviceArray(p, (2048, 2), "<f4"), device="cuda")
+        return torch.view_as_complex(view.clone())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().fft_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class _DeviceArray:
+    """Exposes a raw device pointer through __cuda_array_interface__."""
+
+    def __init__(self, ptr: int, shape, typestr: str):
+        self.__cuda_array_interface__ = {"shape": tuple(shape), "typestr": typestr,
+                                         "data": (int(ptr), False), "version": 2, "strides": None}
+
+
+class RaggedPlan:
+    """fft_plan_create_ragged(count, offsets, sign, dtype): mixed lengths,
+    packed back to back, one persistent launch per execute."""
+
+    def __init__(self, offsets, sign: int = -1, dtype: str = "c32",
+                 ept_by_log2n=None, wg: int = 0, ctas_per_cu: int = 0):
+        import numpy as np
+        L = lib()
+        off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+        self.offsets = off
+        self.count = len(off) - 1
+        self.total = int(off[-1])
+        self.sign = int(sign)
+        self.dtype = DTYPES[dtype]
+        op = off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+        if ept_by_log2n is not None or wg or ctas_per_cu:
+            arr = None
+            if ept_by_log2n is not None:
+                arr = (ctypes.c_int * 12)(*[int(v) for v in ept_by_log2n])
+            h = L.fft_plan_create_ragged_config(self.count, op, self.sign, self.dtype, arr,
+                                                int(wg), int(ctas_per_cu))
+        else:
+            h = L.fft_plan_create_ragged(self.count, op, self.sign, self.dtype)
+        self._h = check_plan(h)
+
+    def _check_tensor(self, x, what):
+        if not x.is_cuda or not x.is_contiguous() or x.dtype != torch.complex64:
+            raise ValueError(f"{what} must be a contiguous complex64 GPU tensor")
+        if x.numel() != self.total:
+            raise ValueError(f"{what} has {x.numel()} elements, plan needs {self.total}")
+
+    def execute(self, x, out=None, stream=None):
+        self._check_tensor(x, "input")
+        if out is None:
+            out = torch.empty_like(x)
+        self._check_tensor(out, "output")
+        check(lib().fft_execute(self._h, _ptr(x), _ptr(out), _stream_handle(stream)))
+        return out
+
+    def adjoint(self, g, out=None, stream=None):
+        self._check_tensor(g, "input")
+        if out is None:
+            out = torch.empty_like(g)
+        self._check_tensor(out, "output")
+        check(lib().fft_execute_adjoint(self._h, _ptr(g), _ptr(out), _stream_handle(stream)))
+        return out
+
+    def describe(self) -> dict:
+        d = native.PlanDesc()
+        check(lib().fft_plan_describe(self._h, ctypes.byref(d)))
+        return d.as_dict()
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().fft_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ------------------------------------------------------------------ plan cache
+_cache: dict = {}
+_cache_lock = threading.Lock()
+
+
+def get_plan(n: int, batch: int, sign: int, dtype: str = "c32", device=None) -> Plan:
+    dev = torch.cuda.current_device() if device is None else device
+    key = (dev, n, batch, sign, dtype)
+    with _cache_lock:
+        p = _cache.get(key)
+        if p is None:
+            with torch.cuda.device(dev):
+                p = Plan(n, batch, sign, dtype)
+            _cache[key] = p
+        return p
+
+
+def fft(x, sign: int = -1):
+    """Transform over the last dimension of a complex64 GPU tensor (new tensor)."""
+    x = x.contiguous()
+    n = x.shape[-1]
+    return get_plan(n, x.numel() // n, sign, "c32", x.device.index).execute(x)
+
+
+def ifft(X):
+    return fft(X, sign=+1)
+
+
+class FFTFn(torch.autograd.Function):
+    """Differentiable batched FFT.  Forward: the plan's transform.  Backward:
+    its adjoint (conjugate sign, same scale) applied to the incoming
+    gradient, which for PyTorch's complex convention (grad = dL/dRe + i
+    dL/dIm) is exactly the gradient of any real loss.  No tensors are saved:
+    the map is linear."""
+
+    @staticmethod
+    def forward(ctx, x, sign: int = -1):
+        x = x.contiguous()
+        n = x.shape[-1]
+        plan = get_plan(n, x.numel() // n, sign, "c32", x.device.index)
+        ctx.plan = plan
+        return plan.execute(x)
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        g = grad_out.contiguous()
+        if g.dtype != torch.complex64:
+            g = g.to(torch.complex64)
+        return ctx.plan.adjoint(g), None
+
+
+def fft_differentiable(x, sign: int = -1):
+    return FFTFn.apply(x, sign)

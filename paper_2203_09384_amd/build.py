@@ -1,0 +1,65 @@
+"""Build libmifft.so (HIP, gfx950) in-tree with hipcc.
+
+Every kernel translation unit is compiled for gfx950 only; the FP32 Stockham
+file is compiled once per transform length (-DMIFFT_LOG2N=1..11).  Objects go
+to ``_build/`` beside this file, the library to ``libmifft.so`` beside it.
+"""
+from __future__ import annotations
+
+import concurrent.futures as cf
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+BUILD = os.path.join(HERE, "_build")
+LIB = os.path.join(HERE, "libmifft.so")
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+
+# Packed FP32 instructions are disabled for every device compile.
+DEVICE_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
+                "-Wno-unused-function", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+
+
+def _units():
+    units = []
+    for L in range(1, 12):
+        units.append(("fft_c32.hip", f"fft_c32_L{L}.o", [f"-DMIFFT_LOG2N={L}"]))
+    units.append(("twiddle.hip", "twiddle.o", []))
+    units.append(("ragged.hip", "ragged.o", []))
+    units.append(("half.hip", "half.o", []))
+    units.append(("api.cpp", "api.o", ["-x", "hip"]))
+    return units
+
+
+def _compile(src, obj, extra):
+    cmd = [HIPCC] + DEVICE_FLAGS + extra + ["-c", os.path.join(CSRC, src), "-o", os.path.join(BUILD, obj)]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed for {src} {extra}:\n{r.stderr}")
+    return r.stderr
+
+
+def build(jobs: int | None = None, verbose: bool = False) -> str:
+    os.makedirs(BUILD, exist_ok=True)
+    units = _units()
+    jobs = jobs or min(16, max(1, len(os.sched_getaffinity(0))))
+    with cf.ThreadPoolExecutor(jobs) as ex:
+        futs = [ex.submit(_compile, *u) for u in units]
+        for f in futs:
+            msg = f.result()
+            if verbose and msg.strip():
+                print(msg, file=sys.stderr)
+    objs = [os.path.join(BUILD, u[1]) for u in units]
+    tmp = LIB + ".tmp"
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link failed:\n{r.stderr}")
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build(verbose="-v" in sys.argv))

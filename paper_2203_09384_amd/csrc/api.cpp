@@ -1,0 +1,562 @@
+// C ABI of mifft: argument checks, planning, plan ownership and dispatch.
+// Kernels live in the *.hip translation units; this file only decides
+// which variant to launch and with what arguments.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <mutex>
+#include <new>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "../../include/mifft.h"
+#include "half.hpp"
+#include "ragged.hpp"
+#include "registry.hpp"
+
+namespace mifft {
+hipError_t launch_twiddle_2048(void* tw, hipStream_t stream);
+}
+
+using namespace mifft;
+
+// ------------------------------------------------------------------ errors
+namespace {
+thread_local int g_err = FFT_OK;
+thread_local char g_msg[512] = "";
+
+int set_err(int code, const char* fmt, ...)
+{
+    g_err = code;
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_msg, sizeof g_msg, fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+int ok()
+{
+    g_err = FFT_OK;
+    g_msg[0] = '\0';
+    return FFT_OK;
+}
+
+int hip_err(hipError_t e, const char* what)
+{
+    return set_err(FFT_EHIP, "%s: %s (%d)", what, hipGetErrorString(e), (int)e);
+}
+
+bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
+int ilog2(int64_t v)
+{
+    int l = 0;
+    while ((int64_t(1) << l) < v)
+        l++;
+    return l;
+}
+size_t elem_bytes(int dtype) { return dtype == FFT_C32 ? 8 : 4; }
+}  // namespace
+
+// ------------------------------------------------------------------ registry
+namespace mifft {
+static std::vector<KernelC32>& c32_reg()
+{
+    static std::vector<KernelC32> r;
+    return r;
+}
+void register_c32(const KernelC32& k) { c32_reg().push_back(k); }
+const KernelC32* find_c32(int log2n, int log2ept, int wg, int sign)
+{
+    for (const auto& k : c32_reg())
+        if (k.log2n == log2n && k.log2ept == log2ept && k.wg == wg && k.sign == sign)
+            return &k;
+    return nullptr;
+}
+int count_c32() { return (int)c32_reg().size(); }
+const KernelC32* c32_at(int i) { return (i >= 0 && i < count_c32()) ? &c32_reg()[i] : nullptr; }
+}  // namespace mifft
+
+// ------------------------------------------------------------------ tuning
+namespace {
+struct Variant {
+    int log2ept, wg;
+};
+
+// Built-in choice per log2 N (index 1..11) for FP32.
+const Variant kDefaultC32[12] = {
+    {0, 0},    // unused
+    {1, 256},  // N=2     one thread per transform
+    {2, 256},  // N=4
+    {3, 256},  // N=8
+    {4, 256},  // N=16
+    {3, 256},  // N=32    4 threads per transform
+    {3, 256},  // N=64
+    {3, 256},  // N=128
+    {4, 256},  // N=256
+    {4, 256},  // N=512
+    {4, 256},  // N=1024
+    {4, 256},  // N=2048  128 threads per transform, 2 per workgroup
+};
+
+std::once_flag g_tune_once;
+Variant g_tuned_c32[12];
+bool g_have_tuned_c32[12];
+
+// MIFFT_TUNE_TABLE: text lines "c32 <log2n> <ept> <wg>"; '#' starts a comment.
+void load_tune_table()
+{
+    const char* path = getenv("MIFFT_TUNE_TABLE");
+    if (!path || !*path)
+        return;
+    std::ifstream f(path);
+    std::string line;
+    while (std::getline(f, line)) {
+        const size_t h = line.find('#');
+        if (h != std::string::npos)
+            line.resize(h);
+        std::istringstream ss(line);
+        std::string dt;
+        int l = 0, ept = 0, wg = 0;
+        if (!(ss >> dt >> l >> ept >> wg))
+            continue;
+        if (dt == "c32" && l >= 1 && l <= 11 && is_pow2(ept) && ept >= 2 && ept <= 16) {
+            g_tuned_c32[l] = Variant{ilog2(ept), wg};
+            g_have_tuned_c32[l] = true;
+        }
+    }
+}
+
+Variant choose_c32(int log2n)
+{
+    std::call_once(g_tune_once, load_tune_table);
+    if (g_have_tuned_c32[log2n]) {
+        const Variant v = g_tuned_c32[log2n];
+        if (find_c32(log2n, v.log2ept, v.wg, -1))
+            return v;
+    }
+    return kDefaultC32[log2n];
+}
+
+// Stockham schedule of (log2 N, log2 EPT): a remainder pass first, then
+// passes of radix EPT.  Mirrors Sched<> in device_fft.hpp.
+int schedule(int log2n, int log2ept, int* radices)
+{
+    const int rem = log2n % log2ept;
+    int np = 0;
+    if (rem)
+        radices[np++] = 1 << rem;
+    for (int i = 0; i < log2n / log2ept; i++)
+        radices[np++] = 1 << log2ept;
+    return np;
+}
+}  // namespace
+
+// ------------------------------------------------------------------ plan
+struct mifft_plan_s {
+    int kind = 0;  // 0 batched, 1 ragged
+    int64_t n = 0, batch = 0;
+    int sign = -1, dtype = FFT_C32;
+    float scale = 1.f;
+    int device = -1;
+    int log2n = 0;
+    Variant var{};
+    const KernelC32* fwd = nullptr;  // sign -1 kernel
+    const KernelC32* bwd = nullptr;  // sign +1 kernel
+    void* tw = nullptr;              // device FP32 twiddle table (2048 entries)
+    int64_t total = 0;               // elements per execute (either kind)
+    RaggedPlan* ragged = nullptr;
+    HalfPlan* half = nullptr;
+};
+
+namespace {
+int check_common(int64_t n, int64_t batch, int sign, int dtype)
+{
+    if (dtype != FFT_C32 && dtype != FFT_C16 && dtype != FFT_CBF16)
+        return set_err(FFT_EINVAL_DTYPE, "dtype %d is not FFT_C32, FFT_C16 or FFT_CBF16", dtype);
+    if (!is_pow2(n) || n < 2 || n > 2048)
+        return set_err(FFT_EINVAL_N, "n=%lld is not a power of two in [2, 2048]", (long long)n);
+    if (batch < 1)
+        return set_err(FFT_EINVAL_BATCH, "batch=%lld must be >= 1", (long long)batch);
+    if (batch > (int64_t(1) << 40) / n)
+        return set_err(FFT_EINVAL_BATCH, "n*batch=%lld*%lld exceeds 2^40 elements", (long long)n,
+                       (long long)batch);
+    if (sign != -1 && sign != 1)
+        return set_err(FFT_EINVAL_SIGN, "sign=%d must be -1 (forward) or +1 (inverse)", sign);
+    return FFT_OK;
+}
+
+int fill_desc_c32(int64_t n, int64_t batch, int sign, int dtype, Variant v, fft_plan_desc* d)
+{
+    memset(d, 0, sizeof *d);
+    const int log2n = ilog2(n);
+    d->n = n;
+    d->batch = batch;
+    d->sign = sign;
+    d->dtype = dtype;
+    d->scale = sign > 0 ? 1.0f / (float)n : 1.0f;
+    d->ept = 1 << v.log2ept;
+    d->wg = v.wg;
+    const int tpt = (int)(n >> v.log2ept);
+    d->transforms_per_wg = v.wg / tpt;
+    d->grid = (batch + d->transforms_per_wg - 1) / d->transforms_per_wg;
+    d->npasses = schedule(log2n, v.log2ept, d->radices);
+    d->lds_bytes = tpt > 1 ? (int)(8 * d->transforms_per_wg * n) : 0;
+    d->kind = 0;
+    return FFT_OK;
+}
+
+int current_gfx950(int* dev)
+{
+    hipError_t e = hipGetDevice(dev);
+    if (e != hipSuccess)
+        return hip_err(e, "hipGetDevice");
+    hipDeviceProp_t prop;
+    e = hipGetDeviceProperties(&prop, *dev);
+    if (e != hipSuccess)
+        return hip_err(e, "hipGetDeviceProperties");
+    if (strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return set_err(FFT_EDEVICE, "device %d is %s; this library is built for gfx950", *dev,
+                       prop.gcnArchName);
+    return FFT_OK;
+}
+
+int make_twiddles(mifft_plan_s* p)
+{
+    hipError_t e = hipMalloc(&p->tw, 2048 * sizeof(float2));
+    if (e != hipSuccess) {
+        p->tw = nullptr;
+        return e == hipErrorOutOfMemory ? set_err(FFT_ENOMEM, "hipMalloc(twiddles) failed")
+                                        : hip_err(e, "hipMalloc(twiddles)");
+    }
+    e = launch_twiddle_2048(p->tw, nullptr);
+    if (e != hipSuccess)
+        return hip_err(e, "twiddle kernel launch");
+    e = hipStreamSynchronize(nullptr);
+    if (e != hipSuccess)
+        return hip_err(e, "twiddle kernel");
+    return FFT_OK;
+}
+
+void free_plan(mifft_plan_s* p)
+{
+    if (!p)
+        return;
+    if (p->ragged)
+        ragged_destroy(p->ragged);
+    if (p->half)
+        half_destroy(p->half);
+    if (p->tw)
+        (void)hipFree(p->tw);
+    delete p;
+}
+
+fft_plan create_batched(int64_t n, int64_t batch, int sign, int dtype, const Variant* force)
+{
+    if (check_common(n, batch, sign, dtype) != FFT_OK)
+        return nullptr;
+    const int log2n = ilog2(n);
+    Variant v{};
+    if (dtype == FFT_C32) {
+        if (force) {
+            v = *force;
+            if (!find_c32(log2n, v.log2ept, v.wg, -1) || !find_c32(log2n, v.log2ept, v.wg, +1)) {
+                set_err(FFT_EINVAL_CONFIG, "no FP32 kernel for n=%lld ept=%d wg=%d", (long long)n,
+                        1 << v.log2ept, v.wg);
+                return nullptr;
+            }
+        } else {
+            v = choose_c32(log2n);
+        }
+        const int tpb = v.wg / (int)(n >> v.log2ept);
+        if ((batch + tpb - 1) / tpb > 0x7fffffffLL) {
+            set_err(FFT_EINVAL_BATCH, "batch=%lld needs more than 2^31-1 workgroups", (long long)batch);
+            return nullptr;
+        }
+    } else if (!half_supported(n)) {
+        set_err(FFT_EINVAL_DTYPE, "FP16/BF16 plans support n in {%s}", half_supported_lengths());
+        return nullptr;
+    }
+    int dev = -1;
+    if (current_gfx950(&dev) != FFT_OK)
+        return nullptr;
+    auto* p = new (std::nothrow) mifft_plan_s();
+    if (!p) {
+        set_err(FFT_ENOMEM, "out of host memory");
+        return nullptr;
+    }
+    p->kind = 0;
+    p->n = n;
+    p->batch = batch;
+    p->sign = sign;
+    p->dtype = dtype;
+    p->scale = sign > 0 ? 1.0f / (float)n : 1.0f;
+    p->device = dev;
+    p->log2n = log2n;
+    p->var = v;
+    p->total = n * batch;
+    if (dtype == FFT_C32) {
+        p->fwd = find_c32(log2n, v.log2ept, v.wg, -1);
+        p->bwd = find_c32(log2n, v.log2ept, v.wg, +1);
+    }
+    if (make_twiddles(p) != FFT_OK) {
+        free_plan(p);
+        return nullptr;
+    }
+    if (dtype != FFT_C32) {
+        int rc = half_create(&p->half, n, batch, dtype);
+        if (rc != FFT_OK) {
+            set_err(rc, "%s", half_last_message());
+            free_plan(p);
+            return nullptr;
+        }
+    }
+    ok();
+    return p;
+}
+
+int check_exec(fft_plan p, const void* in, const void* out)
+{
+    if (!p)
+        return set_err(FFT_ENULL, "plan is NULL");
+    if (!in || !out)
+        return set_err(FFT_ENULL, "in/out pointer is NULL");
+    if ((reinterpret_cast<uintptr_t>(in) | reinterpret_cast<uintptr_t>(out)) & 15)
+        return set_err(FFT_EALIGN, "in/out must be 16-byte aligned");
+    const uintptr_t bytes = (uintptr_t)p->total * elem_bytes(p->dtype);
+    const uintptr_t a = reinterpret_cast<uintptr_t>(in), b = reinterpret_cast<uintptr_t>(out);
+    if (a < b + bytes && b < a + bytes)
+        return set_err(FFT_EOVERLAP, "in [%p, +%zu) and out [%p, +%zu) overlap (out of place only)", in,
+                       (size_t)bytes, out, (size_t)bytes);
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return hip_err(e, "hipGetDevice");
+    if (dev != p->device)
+        return set_err(FFT_EDEVICE, "plan was created on device %d, current device is %d", p->device, dev);
+    return FFT_OK;
+}
+
+// direction: the sign of the exponent actually applied; scale as given.
+int exec_c32(fft_plan p, const void* in, void* out, int sign, float scale, hipStream_t st)
+{
+    if (p->kind == 1) {
+        int rc = ragged_execute(p->ragged, in, out, p->tw, sign, p->sign > 0, st);
+        if (rc != FFT_OK)
+            return set_err(rc, "%s", ragged_last_message());
+        return ok();
+    }
+    const KernelC32* k = sign < 0 ? p->fwd : p->bwd;
+    hipError_t e = k->fn(in, out, p->tw, p->batch, scale, st);
+    if (e != hipSuccess)
+        return hip_err(e, "FFT kernel launch");
+    return ok();
+}
+}  // namespace
+
+// ------------------------------------------------------------------ C ABI
+extern "C" {
+
+fft_plan fft_plan_create(int64_t n, int64_t batch, int sign, int dtype)
+{
+    return create_batched(n, batch, sign, dtype, nullptr);
+}
+
+fft_plan fft_plan_create_config(int64_t n, int64_t batch, int sign, int dtype, int ept, int wg)
+{
+    if (check_common(n, batch, sign, dtype) != FFT_OK)
+        return nullptr;
+    if (dtype != FFT_C32) {
+        set_err(FFT_EINVAL_DTYPE, "fft_plan_create_config selects FP32 variants only");
+        return nullptr;
+    }
+    if (!is_pow2(ept) || ept < 2 || ept > 16 || !is_pow2(wg) || wg < 64 || wg > 512) {
+        set_err(FFT_EINVAL_CONFIG, "ept=%d must be 2..16 and wg=%d 64..512, powers of two", ept, wg);
+        return nullptr;
+    }
+    Variant v{ilog2(ept), wg};
+    return create_batched(n, batch, sign, dtype, &v);
+}
+
+fft_plan fft_plan_create_ragged_config(int64_t count, const int64_t* offsets, int sign, int dtype,
+                                       const int* ept_by_log2n, int wg, int ctas_per_cu)
+{
+    if (dtype != FFT_C32 && dtype != FFT_C16 && dtype != FFT_CBF16) {
+        set_err(FFT_EINVAL_DTYPE, "dtype %d is not FFT_C32, FFT_C16 or FFT_CBF16", dtype);
+        return nullptr;
+    }
+    if (dtype != FFT_C32) {
+        set_err(FFT_EINVAL_DTYPE, "ragged plans are FFT_C32 only");
+        return nullptr;
+    }
+    if (sign != -1 && sign != 1) {
+        set_err(FFT_EINVAL_SIGN, "sign=%d must be -1 (forward) or +1 (inverse)", sign);
+        return nullptr;
+    }
+    if (!offsets) {
+        set_err(FFT_ENULL, "offsets is NULL");
+        return nullptr;
+    }
+    if (count < 1) {
+        set_err(FFT_EINVAL_BATCH, "count=%lld must be >= 1", (long long)count);
+        return nullptr;
+    }
+    if (offsets[0] != 0) {
+        set_err(FFT_EINVAL_OFFSETS, "offsets[0]=%lld must be 0", (long long)offsets[0]);
+        return nullptr;
+    }
+    for (int64_t b = 0; b < count; b++) {
+        const int64_t len = offsets[b + 1] - offsets[b];
+        if (!is_pow2(len) || len < 2 || len > 2048) {
+            set_err(FFT_EINVAL_OFFSETS, "transform %lld has length %lld; lengths must be powers of two in [2, 2048]",
+                    (long long)b, (long long)len);
+            return nullptr;
+        }
+    }
+    if (offsets[count] > (int64_t(1) << 40)) {
+        set_err(FFT_EINVAL_OFFSETS, "total length %lld exceeds 2^40 elements", (long long)offsets[count]);
+        return nullptr;
+    }
+    int rc = ragged_check_config(ept_by_log2n, wg, ctas_per_cu);
+    if (rc != FFT_OK) {
+        set_err(rc, "%s", ragged_last_message());
+        return nullptr;
+    }
+    int dev = -1;
+    if (current_gfx950(&dev) != FFT_OK)
+        return nullptr;
+    auto* p = new (std::nothrow) mifft_plan_s();
+    if (!p) {
+        set_err(FFT_ENOMEM, "out of host memory");
+        return nullptr;
+    }
+    p->kind = 1;
+    p->n = 0;
+    p->batch = count;
+    p->sign = sign;
+    p->dtype = dtype;
+    p->scale = 1.0f;
+    p->device = dev;
+    p->total = offsets[count];
+    if (make_twiddles(p) != FFT_OK) {
+        free_plan(p);
+        return nullptr;
+    }
+    rc = ragged_create(&p->ragged, count, offsets, ept_by_log2n, wg, ctas_per_cu, dev);
+    if (rc != FFT_OK) {
+        set_err(rc, "%s", ragged_last_message());
+        free_plan(p);
+        return nullptr;
+    }
+    ok();
+    return p;
+}
+
+fft_plan fft_plan_create_ragged(int64_t count, const int64_t* offsets, int sign, int dtype)
+{
+    return fft_plan_create_ragged_config(count, offsets, sign, dtype, nullptr, 0, 0);
+}
+
+int fft_execute(fft_plan p, const void* in, void* out, void* stream)
+{
+    int rc = check_exec(p, in, out);
+    if (rc != FFT_OK)
+        return rc;
+    if (p->dtype != FFT_C32)
+        return fft_execute_scaled(p, in, nullptr, out, nullptr, stream);
+    return exec_c32(p, in, out, p->sign, p->scale, static_cast<hipStream_t>(stream));
+}
+
+int fft_execute_adjoint(fft_plan p, const void* in, void* out, void* stream)
+{
+    int rc = check_exec(p, in, out);
+    if (rc != FFT_OK)
+        return rc;
+    if (p->dtype != FFT_C32)
+        return set_err(FFT_EINVAL_DTYPE, "the adjoint is provided for FFT_C32 plans");
+    return exec_c32(p, in, out, -p->sign, p->scale, static_cast<hipStream_t>(stream));
+}
+
+int fft_execute_scaled(fft_plan p, const void* in, const int32_t* in_exp, void* out, int32_t* out_exp,
+                       void* stream)
+{
+    int rc = check_exec(p, in, out);
+    if (rc != FFT_OK)
+        return rc;
+    if (p->dtype == FFT_C32 || !p->half)
+        return set_err(FFT_EINVAL_DTYPE, "fft_execute_scaled needs an FFT_C16 or FFT_CBF16 plan");
+    if ((reinterpret_cast<uintptr_t>(in_exp) | reinterpret_cast<uintptr_t>(out_exp)) & 3)
+        return set_err(FFT_EALIGN, "exponent arrays must be 4-byte aligned");
+    rc = half_execute(p->half, in, in_exp, out, out_exp, p->tw, p->sign, static_cast<hipStream_t>(stream));
+    if (rc != FFT_OK)
+        return set_err(rc, "%s", half_last_message());
+    return ok();
+}
+
+void fft_plan_destroy(fft_plan p) { free_plan(p); }
+
+int fft_plan_describe(fft_plan p, fft_plan_desc* d)
+{
+    if (!p || !d)
+        return set_err(FFT_ENULL, "plan or desc is NULL");
+    if (p->kind == 1) {
+        memset(d, 0, sizeof *d);
+        d->n = 0;
+        d->batch = p->batch;
+        d->sign = p->sign;
+        d->dtype = p->dtype;
+        d->scale = 1.0f;
+        d->kind = 1;
+        ragged_describe(p->ragged, &d->wg, &d->grid, &d->tiles, &d->lds_bytes);
+        return ok();
+    }
+    if (p->dtype == FFT_C32) {
+        fill_desc_c32(p->n, p->batch, p->sign, p->dtype, p->var, d);
+    } else {
+        memset(d, 0, sizeof *d);
+        d->n = p->n;
+        d->batch = p->batch;
+        d->sign = p->sign;
+        d->dtype = p->dtype;
+        d->scale = p->scale;
+        half_describe(p->half, d);
+    }
+    return ok();
+}
+
+int fft_plan_query(int64_t n, int64_t batch, int sign, int dtype, fft_plan_desc* d)
+{
+    if (!d)
+        return set_err(FFT_ENULL, "desc is NULL");
+    int rc = check_common(n, batch, sign, dtype);
+    if (rc != FFT_OK)
+        return rc;
+    if (dtype != FFT_C32) {
+        if (!half_supported(n))
+            return set_err(FFT_EINVAL_DTYPE, "FP16/BF16 plans support n in {%s}", half_supported_lengths());
+        memset(d, 0, sizeof *d);
+        d->n = n;
+        d->batch = batch;
+        d->sign = sign;
+        d->dtype = dtype;
+        d->scale = sign > 0 ? 1.0f / (float)n : 1.0f;
+        half_query(n, batch, d);
+        return ok();
+    }
+    fill_desc_c32(n, batch, sign, dtype, choose_c32(ilog2(n)), d);
+    return ok();
+}
+
+const void* fft_plan_twiddles(fft_plan p) { return p ? p->tw : nullptr; }
+
+int fft_last_error(void) { return g_err; }
+const char* fft_last_error_string(void) { return g_msg; }
+const char* fft_version(void) { return "mifft 0.1 (gfx950)"; }
+
+}  // extern "C"

@@ -1,0 +1,58 @@
+// Twiddle table: tw[m] = exp(-2 pi i m / 2048), m < 2048, stored as FP32.
+//
+// The paper's twiddles w_N^k (Eq. (dft)) come from the device's own sin/cos
+// (section "Portability and Precision").  Here they are generated once per
+// plan on the GPU in FP64 with sincospi, rounded once to FP32; this is the
+// only FP64 arithmetic in the library.  Every w_N^k with N <= 2048 is
+// tw[k * 2048 / N].
+//
+// Symmetry is enforced so that the table is exact where the circle is:
+// angles are folded into the first octant [0, pi/4], evaluated there, and
+// unfolded with the swaps/negations of the quarter-period identities of
+// Eq. (twiddle).  Hence w^{m + 512} = -i w^m holds bit for bit and the
+// points at multiples of 1/8 turn are exact (to FP32 rounding of 1/sqrt 2).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mifft {
+
+__global__ void k_twiddle_2048(float2* __restrict__ tw)
+{
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= 2048)
+        return;
+    const int quad = m >> 9;     // quarter turn index (512 entries per quarter)
+    const int j = m & 511;       // position inside the quarter
+    // angle inside the quarter folded to [0, 1/8 turn]
+    double c, s;
+    if (j <= 256) {
+        sincospi((double)j / 1024.0, &s, &c);
+    } else {
+        double c2, s2;
+        sincospi((double)(512 - j) / 1024.0, &s2, &c2);
+        c = s2;
+        s = c2;
+    }
+    // rotate by quad quarter turns: (c, s) -> (-s, c)
+    double cr = c, sr = s;
+    if (quad == 1) {
+        cr = -s;
+        sr = c;
+    } else if (quad == 2) {
+        cr = -c;
+        sr = -s;
+    } else if (quad == 3) {
+        cr = s;
+        sr = -c;
+    }
+    // exp(-i theta) = cos theta - i sin theta
+    tw[m] = float2{(float)cr, (float)(-sr)};
+}
+
+hipError_t launch_twiddle_2048(void* tw, hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_twiddle_2048, dim3(8), dim3(256), 0, stream, static_cast<float2*>(tw));
+    return hipGetLastError();
+}
+
+}  // namespace mifft

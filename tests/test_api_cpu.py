@@ -1,0 +1,99 @@
+"""C ABI checks that need no GPU: exports, argument validation before any HIP
+call, and host-side planning."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2203_09384_amd import native
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mifft.h")
+
+
+def header_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(fft_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = native.lib()
+    declared = header_functions()
+    assert len(declared) >= 14
+    for name in declared:
+        assert hasattr(L, name), name
+    assert set(declared) == set(native.EXPORTS)
+    assert L.fft_version().decode().startswith("mifft")
+
+
+def q(n, batch=1, sign=-1, dtype=0):
+    d = native.PlanDesc()
+    rc = native.lib().fft_plan_query(n, batch, sign, dtype, ctypes.byref(d))
+    return rc, d
+
+
+@pytest.mark.parametrize("n", [0, 1, 3, 12, 4096, -8, 2049])
+def test_bad_n(n):
+    assert q(n)[0] == 1
+
+
+def test_bad_batch_sign_dtype_null():
+    assert q(256, 0)[0] == 2
+    assert q(256, -5)[0] == 2
+    assert q(2048, 1 << 40)[0] == 2
+    assert q(256, 1, 0)[0] == 3
+    assert q(256, 1, 2)[0] == 3
+    assert q(256, 1, -1, 7)[0] == 4
+    L = native.lib()
+    assert L.fft_plan_query(256, 1, -1, 0, None) == 5
+    assert L.fft_execute(None, None, None, None) == 5
+    assert L.fft_last_error() == 5
+    assert b"NULL" in L.fft_last_error_string()
+    assert L.fft_plan_describe(None, None) == 5
+    L.fft_plan_destroy(None)  # NULL-safe
+
+
+@pytest.mark.parametrize("L", range(1, 12))
+def test_query_plans_are_consistent(L):
+    n = 1 << L
+    for sign in (-1, 1):
+        rc, d = q(n, 1000, sign)
+        assert rc == 0
+        assert int(np.prod(list(d.radices)[: d.npasses])) == n
+        assert d.ept * (d.wg // d.transforms_per_wg) == n
+        assert d.grid == -(-1000 // d.transforms_per_wg)
+        assert d.scale == (1.0 if sign < 0 else np.float32(1.0 / n))
+        assert all(r in (2, 4, 8, 16) for r in list(d.radices)[: d.npasses])
+
+
+def test_validation_happens_before_hip():
+    """Bad arguments report their own status even where no device exists."""
+    L = native.lib()
+    assert L.fft_plan_create(12, 1, -1, 0) is None and L.fft_last_error() == 1
+    assert L.fft_plan_create(256, 0, -1, 0) is None and L.fft_last_error() == 2
+    assert L.fft_plan_create(256, 1, 3, 0) is None and L.fft_last_error() == 3
+    assert L.fft_plan_create(256, 1, -1, 9) is None and L.fft_last_error() == 4
+    assert L.fft_plan_create_config(256, 1, -1, 0, 3, 256) is None and L.fft_last_error() == 10
+    bad = [np.array([0, 8, 20], np.int64), np.array([1, 9], np.int64),
+           np.array([0, 4096], np.int64), np.array([0, 8, 8], np.int64)]
+    for off in bad:
+        p = off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+        assert L.fft_plan_create_ragged(len(off) - 1, p, -1, 0) is None
+        assert L.fft_last_error() == 7, off
+    off = np.array([0, 8, 16], np.int64)
+    p = off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+    assert L.fft_plan_create_ragged(2, None, -1, 0) is None and L.fft_last_error() == 5
+    assert L.fft_plan_create_ragged(0, p, -1, 0) is None and L.fft_last_error() == 2
+    assert L.fft_plan_create_ragged(2, p, 0, 0) is None and L.fft_last_error() == 3
+
+
+@pytest.mark.skipif(torch.cuda.is_available(), reason="checks the no-device path")
+def test_no_device_is_reported_as_hip_error():
+    L = native.lib()
+    assert L.fft_plan_create(256, 4, -1, 0) is None
+    assert L.fft_last_error() == 8
+    assert b"hipGetDevice" in L.fft_last_error_string()
