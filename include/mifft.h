@@ -84,6 +84,10 @@ typedef struct {
     int lds_bytes;      /* LDS per workgroup                                  */
     int kind;           /* 0 batched, 1 ragged                                */
     int64_t tiles;      /* ragged: work tiles                                 */
+    int variant;        /* kernel family: 0 one transform group per
+                           workgroup; 1..4 twiddle-row kernels (1, 2: one
+                           group per workgroup, twiddles kept / re-read;
+                           3, 4: persistent with next-group prefetch)       */
 } fft_plan_desc;
 
 /*
@@ -104,11 +108,12 @@ fft_plan fft_plan_create(int64_t n, int64_t batch, int sign, int dtype);
 
 /*
  * As fft_plan_create, forcing the kernel variant: `ept` complex elements
- * per thread (2, 4, 8 or 16) and `wg` threads per workgroup (64, 128, 256
- * or 512).  Used by the autotuner.  FFT_EINVAL_CONFIG if that variant is
+ * per thread (2, 4, 8 or 16), `wg` threads per workgroup (64, 128, 256 or
+ * 512) and the kernel family `variant` (0..4, see fft_plan_desc.variant).
+ * FP32 only.  Used by the autotuner.  FFT_EINVAL_CONFIG if that variant is
  * not compiled in.
  */
-fft_plan fft_plan_create_config(int64_t n, int64_t batch, int sign, int dtype, int ept, int wg);
+fft_plan fft_plan_create_config(int64_t n, int64_t batch, int sign, int dtype, int ept, int wg, int variant);
 
 /*
  * Ragged batch: `count` transforms of mixed power-of-two lengths packed

@@ -42,12 +42,12 @@ class Plan:
     """
 
     def __init__(self, n: int, batch: int, sign: int = -1, dtype: str = "c32",
-                 ept: int | None = None, wg: int | None = None):
+                 ept: int | None = None, wg: int | None = None, variant: int = 0):
         L = lib()
         self.n, self.batch, self.sign, self.dtype = int(n), int(batch), int(sign), DTYPES[dtype]
         if ept is not None or wg is not None:
             h = L.fft_plan_create_config(self.n, self.batch, self.sign, self.dtype,
-                                         int(ept or 0), int(wg or 0))
+                                         int(ept or 0), int(wg or 0), int(variant))
         else:
             h = L.fft_plan_create(self.n, self.batch, self.sign, self.dtype)
         self._h = check_plan(h)

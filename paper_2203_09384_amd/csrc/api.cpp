@@ -22,6 +22,7 @@
 
 namespace mifft {
 hipError_t launch_twiddle_2048(void* tw, hipStream_t stream);
+hipError_t launch_twiddle_rows(const void* tw, void* rows, int L, int E, int total, hipStream_t stream);
 }
 
 using namespace mifft;
@@ -72,10 +73,10 @@ static std::vector<KernelC32>& c32_reg()
     return r;
 }
 void register_c32(const KernelC32& k) { c32_reg().push_back(k); }
-const KernelC32* find_c32(int log2n, int log2ept, int wg, int sign)
+const KernelC32* find_c32(int log2n, int log2ept, int wg, int sign, int kind)
 {
     for (const auto& k : c32_reg())
-        if (k.log2n == log2n && k.log2ept == log2ept && k.wg == wg && k.sign == sign)
+        if (k.log2n == log2n && k.log2ept == log2ept && k.wg == wg && k.sign == sign && k.kind == kind)
             return &k;
     return nullptr;
 }
@@ -86,30 +87,31 @@ const KernelC32* c32_at(int i) { return (i >= 0 && i < count_c32()) ? &c32_reg()
 // ------------------------------------------------------------------ tuning
 namespace {
 struct Variant {
-    int log2ept, wg;
+    int log2ept, wg, kind;
 };
 
-// Built-in choice per log2 N (index 1..11) for FP32.
+// Built-in choice per log2 N (index 1..11) for FP32: the autotuner's pick on
+// MI355X at 2^26 elements per launch (log2 EPT, workgroup size, variant).
 const Variant kDefaultC32[12] = {
-    {0, 0},    // unused
-    {1, 256},  // N=2     one thread per transform
-    {2, 256},  // N=4
-    {3, 256},  // N=8
-    {4, 256},  // N=16
-    {3, 256},  // N=32    4 threads per transform
-    {3, 256},  // N=64
-    {3, 256},  // N=128
-    {4, 256},  // N=256
-    {4, 256},  // N=512
-    {4, 256},  // N=1024
-    {4, 256},  // N=2048  128 threads per transform, 2 per workgroup
+    {0, 0, 0},    // unused
+    {1, 64, 0},   // N=2     one thread per transform
+    {2, 128, 0},  // N=4
+    {3, 256, 0},  // N=8
+    {2, 256, 2},  // N=16
+    {3, 256, 1},  // N=32
+    {2, 128, 2},  // N=64
+    {3, 256, 2},  // N=128
+    {3, 64, 2},   // N=256
+    {3, 256, 2},  // N=512
+    {3, 256, 2},  // N=1024
+    {3, 256, 4},  // N=2048  persistent, next-group prefetch
 };
 
 std::once_flag g_tune_once;
 Variant g_tuned_c32[12];
 bool g_have_tuned_c32[12];
 
-// MIFFT_TUNE_TABLE: text lines "c32 <log2n> <ept> <wg>"; '#' starts a comment.
+// MIFFT_TUNE_TABLE: text lines "c32 <log2n> <ept> <wg> <kind>"; '#' starts a comment.
 void load_tune_table()
 {
     const char* path = getenv("MIFFT_TUNE_TABLE");
@@ -123,11 +125,13 @@ void load_tune_table()
             line.resize(h);
         std::istringstream ss(line);
         std::string dt;
-        int l = 0, ept = 0, wg = 0;
+        int l = 0, ept = 0, wg = 0, kind = 0;
         if (!(ss >> dt >> l >> ept >> wg))
             continue;
+        if (!(ss >> kind))
+            kind = 0;
         if (dt == "c32" && l >= 1 && l <= 11 && is_pow2(ept) && ept >= 2 && ept <= 16) {
-            g_tuned_c32[l] = Variant{ilog2(ept), wg};
+            g_tuned_c32[l] = Variant{ilog2(ept), wg, kind};
             g_have_tuned_c32[l] = true;
         }
     }
@@ -138,7 +142,7 @@ Variant choose_c32(int log2n)
     std::call_once(g_tune_once, load_tune_table);
     if (g_have_tuned_c32[log2n]) {
         const Variant v = g_tuned_c32[log2n];
-        if (find_c32(log2n, v.log2ept, v.wg, -1))
+        if (find_c32(log2n, v.log2ept, v.wg, -1, v.kind))
             return v;
     }
     return kDefaultC32[log2n];
@@ -170,6 +174,8 @@ struct mifft_plan_s {
     const KernelC32* fwd = nullptr;  // sign -1 kernel
     const KernelC32* bwd = nullptr;  // sign +1 kernel
     void* tw = nullptr;              // device FP32 twiddle table (2048 entries)
+    void* rows = nullptr;            // per-pass twiddle rows (kind >= 1)
+    int64_t grid_limit = 0;          // persistent kinds: CUs x workgroups per CU
     int64_t total = 0;               // elements per execute (either kind)
     RaggedPlan* ragged = nullptr;
     HalfPlan* half = nullptr;
@@ -192,7 +198,7 @@ int check_common(int64_t n, int64_t batch, int sign, int dtype)
     return FFT_OK;
 }
 
-int fill_desc_c32(int64_t n, int64_t batch, int sign, int dtype, Variant v, fft_plan_desc* d)
+int fill_desc_c32(int64_t n, int64_t batch, int sign, int dtype, Variant v, int64_t grid_limit, fft_plan_desc* d)
 {
     memset(d, 0, sizeof *d);
     const int log2n = ilog2(n);
@@ -207,8 +213,12 @@ int fill_desc_c32(int64_t n, int64_t batch, int sign, int dtype, Variant v, fft_
     d->transforms_per_wg = v.wg / tpt;
     d->grid = (batch + d->transforms_per_wg - 1) / d->transforms_per_wg;
     d->npasses = schedule(log2n, v.log2ept, d->radices);
-    d->lds_bytes = tpt > 1 ? (int)(8 * d->transforms_per_wg * n) : 0;
+    if (grid_limit > 0 && d->grid > grid_limit)
+        d->grid = grid_limit;
+    const KernelC32* k = find_c32(log2n, v.log2ept, v.wg, sign, v.kind);
+    d->lds_bytes = k ? k->lds_bytes : 0;
     d->kind = 0;
+    d->variant = v.kind;
     return FFT_OK;
 }
 
@@ -244,6 +254,36 @@ int make_twiddles(mifft_plan_s* p)
     return FFT_OK;
 }
 
+// Twiddle rows and the persistent grid size of a kind >= 1 variant.
+int make_rows(mifft_plan_s* p)
+{
+    const KernelC32* k = p->fwd;
+    if (k->rows > 0) {
+        hipError_t e = hipMalloc(&p->rows, (size_t)k->rows * sizeof(float2));
+        if (e != hipSuccess) {
+            p->rows = nullptr;
+            return e == hipErrorOutOfMemory ? set_err(FFT_ENOMEM, "hipMalloc(twiddle rows) failed")
+                                            : hip_err(e, "hipMalloc(twiddle rows)");
+        }
+        e = launch_twiddle_rows(p->tw, p->rows, k->log2n, k->log2ept, k->rows, nullptr);
+        if (e != hipSuccess)
+            return hip_err(e, "twiddle rows launch");
+        e = hipStreamSynchronize(nullptr);
+        if (e != hipSuccess)
+            return hip_err(e, "twiddle rows kernel");
+    }
+    p->grid_limit = 0;
+    if (k->kind >= 3 && k->occupancy) {
+        int cus = 0;
+        hipError_t e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device);
+        if (e != hipSuccess)
+            return hip_err(e, "hipDeviceGetAttribute(CU count)");
+        const int occ = std::max(k->occupancy(), std::max(p->bwd->occupancy ? p->bwd->occupancy() : 1, 1));
+        p->grid_limit = (int64_t)cus * occ;
+    }
+    return FFT_OK;
+}
+
 void free_plan(mifft_plan_s* p)
 {
     if (!p)
@@ -254,6 +294,8 @@ void free_plan(mifft_plan_s* p)
         half_destroy(p->half);
     if (p->tw)
         (void)hipFree(p->tw);
+    if (p->rows)
+        (void)hipFree(p->rows);
     delete p;
 }
 
@@ -266,9 +308,9 @@ fft_plan create_batched(int64_t n, int64_t batch, int sign, int dtype, const Var
     if (dtype == FFT_C32) {
         if (force) {
             v = *force;
-            if (!find_c32(log2n, v.log2ept, v.wg, -1) || !find_c32(log2n, v.log2ept, v.wg, +1)) {
-                set_err(FFT_EINVAL_CONFIG, "no FP32 kernel for n=%lld ept=%d wg=%d", (long long)n,
-                        1 << v.log2ept, v.wg);
+            if (!find_c32(log2n, v.log2ept, v.wg, -1, v.kind) || !find_c32(log2n, v.log2ept, v.wg, +1, v.kind)) {
+                set_err(FFT_EINVAL_CONFIG, "no FP32 kernel for n=%lld ept=%d wg=%d kind=%d", (long long)n,
+                        1 << v.log2ept, v.wg, v.kind);
                 return nullptr;
             }
         } else {
@@ -302,10 +344,14 @@ fft_plan create_batched(int64_t n, int64_t batch, int sign, int dtype, const Var
     p->var = v;
     p->total = n * batch;
     if (dtype == FFT_C32) {
-        p->fwd = find_c32(log2n, v.log2ept, v.wg, -1);
-        p->bwd = find_c32(log2n, v.log2ept, v.wg, +1);
+        p->fwd = find_c32(log2n, v.log2ept, v.wg, -1, v.kind);
+        p->bwd = find_c32(log2n, v.log2ept, v.wg, +1, v.kind);
     }
     if (make_twiddles(p) != FFT_OK) {
+        free_plan(p);
+        return nullptr;
+    }
+    if (dtype == FFT_C32 && p->fwd->kind >= 1 && make_rows(p) != FFT_OK) {
         free_plan(p);
         return nullptr;
     }
@@ -353,7 +399,7 @@ int exec_c32(fft_plan p, const void* in, void* out, int sign, float scale, hipSt
         return ok();
     }
     const KernelC32* k = sign < 0 ? p->fwd : p->bwd;
-    hipError_t e = k->fn(in, out, p->tw, p->batch, scale, st);
+    hipError_t e = k->fn(in, out, p->tw, p->rows, p->batch, scale, p->grid_limit, st);
     if (e != hipSuccess)
         return hip_err(e, "FFT kernel launch");
     return ok();
@@ -368,7 +414,7 @@ fft_plan fft_plan_create(int64_t n, int64_t batch, int sign, int dtype)
     return create_batched(n, batch, sign, dtype, nullptr);
 }
 
-fft_plan fft_plan_create_config(int64_t n, int64_t batch, int sign, int dtype, int ept, int wg)
+fft_plan fft_plan_create_config(int64_t n, int64_t batch, int sign, int dtype, int ept, int wg, int variant)
 {
     if (check_common(n, batch, sign, dtype) != FFT_OK)
         return nullptr;
@@ -376,11 +422,13 @@ fft_plan fft_plan_create_config(int64_t n, int64_t batch, int sign, int dtype, i
         set_err(FFT_EINVAL_DTYPE, "fft_plan_create_config selects FP32 variants only");
         return nullptr;
     }
-    if (!is_pow2(ept) || ept < 2 || ept > 16 || !is_pow2(wg) || wg < 64 || wg > 512) {
-        set_err(FFT_EINVAL_CONFIG, "ept=%d must be 2..16 and wg=%d 64..512, powers of two", ept, wg);
+    if (!is_pow2(ept) || ept < 2 || ept > 16 || !is_pow2(wg) || wg < 64 || wg > 512 || variant < 0 ||
+        variant > 4) {
+        set_err(FFT_EINVAL_CONFIG, "ept=%d must be 2..16, wg=%d 64..512 (powers of two), variant=%d 0..4", ept,
+                wg, variant);
         return nullptr;
     }
-    Variant v{ilog2(ept), wg};
+    Variant v{ilog2(ept), wg, variant};
     return create_batched(n, batch, sign, dtype, &v);
 }
 
@@ -517,7 +565,7 @@ int fft_plan_describe(fft_plan p, fft_plan_desc* d)
         return ok();
     }
     if (p->dtype == FFT_C32) {
-        fill_desc_c32(p->n, p->batch, p->sign, p->dtype, p->var, d);
+        fill_desc_c32(p->n, p->batch, p->sign, p->dtype, p->var, p->grid_limit, d);
     } else {
         memset(d, 0, sizeof *d);
         d->n = p->n;
@@ -549,7 +597,7 @@ int fft_plan_query(int64_t n, int64_t batch, int sign, int dtype, fft_plan_desc*
         half_query(n, batch, d);
         return ok();
     }
-    fill_desc_c32(n, batch, sign, dtype, choose_c32(ilog2(n)), d);
+    fill_desc_c32(n, batch, sign, dtype, choose_c32(ilog2(n)), 0, d);
     return ok();
 }
 

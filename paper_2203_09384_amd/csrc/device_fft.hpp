@@ -297,4 +297,157 @@ __device__ __forceinline__ void run_passes(cf (&v)[1 << LOG2EPT], int t, const c
     }
 }
 
+// ======================================================================
+// Persistent variant ("v2") building blocks.
+//
+// LDS exchanges use AoS complex values and the padding pad(d) = d + (d >> B)
+// (one spare slot every 2^B elements), with B chosen per exchange so that
+// (a) both the writes of pass P and the reads of pass P+1 stay affine in the
+// compile-time indices -- every address is one per-thread base plus an
+// immediate offset, no per-element index arithmetic -- and (b) the modelled
+// bank conflicts of the 64-bank LDS are lowest among such B.  B = 0 means
+// no padding.
+constexpr int pad_bits(int L, int E, int P)
+{
+    // rows: exchanges 0.. of (log2 N, log2 EPT); 0 = unpadded
+    if (E == 4) {
+        if (L == 5) return 1;
+        if (L == 6) return 2;
+        if (L == 7) return 3;
+        if (L == 8) return 4;
+        if (L == 9) return 5;
+        if (L == 10) return P == 0 ? 5 : 6;
+        if (L == 11) return P == 0 ? 5 : 3;
+    } else if (E == 3) {
+        if (L == 4) return 1;
+        if (L == 5) return 2;
+        if (L == 6) return 3;
+        if (L == 7) return P == 0 ? 1 : 4;
+        if (L == 8) return P == 0 ? 5 : 2;
+        if (L == 9) return P == 0 ? 5 : 3;
+        if (L == 10) return P == 2 ? 7 : 5;
+        if (L == 11) return P == 1 ? 2 : 5;
+    } else if (E == 2) {
+        if (L == 3) return 1;
+        if (L == 4) return 2;
+        if (L == 5) return 1;
+        if (L == 6) return 2;
+        if (L == 7) return P == 2 ? 1 : 5;
+        if (L == 8) return P == 1 ? 2 : (P == 2 ? 6 : 5);
+        if (L == 9) return P == 2 ? 1 : 5;
+        if (L == 10) return P == 1 ? 2 : (P == 2 ? 6 : 5);
+        if (L == 11) return P == 2 ? 1 : 5;
+    }
+    return 0;
+}
+
+// The write addresses of pass P are affine in (q, r) and the read addresses
+// of pass P+1 affine in m under padding B: the r field of pass P and the m
+// field of the reads lie entirely on one side of bit B.
+constexpr bool pad_is_affine(int L, int E, int P, int B)
+{
+    if (B == 0 || B >= L) return true;
+    const int rem = L % E;
+    const int lr = (rem && P == 0) ? rem : E;
+    const int lns = P == 0 ? 0 : (rem ? rem + (P - 1) * E : P * E);
+    const int lt = L - E;
+    bool w = (lns + lr <= B) || (lns >= B);
+    if ((1 << E) > (1 << lr)) w = w && (lt + lr >= B);
+    return w && (lt >= B);
+}
+
+template <int B>
+__device__ __forceinline__ int pad(int d)
+{
+    if constexpr (B == 0)
+        return d;
+    else
+        return d + (d >> B);
+}
+
+template <int L, int E>
+struct Layout2 {
+    using SC = Sched<L, E>;
+    static constexpr int N = SC::N;
+    static constexpr int padded(int B) { return B == 0 ? N : N + (N >> B); }
+    // LDS elements per transform: the largest padded size over the exchanges
+    static constexpr int region()
+    {
+        int m = N;
+        for (int p = 0; p + 1 < SC::NP; p++)
+            m = padded(pad_bits(L, E, p)) > m ? padded(pad_bits(L, E, p)) : m;
+        return m;
+    }
+    // twiddle rows: for each pass P >= 1 (NS > 1), NS rows of EPT entries
+    // w_{NS R}^{r k}, r < R = EPT (entry 0 is 1).
+    static constexpr int rows_offset(int P)
+    {
+        int off = 0;
+        for (int p = 0; p < P; p++)
+            if (SC::log2ns(p) > 0) off += (1 << SC::log2ns(p)) * SC::EPT;
+        return off;
+    }
+    static constexpr int rows_total() { return rows_offset(SC::NP); }
+};
+
+// Twiddles of pass P for thread t, read as EPT/2 16-byte loads of one row.
+template <int L, int E, int S, int P>
+__device__ __forceinline__ void load_row(cf (&w)[1 << E], const cf* __restrict__ rows, int t)
+{
+    using SC = Sched<L, E>;
+    constexpr int EPT = SC::EPT, NS = 1 << SC::log2ns(P);
+    static_assert(SC::log2r(P) == E, "twiddled passes have radix EPT");
+    const float4* r4 = reinterpret_cast<const float4*>(rows + Layout2<L, E>::rows_offset(P) + (t & (NS - 1)) * EPT);
+#pragma unroll
+    for (int i = 0; i < EPT / 2; i++) {
+        const float4 q = r4[i];
+        w[2 * i] = cf{q.x, S > 0 ? -q.y : q.y};
+        w[2 * i + 1] = cf{q.z, S > 0 ? -q.w : q.w};
+    }
+}
+
+// Twiddle + butterflies of pass P given the row values w (ignored if NS = 1).
+template <int L, int E, int S, int P>
+__device__ __forceinline__ void pass_compute2(cf (&v)[1 << E], const cf (&w)[1 << E])
+{
+    using SC = Sched<L, E>;
+    constexpr int LR = SC::log2r(P), R = 1 << LR, NS = 1 << SC::log2ns(P), Q = SC::EPT / R;
+    if constexpr (NS > 1) {
+#pragma unroll
+        for (int r = 1; r < R; r++)
+            v[r] = cmul(v[r], w[r]);
+    }
+#pragma unroll
+    for (int q = 0; q < Q; q++)
+        dft_strided<R, S, Q, SC::EPT>(v, q);
+}
+
+// Exchange after pass P through this transform's LDS region `lds`.
+template <int L, int E, int P>
+__device__ __forceinline__ void exchange2(cf (&v)[1 << E], int t, cf* lds)
+{
+    using SC = Sched<L, E>;
+    constexpr int LR = SC::log2r(P), R = 1 << LR, LNS = SC::log2ns(P), NS = 1 << LNS;
+    constexpr int EPT = SC::EPT, TPT = SC::TPT, Q = EPT / R;
+    constexpr int B = pad_bits(L, E, P);
+    static_assert(pad_is_affine(L, E, P, B), "padding must keep addresses affine");
+    constexpr int DR = B == 0 ? NS : (LNS >= B ? NS + (NS >> B) : NS);
+    constexpr int DQ = B == 0 ? TPT * R : (TPT * R + ((TPT * R) >> B));
+    constexpr int DM = B == 0 ? TPT : (TPT + (TPT >> B));
+    // base: r = 0, q = 0
+    const int k = t & (NS - 1);
+    const int d0 = ((t >> LNS) << (LNS + LR)) + k;
+    cf* wb = lds + pad<B>(d0);
+#pragma unroll
+    for (int q = 0; q < Q; q++)
+#pragma unroll
+        for (int r = 0; r < R; r++)
+            wb[q * DQ + r * DR] = v[q + r * Q];
+    __syncthreads();
+    const cf* rb = lds + pad<B>(t);
+#pragma unroll
+    for (int m = 0; m < EPT; m++)
+        v[m] = rb[m * DM];
+}
+
 }  // namespace mifft

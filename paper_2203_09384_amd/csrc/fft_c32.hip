@@ -73,51 +73,253 @@ __global__ __launch_bounds__(WG) void k_fft_c32(const cf* __restrict__ in, cf* _
     }
 }
 
+// ---------------------------------------------------------------- v2
+// Persistent, pipelined variant.  Each workgroup walks the transform groups
+// g = blockIdx.x, blockIdx.x + gridDim.x, ...; TPB transforms per group.
+//   TW = 0: the thread's twiddle rows for every pass are loaded once and kept
+//           in VGPRs (they depend on the thread index only);
+//   TW = 1: they are re-read (from L1/L2) for every group.
+//   PF = 1: the next group's input is loaded into a second register set
+//           while the current group is transformed and stored.
+// Global addresses are a uniform (SGPR) group base plus a 32-bit per-thread
+// byte offset; LDS addresses are one per-thread base plus immediates.
+
+template <int L, int E>
+using TwRegs = cf[Sched<L, E>::NP][1 << E];
+
+template <int L, int E, int S, int P = 0>
+__device__ __forceinline__ void load_all_rows(TwRegs<L, E>& tws, const cf* __restrict__ rows, int t)
+{
+    if constexpr (P < Sched<L, E>::NP) {
+        if constexpr (Sched<L, E>::log2ns(P) > 0)
+            load_row<L, E, S, P>(tws[P], rows, t);
+        load_all_rows<L, E, S, P + 1>(tws, rows, t);
+    }
+}
+
+template <int L, int E, int S, int TW, int P = 0>
+__device__ __forceinline__ void run2(cf (&v)[1 << E], int t, const cf* __restrict__ rows,
+                                     const TwRegs<L, E>& tws, cf* lds)
+{
+    using SC = Sched<L, E>;
+    constexpr int EPT = SC::EPT;
+    if constexpr (SC::log2ns(P) > 0) {
+        if constexpr (TW == 0) {
+            pass_compute2<L, E, S, P>(v, tws[P]);
+        } else {
+            cf w[EPT];
+            load_row<L, E, S, P>(w, rows, t);
+            pass_compute2<L, E, S, P>(v, w);
+        }
+    } else {
+        pass_compute2<L, E, S, P>(v, tws[0]);
+    }
+    if constexpr (P + 1 < SC::NP) {
+        if constexpr (P > 0)
+            __syncthreads();  // all reads of the previous exchange are done
+        exchange2<L, E, P>(v, t, lds);
+        run2<L, E, S, TW, P + 1>(v, t, rows, tws, lds);
+    }
+}
+
+template <int L, int E, int TPB>
+__device__ __forceinline__ void load_group(cf (&v)[1 << E], const cf* __restrict__ in, int64_t g, int64_t batch,
+                                           int tb, unsigned toff8)
+{
+    using SC = Sched<L, E>;
+    constexpr int N = SC::N, EPT = SC::EPT, TPT = SC::TPT;
+    const int64_t first = g * TPB;
+    const char* gb = reinterpret_cast<const char*>(in + first * N);
+    if (first + TPB <= batch) {
+#pragma unroll
+        for (int m = 0; m < EPT; m++)
+            v[m] = *reinterpret_cast<const cf*>(gb + (toff8 + (unsigned)(m * TPT * 8)));
+    } else {
+        const bool live = first + tb < batch;
+#pragma unroll
+        for (int m = 0; m < EPT; m++)
+            v[m] = live ? *reinterpret_cast<const cf*>(gb + (toff8 + (unsigned)(m * TPT * 8))) : cf{0.f, 0.f};
+    }
+}
+
+template <int L, int E, int TPB>
+__device__ __forceinline__ void store_group(const cf (&v)[1 << E], cf* __restrict__ out, int64_t g, int64_t batch,
+                                            int tb, unsigned toff8, float scale)
+{
+    using SC = Sched<L, E>;
+    constexpr int N = SC::N, EPT = SC::EPT, TPT = SC::TPT;
+    const int64_t first = g * TPB;
+    char* gb = reinterpret_cast<char*>(out + first * N);
+    if (first + TPB <= batch || first + tb < batch) {
+#pragma unroll
+        for (int m = 0; m < EPT; m++)
+            *reinterpret_cast<cf*>(gb + (toff8 + (unsigned)(m * TPT * 8))) = cscale(v[m], scale);
+    }
+}
+
+template <int L, int E, int WG, int S, int TW, int PF>
+__global__ __launch_bounds__(WG) void k_fft_c32_v2(const cf* __restrict__ in, cf* __restrict__ out,
+                                                   const cf* __restrict__ rows, int64_t batch, float scale)
+{
+    using SC = Sched<L, E>;
+    constexpr int N = SC::N, EPT = SC::EPT, TPT = SC::TPT, TPB = WG / TPT, NP = SC::NP;
+    constexpr int REG = Layout2<L, E>::region();
+    static_assert(TPT >= 2, "v2 needs an LDS exchange");
+    __shared__ cf lds[TPB * REG];
+    const int tid = threadIdx.x, tb = tid / TPT, t = tid % TPT;
+    cf* my = lds + tb * REG;
+    const unsigned toff8 = (unsigned)(tb * N + t) * 8u;
+    const int64_t ngroups = (batch + TPB - 1) / TPB;
+    int64_t g = blockIdx.x;
+    if (g >= ngroups)
+        return;
+    cf tws[NP][EPT];
+#pragma unroll
+    for (int p = 0; p < NP; p++)
+#pragma unroll
+        for (int r = 0; r < EPT; r++)
+            tws[p][r] = cf{1.f, 0.f};
+    if constexpr (TW == 0)
+        load_all_rows<L, E, S>(tws, rows, t);
+    cf a[EPT], b[EPT];
+    load_group<L, E, TPB>(a, in, g, batch, tb, toff8);
+    const int64_t stride = gridDim.x;
+    while (true) {
+        int64_t g1 = g + stride;
+        if (PF && g1 < ngroups)
+            load_group<L, E, TPB>(b, in, g1, batch, tb, toff8);
+        run2<L, E, S, TW>(a, t, rows, tws, my);
+        store_group<L, E, TPB>(a, out, g, batch, tb, toff8, scale);
+        if (g1 >= ngroups)
+            break;
+        if (!PF)
+            load_group<L, E, TPB>(b, in, g1, batch, tb, toff8);
+        __syncthreads();  // LDS is reused by the next group
+        g = g1;
+        g1 = g + stride;
+        if (PF && g1 < ngroups)
+            load_group<L, E, TPB>(a, in, g1, batch, tb, toff8);
+        run2<L, E, S, TW>(b, t, rows, tws, my);
+        store_group<L, E, TPB>(b, out, g, batch, tb, toff8, scale);
+        if (g1 >= ngroups)
+            break;
+        if (!PF)
+            load_group<L, E, TPB>(a, in, g1, batch, tb, toff8);
+        __syncthreads();
+        g = g1;
+    }
+}
+
 template <int LOG2N, int LOG2EPT, int WG, int S>
-hipError_t launch_c32(const void* in, void* out, const void* tw, int64_t batch, float scale,
-                      hipStream_t stream)
+hipError_t launch_c32(const void* in, void* out, const void* tw, const void*, int64_t batch, float scale,
+                      int64_t, hipStream_t stream)
 {
     constexpr int TPB = WG / Sched<LOG2N, LOG2EPT>::TPT;
     const int64_t grid = (batch + TPB - 1) / TPB;
     hipLaunchKernelGGL((k_fft_c32<LOG2N, LOG2EPT, WG, S>), dim3((unsigned)grid), dim3(WG), 0, stream,
-                       static_cast<const cf*>(in), static_cast<cf*>(out), static_cast<const cf*>(tw),
-                       batch, scale);
+                       static_cast<const cf*>(in), static_cast<cf*>(out), static_cast<const cf*>(tw), batch,
+                       scale);
     return hipGetLastError();
 }
 
-// Variant menu: EPT in {2,4,8,16} (not above N; at least 4 once N >= 64),
-// WG in {64,128,256,512}, TPT <= WG, LDS per workgroup <= 64 KiB; a thread
-// owns a whole transform (TPT = 1) only for N <= 16.
+// grid_limit > 0 caps the number of (persistent) workgroups.
+template <int L, int E, int WG, int S, int TW, int PF>
+hipError_t launch_c32_v2(const void* in, void* out, const void*, const void* rows, int64_t batch, float scale,
+                         int64_t grid_limit, hipStream_t stream)
+{
+    constexpr int TPB = WG / Sched<L, E>::TPT;
+    int64_t grid = (batch + TPB - 1) / TPB;
+    if (grid_limit > 0 && grid > grid_limit)
+        grid = grid_limit;
+    hipLaunchKernelGGL((k_fft_c32_v2<L, E, WG, S, TW, PF>), dim3((unsigned)grid), dim3(WG), 0, stream,
+                       static_cast<const cf*>(in), static_cast<cf*>(out), static_cast<const cf*>(rows), batch,
+                       scale);
+    return hipGetLastError();
+}
+
+template <int L, int E, int WG, int S, int TW, int PF>
+int occupancy_v2()
+{
+    int blocks = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_fft_c32_v2<L, E, WG, S, TW, PF>, WG, 0) !=
+        hipSuccess)
+        return 0;
+    return blocks;
+}
+
+// Variant menu, v1: EPT in {2,4,8,16} (not above N; at least 4 once
+// N >= 64), WG in {64,128,256,512}, TPT <= WG, LDS per workgroup <= 64 KiB;
+// a thread owns a whole transform (TPT = 1) only for N <= 16.
 template <int LOG2N, int LOG2EPT, int WG>
 constexpr bool valid_cfg()
 {
-    if (LOG2EPT > LOG2N) return false;
-    if (LOG2N >= 6 && LOG2EPT < 2) return false;
-    constexpr int TPT = (1 << LOG2N) >> LOG2EPT;
-    if (TPT > WG) return false;
-    if (TPT == 1 && LOG2N > 4) return false;
-    if (TPT > 1 && (WG << LOG2EPT) * 8 > 65536) return false;
-    return true;
+    if constexpr (LOG2EPT > LOG2N) {
+        return false;
+    } else {
+        constexpr int TPT = (1 << LOG2N) >> LOG2EPT;
+        if (LOG2N >= 6 && LOG2EPT < 2) return false;
+        if (TPT > WG) return false;
+        if (TPT == 1 && LOG2N > 4) return false;
+        if (TPT > 1 && (WG << LOG2EPT) * 8 > 65536) return false;
+        return true;
+    }
+}
+
+// v2: EPT in {4, 8, 16}, at least two threads per transform, WG <= 256.
+template <int L, int E, int WG>
+constexpr bool valid_v2()
+{
+    if constexpr (E < 2 || E >= L || WG > 256) {
+        return false;
+    } else {
+        constexpr int TPT = (1 << L) >> E;
+        if constexpr (TPT > WG)
+            return false;
+        else
+            return (WG / TPT) * Layout2<L, E>::region() * 8 <= 65536;
+    }
 }
 
 template <int LOG2N, int LOG2EPT, int WG, int S>
 void add_one()
 {
     if constexpr (valid_cfg<LOG2N, LOG2EPT, WG>())
-        register_c32(KernelC32{LOG2N, LOG2EPT, WG, S, &launch_c32<LOG2N, LOG2EPT, WG, S>});
+        register_c32(KernelC32{LOG2N, LOG2EPT, WG, S, 0, &launch_c32<LOG2N, LOG2EPT, WG, S>, nullptr, 0,
+                               ((1 << LOG2N) >> LOG2EPT) > 1 ? WG * (1 << LOG2EPT) * 8 : 0});
+}
+
+template <int L, int E, int WG, int S, int TW, int PF>
+void add_v2()
+{
+    if constexpr (valid_v2<L, E, WG>())
+        register_c32(KernelC32{L, E, WG, S, 1 + TW + 2 * PF, &launch_c32_v2<L, E, WG, S, TW, PF>,
+                               &occupancy_v2<L, E, WG, S, TW, PF>, Layout2<L, E>::rows_total(),
+                               (WG / ((1 << L) >> E)) * Layout2<L, E>::region() * 8});
+}
+
+template <int LOG2N, int LOG2EPT, int WG>
+void add_signs()
+{
+    add_one<LOG2N, LOG2EPT, WG, -1>();
+    add_one<LOG2N, LOG2EPT, WG, +1>();
+    // kinds: 1 = TW0 PF0, 2 = TW1 PF0, 3 = TW0 PF1, 4 = TW1 PF1
+    add_v2<LOG2N, LOG2EPT, WG, -1, 0, 0>();
+    add_v2<LOG2N, LOG2EPT, WG, +1, 0, 0>();
+    add_v2<LOG2N, LOG2EPT, WG, -1, 1, 0>();
+    add_v2<LOG2N, LOG2EPT, WG, +1, 1, 0>();
+    add_v2<LOG2N, LOG2EPT, WG, -1, 0, 1>();
+    add_v2<LOG2N, LOG2EPT, WG, +1, 0, 1>();
+    add_v2<LOG2N, LOG2EPT, WG, -1, 1, 1>();
+    add_v2<LOG2N, LOG2EPT, WG, +1, 1, 1>();
 }
 
 template <int LOG2N, int LOG2EPT>
 void add_wgs()
 {
-    add_one<LOG2N, LOG2EPT, 64, -1>();
-    add_one<LOG2N, LOG2EPT, 64, +1>();
-    add_one<LOG2N, LOG2EPT, 128, -1>();
-    add_one<LOG2N, LOG2EPT, 128, +1>();
-    add_one<LOG2N, LOG2EPT, 256, -1>();
-    add_one<LOG2N, LOG2EPT, 256, +1>();
-    add_one<LOG2N, LOG2EPT, 512, -1>();
-    add_one<LOG2N, LOG2EPT, 512, +1>();
+    add_signs<LOG2N, LOG2EPT, 64>();
+    add_signs<LOG2N, LOG2EPT, 128>();
+    add_signs<LOG2N, LOG2EPT, 256>();
+    add_signs<LOG2N, LOG2EPT, 512>();
 }
 
 struct Registrar {

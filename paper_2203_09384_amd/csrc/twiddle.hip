@@ -56,3 +56,44 @@ hipError_t launch_twiddle_2048(void* tw, hipStream_t stream)
 }
 
 }  // namespace mifft
+
+namespace mifft {
+
+// Per-pass twiddle rows of a (log2 N, log2 EPT) Stockham schedule: for each
+// pass with NS > 1 (radix EPT), NS rows of EPT entries, row k holding
+// w_{NS EPT}^{r k} = tw[(r k) * 2048 / (NS EPT)], r < EPT.  The entries are
+// copies of the 2048-entry table, so both kernel families use identical
+// twiddle values.
+__global__ void k_twiddle_rows(const float2* __restrict__ tw, float2* __restrict__ rows, int L, int E, int total)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= total)
+        return;
+    const int rem = L % E;
+    const int np = L / E + (rem ? 1 : 0);
+    int off = 0;
+    for (int p = 0; p < np; p++) {
+        const int lns = p == 0 ? 0 : (rem ? rem + (p - 1) * E : p * E);
+        if (lns == 0)
+            continue;
+        const int size = (1 << lns) << E;
+        if (i < off + size) {
+            const int k = (i - off) >> E;
+            const int r = (i - off) & ((1 << E) - 1);
+            rows[i] = tw[(r * k) << (11 - lns - E)];
+            return;
+        }
+        off += size;
+    }
+}
+
+hipError_t launch_twiddle_rows(const void* tw, void* rows, int L, int E, int total, hipStream_t stream)
+{
+    if (total <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_twiddle_rows, dim3((total + 255) / 256), dim3(256), 0, stream,
+                       static_cast<const float2*>(tw), static_cast<float2*>(rows), L, E, total);
+    return hipGetLastError();
+}
+
+}  // namespace mifft

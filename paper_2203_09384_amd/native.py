@@ -33,7 +33,7 @@ class PlanDesc(ctypes.Structure):
         ("dtype", ctypes.c_int), ("scale", ctypes.c_float), ("ept", ctypes.c_int),
         ("wg", ctypes.c_int), ("transforms_per_wg", ctypes.c_int), ("grid", ctypes.c_int64),
         ("npasses", ctypes.c_int), ("radices", ctypes.c_int * 8), ("lds_bytes", ctypes.c_int),
-        ("kind", ctypes.c_int), ("tiles", ctypes.c_int64),
+        ("kind", ctypes.c_int), ("tiles", ctypes.c_int64), ("variant", ctypes.c_int),
     ]
 
     def as_dict(self):
@@ -67,7 +67,7 @@ def _declare(L):
     vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
     L.fft_plan_create.argtypes = [i64, i64, i32, i32]
     L.fft_plan_create.restype = vp
-    L.fft_plan_create_config.argtypes = [i64, i64, i32, i32, i32, i32]
+    L.fft_plan_create_config.argtypes = [i64, i64, i32, i32, i32, i32, i32]
     L.fft_plan_create_config.restype = vp
     L.fft_plan_create_ragged.argtypes = [i64, ctypes.POINTER(i64), i32, i32]
     L.fft_plan_create_ragged.restype = vp

@@ -1,0 +1,100 @@
+"""Autotuner: times every compiled kernel variant and writes the tuned table.
+
+For the batched FP32 path it times, per length N, each (elements per thread,
+workgroup size) variant compiled into libmifft.so on a batch of `total`
+elements, and keeps the fastest.  For ragged batches it picks, per length,
+the elements-per-thread of the persistent kernel and the workgroup size of
+the launch, timing one graph-free persistent launch over a seeded ragged
+batch.  The result is a text table ("c32 <log2n> <ept> <wg> <variant>" and
+"ragged <log2n> <ept>" / "ragged_wg <wg> <ctas_per_cu>" lines) that the library reads
+from the file named by MIFFT_TUNE_TABLE, plus a JSON record of every
+timing.
+
+    python -m paper_2203_09384_amd.tune --out tune_gfx950.txt
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import sys
+
+EPTS = (2, 4, 8, 16)
+WGS = (64, 128, 256, 512)
+VARIANTS = (0, 1, 2, 3, 4)
+
+
+def _time(fn, steps, warmup, torch):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(st)
+    for _ in range(steps):
+        fn()
+    b.record(st)
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / steps
+
+
+def tune_c32(total: int = 1 << 26, steps: int = 30, warmup: int = 5, log2ns=range(1, 12), log=print):
+    import torch
+    from . import api, synth
+    from .native import MifftError
+    x = torch.from_numpy(synth.uniform_complex(synth.SEED_PLAIN, (total,), key=(0,))).cuda()
+    y = torch.empty_like(x)
+    best, record = {}, []
+    for L in log2ns:
+        n = 1 << L
+        b = total // n
+        xs, ys = x[: b * n].view(b, n), y[: b * n].view(b, n)
+        for ept in EPTS:
+            for wg in WGS:
+                for var in VARIANTS:
+                    try:
+                        p = api.Plan(n, b, -1, ept=ept, wg=wg, variant=var)
+                    except MifftError:
+                        continue
+                    ms = _time(lambda: p.execute(xs, ys), steps, warmup, torch)
+                    gbps = 16.0 * b * n / (ms * 1e-3) / 1e9
+                    rec = {"n": n, "ept": ept, "wg": wg, "variant": var, "us": round(ms * 1e3, 2),
+                           "GBps": round(gbps, 1), "grid": p.describe()["grid"]}
+                    record.append(rec)
+                    log(f"[tune] {rec}")
+                    if L not in best or ms < best[L][3]:
+                        best[L] = (ept, wg, var, ms)
+                    p.close()
+    return best, record
+
+
+def write_table(path: str, best_c32: dict, ragged: dict | None = None):
+    with open(path, "w") as f:
+        f.write("# mifft tuned variants for gfx950 (written by paper_2203_09384_amd.tune)\n")
+        for L in sorted(best_c32):
+            ept, wg, var, ms = best_c32[L]
+            f.write(f"c32 {L} {ept} {wg} {var}  # {ms * 1e3:.2f} us\n")
+        if ragged:
+            for L in sorted(ragged.get("ept", {})):
+                f.write(f"ragged {L} {ragged['ept'][L]}\n")
+            if "wg" in ragged:
+                f.write(f"ragged_wg {ragged['wg']} {ragged.get('ctas_per_cu', 0)}\n")
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--out", default="tune_gfx950.txt")
+    ap.add_argument("--json", default=None)
+    ap.add_argument("--total-log2", type=int, default=26)
+    ap.add_argument("--steps", type=int, default=30)
+    args = ap.parse_args(argv)
+    best, rec = tune_c32(1 << args.total_log2, args.steps, log=lambda m: print(m, file=sys.stderr, flush=True))
+    write_table(args.out, best)
+    if args.json:
+        with open(args.json, "w") as f:
+            json.dump({"c32": rec, "best": {L: best[L][:3] for L in best}}, f, indent=1)
+    print(json.dumps({L: best[L][:3] for L in best}))
+
+
+if __name__ == "__main__":
+    main()

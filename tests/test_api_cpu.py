@@ -77,7 +77,7 @@ def test_validation_happens_before_hip():
     assert L.fft_plan_create(256, 0, -1, 0) is None and L.fft_last_error() == 2
     assert L.fft_plan_create(256, 1, 3, 0) is None and L.fft_last_error() == 3
     assert L.fft_plan_create(256, 1, -1, 9) is None and L.fft_last_error() == 4
-    assert L.fft_plan_create_config(256, 1, -1, 0, 3, 256) is None and L.fft_last_error() == 10
+    assert L.fft_plan_create_config(256, 1, -1, 0, 3, 256, 0) is None and L.fft_last_error() == 10
     bad = [np.array([0, 8, 20], np.int64), np.array([1, 9], np.int64),
            np.array([0, 4096], np.int64), np.array([0, 8, 8], np.int64)]
     for off in bad:

@@ -83,23 +83,31 @@ def variants():
     for n in NS:
         for ept in (2, 4, 8, 16):
             for wg in (64, 128, 256, 512):
-                out.append((n, ept, wg))
+                for var in range(5):
+                    out.append((n, ept, wg, var))
     return out
 
 
-@pytest.mark.parametrize("n,ept,wg", variants())
-def test_every_compiled_variant(n, ept, wg):
+@pytest.mark.parametrize("n,ept,wg,var", variants())
+def test_every_compiled_variant(n, ept, wg, var):
+    """Every compiled kernel variant, both signs, several workgroups and a
+    partly filled last group; persistent variants (3, 4) additionally with
+    more groups than workgroups, so each workgroup loops and prefetches."""
     try:
-        p = api.Plan(n, 1, -1, ept=ept, wg=wg)
+        p = api.Plan(n, 1 << 24, -1, ept=ept, wg=wg, variant=var)
     except MifftError as e:
         assert e.status == "FFT_EINVAL_CONFIG"
         pytest.skip("variant not compiled in")
-    tpw = p.describe()["transforms_per_wg"]
-    batch = 2 * tpw + 3 if tpw > 3 else 2 * tpw + 1
-    for sign in (-1, 1):
-        x = synth.uniform_complex(synth.SEED_PLAIN, (batch, n), key=(n, ept, wg, sign + 1))
-        y = run(api.Plan(n, batch, sign, ept=ept, wg=wg), x)
-        assert per_transform_relerr(y, oracle_ref(x, sign)) <= TOL, (n, ept, wg, sign)
+    d = p.describe()
+    tpw = d["transforms_per_wg"]
+    batches = [2 * tpw + 3 if tpw > 3 else 2 * tpw + 1]
+    if var >= 3:
+        batches.append(int(2.5 * d["grid"] * tpw) + (tpw // 2 if tpw > 1 else 0) + 1)
+    for batch in batches:
+        for sign in (-1, 1):
+            x = synth.uniform_complex(synth.SEED_PLAIN, (batch, n), key=(n, ept, wg, var, sign + 1))
+            y = run(api.Plan(n, batch, sign, ept=ept, wg=wg, variant=var), x)
+            assert per_transform_relerr(y, oracle_ref(x, sign)) <= TOL, (n, ept, wg, var, sign, batch)
 
 
 @pytest.mark.parametrize("n", NS)
