@@ -87,7 +87,10 @@ typedef struct {
     int variant;        /* kernel family: 0 one transform group per
                            workgroup; 1..4 twiddle-row kernels (1, 2: one
                            group per workgroup, twiddles kept / re-read;
-                           3, 4: persistent with next-group prefetch)       */
+                           3, 4: persistent with next-group prefetch);
+                           5..8 as 1..4 with wavefront-local exchanges
+                           (transforms of at most 64 threads)               */
+    int ept_by_log2n[12]; /* ragged: elements per thread used for length 2^L */
 } fft_plan_desc;
 
 /*
@@ -109,7 +112,7 @@ fft_plan fft_plan_create(int64_t n, int64_t batch, int sign, int dtype);
 /*
  * As fft_plan_create, forcing the kernel variant: `ept` complex elements
  * per thread (2, 4, 8 or 16), `wg` threads per workgroup (64, 128, 256 or
- * 512) and the kernel family `variant` (0..4, see fft_plan_desc.variant).
+ * 512) and the kernel family `variant` (0..8, see fft_plan_desc.variant).
  * FP32 only.  Used by the autotuner.  FFT_EINVAL_CONFIG if that variant is
  * not compiled in.
  */
@@ -134,7 +137,8 @@ fft_plan fft_plan_create_ragged(int64_t count, const int64_t *offsets, int sign,
  * ept_by_log2n[L] (L = 1..11; entries 0 ignored) gives the elements per
  * thread used for length 2^L, `wg` the workgroup size of the persistent
  * launch (64..512) and `ctas_per_cu` how many workgroups per compute unit
- * the launch holds (0: as many as fit).  Used by the autotuner.
+ * the launch holds (0: as many as fit).  wg must be 64, 128 or 256 (0: the
+ * built-in choice).  Used by the autotuner.
  */
 fft_plan fft_plan_create_ragged_config(int64_t count, const int64_t *offsets, int sign, int dtype,
                                        const int *ept_by_log2n, int wg, int ctas_per_cu);

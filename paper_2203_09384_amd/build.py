@@ -27,7 +27,9 @@ def _units():
     for L in range(1, 12):
         units.append(("fft_c32.hip", f"fft_c32_L{L}.o", [f"-DMIFFT_LOG2N={L}"]))
     units.append(("twiddle.hip", "twiddle.o", []))
-    units.append(("ragged.hip", "ragged.o", []))
+    for wg in (64, 128, 256):
+        units.append(("ragged.hip", f"ragged_wg{wg}.o", [f"-DMIFFT_RAGGED_WG={wg}"]))
+    units.append(("ragged_plan.cpp", "ragged_plan.o", ["-x", "hip"]))
     units.append(("half.hip", "half.o", []))
     units.append(("api.cpp", "api.o", ["-x", "hip"]))
     return units

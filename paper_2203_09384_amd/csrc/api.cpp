@@ -99,12 +99,12 @@ const Variant kDefaultC32[12] = {
     {3, 256, 0},  // N=8
     {2, 256, 2},  // N=16
     {3, 256, 1},  // N=32
-    {2, 128, 2},  // N=64
-    {3, 256, 2},  // N=128
-    {3, 64, 2},   // N=256
-    {3, 256, 2},  // N=512
-    {3, 256, 2},  // N=1024
-    {3, 256, 4},  // N=2048  persistent, next-group prefetch
+    {2, 128, 6},  // N=64    wavefront-local exchanges
+    {3, 64, 6},   // N=128
+    {3, 64, 6},   // N=256
+    {3, 64, 5},   // N=512
+    {4, 64, 3},   // N=1024  persistent, next-group prefetch
+    {4, 128, 3},  // N=2048  persistent, next-group prefetch
 };
 
 std::once_flag g_tune_once;
@@ -273,7 +273,7 @@ int make_rows(mifft_plan_s* p)
             return hip_err(e, "twiddle rows kernel");
     }
     p->grid_limit = 0;
-    if (k->kind >= 3 && k->occupancy) {
+    if ((k->kind == 3 || k->kind == 4 || k->kind == 7 || k->kind == 8) && k->occupancy) {
         int cus = 0;
         hipError_t e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device);
         if (e != hipSuccess)
@@ -423,8 +423,8 @@ fft_plan fft_plan_create_config(int64_t n, int64_t batch, int sign, int dtype, i
         return nullptr;
     }
     if (!is_pow2(ept) || ept < 2 || ept > 16 || !is_pow2(wg) || wg < 64 || wg > 512 || variant < 0 ||
-        variant > 4) {
-        set_err(FFT_EINVAL_CONFIG, "ept=%d must be 2..16, wg=%d 64..512 (powers of two), variant=%d 0..4", ept,
+        variant > 8) {
+        set_err(FFT_EINVAL_CONFIG, "ept=%d must be 2..16, wg=%d 64..512 (powers of two), variant=%d 0..8", ept,
                 wg, variant);
         return nullptr;
     }
@@ -496,7 +496,7 @@ fft_plan fft_plan_create_ragged_config(int64_t count, const int64_t* offsets, in
         free_plan(p);
         return nullptr;
     }
-    rc = ragged_create(&p->ragged, count, offsets, ept_by_log2n, wg, ctas_per_cu, dev);
+    rc = ragged_create(&p->ragged, count, offsets, ept_by_log2n, wg, ctas_per_cu, dev, p->tw);
     if (rc != FFT_OK) {
         set_err(rc, "%s", ragged_last_message());
         free_plan(p);
@@ -561,7 +561,7 @@ int fft_plan_describe(fft_plan p, fft_plan_desc* d)
         d->dtype = p->dtype;
         d->scale = 1.0f;
         d->kind = 1;
-        ragged_describe(p->ragged, &d->wg, &d->grid, &d->tiles, &d->lds_bytes);
+        ragged_describe(p->ragged, &d->wg, &d->grid, &d->tiles, &d->lds_bytes, d->ept_by_log2n);
         return ok();
     }
     if (p->dtype == FFT_C32) {

@@ -422,8 +422,25 @@ __device__ __forceinline__ void pass_compute2(cf (&v)[1 << E], const cf (&w)[1 <
         dft_strided<R, S, Q, SC::EPT>(v, q);
 }
 
+// Orders LDS accesses between the threads that share a transform.  When a
+// transform's threads all sit in one wavefront (WAVE), its LDS region is
+// private to that wavefront and LDS instructions of a wavefront execute in
+// issue order, so only compiler reordering must be prevented: no s_barrier.
+// Otherwise a workgroup barrier.
+template <bool WAVE>
+__device__ __forceinline__ void lds_sync()
+{
+    if constexpr (WAVE) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+        __syncthreads();
+    }
+}
+
 // Exchange after pass P through this transform's LDS region `lds`.
-template <int L, int E, int P>
+template <int L, int E, int P, bool WAVE>
 __device__ __forceinline__ void exchange2(cf (&v)[1 << E], int t, cf* lds)
 {
     using SC = Sched<L, E>;
@@ -443,11 +460,50 @@ __device__ __forceinline__ void exchange2(cf (&v)[1 << E], int t, cf* lds)
 #pragma unroll
         for (int r = 0; r < R; r++)
             wb[q * DQ + r * DR] = v[q + r * Q];
-    __syncthreads();
+    lds_sync<WAVE>();
     const cf* rb = lds + pad<B>(t);
 #pragma unroll
     for (int m = 0; m < EPT; m++)
         v[m] = rb[m * DM];
+}
+
+// ---------------------------------------------------------------- pass runner
+template <int L, int E>
+using TwRegs = cf[Sched<L, E>::NP][1 << E];
+
+template <int L, int E, int S, int P = 0>
+__device__ __forceinline__ void load_all_rows(TwRegs<L, E>& tws, const cf* __restrict__ rows, int t)
+{
+    if constexpr (P < Sched<L, E>::NP) {
+        if constexpr (Sched<L, E>::log2ns(P) > 0)
+            load_row<L, E, S, P>(tws[P], rows, t);
+        load_all_rows<L, E, S, P + 1>(tws, rows, t);
+    }
+}
+
+template <int L, int E, int S, int TW, bool WAVE, int P = 0>
+__device__ __forceinline__ void run2(cf (&v)[1 << E], int t, const cf* __restrict__ rows,
+                                     const TwRegs<L, E>& tws, cf* lds)
+{
+    using SC = Sched<L, E>;
+    constexpr int EPT = SC::EPT;
+    if constexpr (SC::log2ns(P) > 0) {
+        if constexpr (TW == 0) {
+            pass_compute2<L, E, S, P>(v, tws[P]);
+        } else {
+            cf w[EPT];
+            load_row<L, E, S, P>(w, rows, t);
+            pass_compute2<L, E, S, P>(v, w);
+        }
+    } else {
+        pass_compute2<L, E, S, P>(v, tws[0]);
+    }
+    if constexpr (P + 1 < SC::NP) {
+        if constexpr (P > 0)
+            lds_sync<WAVE>();  // all reads of the previous exchange are done
+        exchange2<L, E, P, WAVE>(v, t, lds);
+        run2<L, E, S, TW, WAVE, P + 1>(v, t, rows, tws, lds);
+    }
 }
 
 }  // namespace mifft

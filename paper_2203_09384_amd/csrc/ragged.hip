@@ -1,15 +1,167 @@
-// Ragged batches (placeholder until the persistent kernel lands).
-#include "ragged.hpp"
-#include "../../include/mifft.h"
+// Persistent kernel for ragged batches (mixed power-of-two lengths packed
+// back to back), compiled once per workgroup size (-DMIFFT_RAGGED_WG).
+//
+// The paper finds that for transforms running O(10) us, kernel dispatch --
+// not the transform -- dominates (section "Results", launch-latency table).
+// A mixed batch would otherwise need one launch per length.  Here one
+// launch of CUs x occupancy workgroups pulls tiles from a counter (largest
+// lengths first) and dispatches, per tile, to the transform instantiated
+// for that (length, elements per thread); every such instantiation is the
+// same Stockham pass machinery as the batched kernels.  The last workgroup
+// to finish resets the counters, so the launch can be replayed from a
+// hipGraph without any memset node.
+#include "device_fft.hpp"
+#include "ragged_kernel.hpp"
+
+#ifndef MIFFT_RAGGED_WG
+#error "compile with -DMIFFT_RAGGED_WG=<64|128|256>"
+#endif
 
 namespace mifft {
-struct RaggedPlan {
-    int dummy;
+namespace {
+
+// LDS elements a kernel needs: the largest per-tile region over its pairs.
+template <int WG, int MAXE>
+constexpr int ragged_lds_elems()
+{
+    int m = 0;
+    for (int L = 1; L <= 11; L++)
+        for (int E = 1; E <= 4; E++) {
+            if (!ragged_pair_ok(L, E, WG, MAXE))
+                continue;
+            const int tpt = (1 << L) >> E;
+            if (tpt < 2)
+                continue;
+            // region(): N + N >> B for the largest padding of the schedule
+            int reg = 1 << L;
+            const int rem = L % E;
+            const int np = L / E + (rem ? 1 : 0);
+            for (int p = 0; p + 1 < np; p++) {
+                const int B = pad_bits(L, E, p);
+                const int r = B == 0 ? (1 << L) : (1 << L) + ((1 << L) >> B);
+                reg = r > reg ? r : reg;
+            }
+            const int need = (WG / tpt) * reg;
+            m = need > m ? need : m;
+        }
+    return m > 0 ? m : 1;
+}
+
+template <int L, int E, int WG, int S>
+__device__ __forceinline__ void ragged_tile(const RaggedArgs& a, const RaggedTile& tile, cf* lds)
+{
+    using SC = Sched<L, E>;
+    constexpr int N = SC::N, EPT = SC::EPT, TPT = SC::TPT;
+    const int tid = threadIdx.x, tb = tid / TPT, t = tid % TPT;
+    const bool live = tb < tile.count;
+    const int64_t off = live ? a.toff[tile.first + tb] : 0;
+    const cf* __restrict__ src = static_cast<const cf*>(a.in) + off;
+    cf* __restrict__ dst = static_cast<cf*>(a.out) + off;
+    const float scale = a.inv ? 1.0f / (float)N : 1.0f;
+    cf v[EPT];
+#pragma unroll
+    for (int m = 0; m < EPT; m++)
+        v[m] = live ? src[t + m * TPT] : cf{0.f, 0.f};
+    TwRegs<L, E> tws;
+#pragma unroll
+    for (int p = 0; p < SC::NP; p++)
+#pragma unroll
+        for (int r = 0; r < EPT; r++)
+            tws[p][r] = cf{1.f, 0.f};
+    if constexpr (TPT == 1) {
+        pass_compute2<L, E, S, 0>(v, tws[0]);
+    } else {
+        constexpr int REG = Layout2<L, E>::region();
+        run2<L, E, S, 1, (TPT <= 64)>(v, t, static_cast<const cf*>(a.rows) + a.rows_off[L], tws,
+                                      lds + tb * REG);
+    }
+    if (live) {
+#pragma unroll
+        for (int m = 0; m < EPT; m++)
+            dst[t + m * TPT] = cscale(v[m], scale);
+    }
+}
+
+#define MIFFT_RCASE(L, E)                                      \
+    case (L) * 8 + (E):                                        \
+        if constexpr (ragged_pair_ok(L, E, WG, MAXE))          \
+            ragged_tile<L, E, WG, S>(a, tile, lds);            \
+        break;
+
+template <int WG, int MAXE, int S>
+__global__ __launch_bounds__(WG) void k_fft_ragged(RaggedArgs a)
+{
+    __shared__ cf lds[ragged_lds_elems<WG, MAXE>()];
+    __shared__ int s_tile;
+    while (true) {
+        if (threadIdx.x == 0)
+            s_tile = atomicAdd(a.counter, 1);
+        __syncthreads();
+        const int ti = s_tile;
+        __syncthreads();  // s_tile read by all; the previous tile's LDS use is over
+        if (ti >= a.ntiles)
+            break;
+        const RaggedTile tile = a.tiles[ti];
+        switch (tile.log2n * 8 + tile.log2e) {
+            MIFFT_RCASE(1, 1)
+            MIFFT_RCASE(2, 1) MIFFT_RCASE(2, 2)
+            MIFFT_RCASE(3, 2) MIFFT_RCASE(3, 3)
+            MIFFT_RCASE(4, 2) MIFFT_RCASE(4, 3) MIFFT_RCASE(4, 4)
+            MIFFT_RCASE(5, 2) MIFFT_RCASE(5, 3) MIFFT_RCASE(5, 4)
+            MIFFT_RCASE(6, 2) MIFFT_RCASE(6, 3) MIFFT_RCASE(6, 4)
+            MIFFT_RCASE(7, 2) MIFFT_RCASE(7, 3) MIFFT_RCASE(7, 4)
+            MIFFT_RCASE(8, 2) MIFFT_RCASE(8, 3) MIFFT_RCASE(8, 4)
+            MIFFT_RCASE(9, 2) MIFFT_RCASE(9, 3) MIFFT_RCASE(9, 4)
+            MIFFT_RCASE(10, 2) MIFFT_RCASE(10, 3) MIFFT_RCASE(10, 4)
+            MIFFT_RCASE(11, 2) MIFFT_RCASE(11, 3) MIFFT_RCASE(11, 4)
+            default:
+                break;
+        }
+    }
+    // The last workgroup out resets both counters for the next launch.
+    if (threadIdx.x == 0) {
+        if (atomicAdd(a.done, 1) == (int)gridDim.x - 1) {
+            atomicExch(a.counter, 0);
+            atomicExch(a.done, 0);
+        }
+    }
+}
+
+#undef MIFFT_RCASE
+
+template <int WG, int MAXE, int S>
+hipError_t launch_ragged(const RaggedArgs& a, int grid, hipStream_t stream)
+{
+    hipLaunchKernelGGL((k_fft_ragged<WG, MAXE, S>), dim3(grid), dim3(WG), 0, stream, a);
+    return hipGetLastError();
+}
+
+template <int WG, int MAXE, int S>
+int occupancy_ragged()
+{
+    int blocks = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_fft_ragged<WG, MAXE, S>, WG, 0) != hipSuccess)
+        return 0;
+    return blocks;
+}
+
+template <int WG, int MAXE, int S>
+void add_ragged()
+{
+    register_ragged(KernelRagged{WG, MAXE, S, &launch_ragged<WG, MAXE, S>, &occupancy_ragged<WG, MAXE, S>,
+                                 (int)(ragged_lds_elems<WG, MAXE>() * sizeof(cf))});
+}
+
+struct RaggedRegistrar {
+    RaggedRegistrar()
+    {
+        add_ragged<MIFFT_RAGGED_WG, 3, -1>();
+        add_ragged<MIFFT_RAGGED_WG, 3, +1>();
+        add_ragged<MIFFT_RAGGED_WG, 4, -1>();
+        add_ragged<MIFFT_RAGGED_WG, 4, +1>();
+    }
 };
-int ragged_check_config(const int*, int, int) { return FFT_OK; }
-int ragged_create(RaggedPlan**, int64_t, const int64_t*, const int*, int, int, int) { return FFT_EINVAL_DTYPE; }
-int ragged_execute(RaggedPlan*, const void*, void*, const void*, int, bool, hipStream_t) { return FFT_EINVAL_DTYPE; }
-void ragged_destroy(RaggedPlan* rp) { delete rp; }
-void ragged_describe(const RaggedPlan*, int*, int64_t*, int64_t*, int*) {}
-const char* ragged_last_message() { return "ragged plans are not available in this build"; }
+RaggedRegistrar ragged_registrar;
+
+}  // namespace
 }  // namespace mifft

@@ -18,7 +18,8 @@ using LaunchC32 = hipError_t (*)(const void* in, void* out, const void* tw, cons
 struct KernelC32 {
     int log2n, log2ept, wg, sign;
     int kind;                 // 0: one transform group per workgroup, per-pass table reads
-                              // 1..4: persistent (1 + TW + 2 PF), see fft_c32.hip
+                              // 1..4: twiddle-row kernels (1 + TW + 2 PF), see fft_c32.hip
+                              // 5..8: the same with wave-local LDS exchanges
     LaunchC32 fn;
     int (*occupancy)();       // workgroups per CU (persistent kinds), else NULL
     int rows;                 // twiddle-row entries the variant needs (kind >= 1)

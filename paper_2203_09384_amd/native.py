@@ -34,11 +34,13 @@ class PlanDesc(ctypes.Structure):
         ("wg", ctypes.c_int), ("transforms_per_wg", ctypes.c_int), ("grid", ctypes.c_int64),
         ("npasses", ctypes.c_int), ("radices", ctypes.c_int * 8), ("lds_bytes", ctypes.c_int),
         ("kind", ctypes.c_int), ("tiles", ctypes.c_int64), ("variant", ctypes.c_int),
+        ("ept_by_log2n", ctypes.c_int * 12),
     ]
 
     def as_dict(self):
-        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "radices"}
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k not in ("radices", "ept_by_log2n")}
         d["radices"] = list(self.radices)[: self.npasses]
+        d["ept_by_log2n"] = list(self.ept_by_log2n)
         return d
 
 

@@ -21,7 +21,7 @@ import sys
 
 EPTS = (2, 4, 8, 16)
 WGS = (64, 128, 256, 512)
-VARIANTS = (0, 1, 2, 3, 4)
+VARIANTS = tuple(range(9))
 
 
 def _time(fn, steps, warmup, torch):

@@ -83,7 +83,7 @@ def variants():
     for n in NS:
         for ept in (2, 4, 8, 16):
             for wg in (64, 128, 256, 512):
-                for var in range(5):
+                for var in range(9):
                     out.append((n, ept, wg, var))
     return out
 
@@ -91,7 +91,7 @@ def variants():
 @pytest.mark.parametrize("n,ept,wg,var", variants())
 def test_every_compiled_variant(n, ept, wg, var):
     """Every compiled kernel variant, both signs, several workgroups and a
-    partly filled last group; persistent variants (3, 4) additionally with
+    partly filled last group; persistent variants (3, 4, 7, 8) additionally with
     more groups than workgroups, so each workgroup loops and prefetches."""
     try:
         p = api.Plan(n, 1 << 24, -1, ept=ept, wg=wg, variant=var)
@@ -101,7 +101,7 @@ def test_every_compiled_variant(n, ept, wg, var):
     d = p.describe()
     tpw = d["transforms_per_wg"]
     batches = [2 * tpw + 3 if tpw > 3 else 2 * tpw + 1]
-    if var >= 3:
+    if var in (3, 4, 7, 8):
         batches.append(int(2.5 * d["grid"] * tpw) + (tpw // 2 if tpw > 1 else 0) + 1)
     for batch in batches:
         for sign in (-1, 1):
