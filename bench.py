@@ -7,13 +7,13 @@ One step = one fft_execute of that batch.  Also measured in the same run:
 the forward + adjoint pair of the differentiable FFT (N = 2048, batch
 16384), the per-N sweep (every N = 2..2048 at 2^26 elements, forward and
 inverse), a plain 512 MiB copy kernel as the practical bandwidth ceiling,
-and the FP64 CPU oracle on a bounded sample (cpu_baseline).
+the ragged batch (4096 mixed lengths, one persistent launch vs per-length
+launches), and the FP64 CPU oracle on a bounded sample (cpu_baseline).
 
 Prints ONE JSON line.  Times come from HIP events recorded on the stream
 the kernels are launched on (torch's current stream).
 """
 import argparse
-import hashlib
 import json
 import math
 import os
@@ -26,7 +26,6 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBPS = 8000.0
 METRIC = "FP32 C2C FFT GFLOP/s (5NlogN) & HBM GB/s at N=2048; fwd+adjoint vs plain fwd"
-KERNEL_SOURCES = ["paper_2203_09384_amd/csrc/device_fft.hpp", "paper_2203_09384_amd/csrc/fft_c32.hip"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_fft_c32_n2048_b32768.json")
 
 
@@ -34,12 +33,16 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def kernel_hash():
-    h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
+def kernel_name(d):
+    """Name of the kernel template instance a plan launches."""
+    L = int(math.log2(d["n"]))
+    e = int(math.log2(d["ept"]))
+    if d["variant"] == 0:
+        return f"k_fft_c32<{L}, {e}, {d['wg']}, {d['sign']}>"
+    v = d["variant"] - 1
+    wave = v >= 4
+    v %= 4
+    return f"k_fft_c32_v2<{L}, {e}, {d['wg']}, {d['sign']}, {v % 2}, {v // 2}, {str(wave).lower()}>"
 
 
 def time_launches(fn, steps, warmup, torch):
@@ -72,26 +75,91 @@ def per_call_distribution(fn, reps, torch):
     return {"min_ms": ts[0], "median_ms": ts[len(ts) // 2], "mean_ms": sum(ts) / len(ts)}
 
 
-def cpu_baseline(n, budget_s=12.0):
-    """FP64 oracle on a bounded sample of the headline workload."""
+def cpu_baseline(n, batch, budget_s=12.0):
+    """FP64 oracle on a bounded sample of the headline workload: chunks of
+    the same seeded N=2048 batch, repeated until about budget_s seconds."""
     import numpy as np
     import oracle
     from paper_2203_09384_amd import synth
     threads = oracle.default_threads()
-    probe = synth.uniform_complex(synth.SEED_PLAIN, (threads * 4, n), key=(n, 1234)).astype(np.complex128)
-    t0 = time.perf_counter()
-    oracle.forward(probe, threads=threads)
-    dt = time.perf_counter() - t0
-    per = dt / probe.shape[0]
-    count = int(max(threads * 4, min(1 << 15, budget_s / max(per, 1e-9))))
-    x = synth.uniform_complex(synth.SEED_PLAIN, (count, n), key=(n, 4321)).astype(np.complex128)
-    t0 = time.perf_counter()
-    oracle.forward(x, threads=threads)
-    dt = time.perf_counter() - t0
-    flops = 5.0 * n * math.log2(n) * count
+    chunk = min(batch, 4096)
+    x = synth.uniform_complex(synth.SEED_PLAIN, (chunk * n,), key=(0,)).reshape(chunk, n).astype(np.complex128)
+    done, t0 = 0, time.perf_counter()
+    while True:
+        oracle.forward(x, threads=threads)
+        done += chunk
+        dt = time.perf_counter() - t0
+        if dt >= budget_s or done >= 64 * batch:
+            break
+    flops = 5.0 * n * math.log2(n) * done
     return {"value": round(flops / dt / 1e9, 3), "unit": "GFLOP/s", "cores": threads, "kind": "oracle",
-            "sample": f"{count} forward transforms of N={n} (FP64 recursive radix-2, {dt:.1f} s)",
+            "sample": f"{done} forward transforms of N={n} (the first {chunk} transforms of the headline "
+                      f"batch, repeated; FP64 recursive radix-2 on {threads} threads, {dt:.1f} s)",
             "seconds": round(dt, 2)}
+
+
+def bench_ragged(api, synth, torch, dev, iters):
+    """One persistent launch over 4096 mixed-length transforms (eager and
+    graph-replayed) against per-length plain launches (eager and in one
+    graph), the transforms pre-grouped by length outside the timed region."""
+    import numpy as np
+    lengths = synth.ragged_lengths(synth.SEED_RAGGED, 4096, 3, 11)
+    off = synth.offsets_from_lengths(lengths)
+    total = int(off[-1])
+    x = torch.from_numpy(synth.uniform_complex(synth.SEED_RAGGED, (total,), key=(1,))).to(dev)
+    y = torch.empty_like(x)
+    rp = api.RaggedPlan(off, -1)
+    desc = rp.describe()
+    t_eager = time_launches(lambda: rp.execute(x, y), iters, 50, torch)
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        rp.execute(x, y)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g):
+        rp.execute(x, y)
+    t_graph = time_launches(g.replay, iters, 50, torch)
+    # per-length batches, grouped once (untimed)
+    groups = []
+    for L in range(3, 12):
+        idx = np.nonzero(lengths == (1 << L))[0]
+        if len(idx) == 0:
+            continue
+        n = 1 << L
+        cols = (off[idx][:, None] + np.arange(n)[None, :]).reshape(-1)
+        xs = x[torch.from_numpy(cols).to(dev)].view(len(idx), n).contiguous()
+        groups.append((api.Plan(n, len(idx), -1), xs, torch.empty_like(xs)))
+
+    def per_length():
+        for p, xs, ys in groups:
+            p.execute(xs, ys)
+    t_pl = time_launches(per_length, iters, 50, torch)
+    g2 = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        per_length()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g2):
+        per_length()
+    t_pl_graph = time_launches(g2.replay, iters, 50, torch)
+    flops = float(np.sum(5.0 * lengths * np.log2(lengths)))
+    bytes_ = 16.0 * total
+    us = lambda ms: round(ms * 1e3, 2)
+    return {
+        "workload": "4096 FP32 C2C forward transforms, N=2^L with L uniform on 3..11 (seeded), "
+                    f"{total} elements packed with int64 offsets",
+        "persistent_eager_us": us(t_eager), "persistent_graph_us": us(t_graph),
+        "per_length_eager_us": us(t_pl), "per_length_graph_us": us(t_pl_graph),
+        "launches_per_length_path": len(groups),
+        "speedup_vs_per_length_eager": round(t_pl / t_eager, 2),
+        "speedup_graph_vs_per_length_graph": round(t_pl_graph / t_graph, 2),
+        "persistent_graph_GFLOPs": round(flops / (t_graph * 1e-3) / 1e9, 1),
+        "persistent_graph_effective_GBps": round(bytes_ / (t_graph * 1e-3) / 1e9, 1),
+        "note": "about 30 MB moved: cache-resident, so effective GB/s is not an HBM figure",
+        "plan": {k: desc[k] for k in ("wg", "grid", "tiles", "lds_bytes", "ept_by_log2n")},
+    }
 
 
 def main():
@@ -103,6 +171,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--only-headline", action="store_true",
                     help="time only the headline kernel (for profiler runs)")
+    ap.add_argument("--with-copy", action="store_true",
+                    help="with --only-headline: also run the 512 MiB copy kernel (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: the batched transforms are independent, so the path "
@@ -112,6 +182,7 @@ def main():
     import numpy as np
     import torch
     from paper_2203_09384_amd import api, synth
+    from paper_2203_09384_amd.profiling import kernel_hash
 
     torch.cuda.set_device(0)
     dev = torch.device("cuda", 0)
@@ -132,6 +203,12 @@ def main():
     plan = api.Plan(n, batch, -1)
     desc = plan.describe()
     log(f"[bench] headline plan {desc}")
+    # settle clocks: about half a second of the same kernel before timing
+    t_end = time.perf_counter() + 0.5
+    while time.perf_counter() < t_end:
+        for _ in range(20):
+            plan.execute(x, y)
+        torch.cuda.synchronize()
     ms = time_launches(lambda: plan.execute(x, y), args.steps, args.warmup, torch)
     bytes_alg = 16.0 * total
     gbps = bytes_alg / (ms * 1e-3) / 1e9
@@ -145,6 +222,7 @@ def main():
         "config": {"workload": "FP32 C2C forward FFT, N=2048, batch 32768 (2^26 complex64, "
                                "512 MiB in + 512 MiB out), out of place, re/im uniform[-1,1) seeded",
                    "n": n, "batch": batch, "ept": desc["ept"], "wg": desc["wg"],
+                   "variant": desc["variant"], "grid": desc["grid"],
                    "radices": desc["radices"], "seed": synth.SEED_PLAIN},
     }
     traffic = None
@@ -156,11 +234,16 @@ def main():
             traffic = tr.get("bytes_per_launch")
     out["roofline"] = {"bound": "hbm", "achieved": round(gbps, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                        "frac": round(gbps / HBM_PEAK_GBPS, 4), "traffic": traffic,
-                       "kernel": "k_fft_c32<11,4,256,-1>", "kernel_hash": khash,
+                       "kernel": kernel_name(desc), "kernel_hash": khash,
                        "algorithmic_bytes_per_launch": bytes_alg}
     out["headline_distribution"] = per_call_distribution(lambda: plan.execute(x, y), 50, torch)
     out["gflops_fwd_2048"] = round(gflops, 1)
     out["gbps_fwd_2048"] = round(gbps, 1)
+
+    if args.only_headline and args.with_copy:
+        for _ in range(args.steps):
+            torch.mul(x_all, 1.0, out=y_all)
+        torch.cuda.synchronize()
 
     if not args.only_headline:
         # ------------------------------------------------------------ copy ceiling
@@ -221,10 +304,14 @@ def main():
                 log(f"[bench] sweep {row}")
             out["sweep"] = sweep
 
+        # ------------------------------------------------------------ ragged
+        out["ragged"] = bench_ragged(api, synth, torch, dev, max(200, args.steps * 5))
+        log(f"[bench] ragged {out['ragged']}")
+
     # ---------------------------------------------------------------- cpu baseline
     if not args.no_cpu:
         log("[bench] timing the FP64 CPU oracle")
-        out["cpu_baseline"] = cpu_baseline(n)
+        out["cpu_baseline"] = cpu_baseline(n, batch)
         log(f"[bench] cpu {out['cpu_baseline']}")
     print(json.dumps(out), flush=True)
 

@@ -68,6 +68,51 @@ def tune_c32(total: int = 1 << 26, steps: int = 30, warmup: int = 5, log2ns=rang
     return best, record
 
 
+def tune_ragged(count: int = 4096, iters: int = 300, log=print):
+    """Per-length elements per thread and the workgroup size of the ragged
+    persistent kernel, by coordinate descent on one seeded ragged batch
+    (lengths 2^3..2^11), timing one launch per call."""
+    import numpy as np
+    import torch
+    from . import api, synth
+    from .native import MifftError
+    lengths = synth.ragged_lengths(synth.SEED_RAGGED, count, 3, 11)
+    off = synth.offsets_from_lengths(lengths)
+    x = torch.from_numpy(synth.uniform_complex(synth.SEED_RAGGED, (int(off[-1]),), key=(1,))).cuda()
+    y = torch.empty_like(x)
+
+    def cost(table, wg):
+        try:
+            p = api.RaggedPlan(off, -1, ept_by_log2n=table, wg=wg)
+        except MifftError:
+            return float("inf")
+        ms = min(_time(lambda: p.execute(x, y), iters, 20, torch) for _ in range(2))
+        p.close()
+        return ms
+
+    record, best = [], None
+    for wg in (64, 128, 256):
+        table = [0, 2, 4, 8, 4, 4, 4, 8, 8, 8, 16, 16]
+        cur = cost(table, wg)
+        for _ in range(2):
+            for L in range(3, 12):
+                for ept in (4, 8, 16):
+                    if ept > (1 << L) or ept == table[L]:
+                        continue
+                    trial = list(table)
+                    trial[L] = ept
+                    c = cost(trial, wg)
+                    if c < cur:
+                        cur, table = c, trial
+        rec = {"wg": wg, "ept_by_log2n": table, "us": round(cur * 1e3, 2)}
+        record.append(rec)
+        log(f"[tune-ragged] {rec}")
+        if best is None or cur < best[2]:
+            best = (wg, table, cur)
+    return {"wg": best[0], "ctas_per_cu": 0, "ept": {L: best[1][L] for L in range(1, 12) if best[1][L]},
+            "us": round(best[2] * 1e3, 2)}, record
+
+
 def write_table(path: str, best_c32: dict, ragged: dict | None = None):
     with open(path, "w") as f:
         f.write("# mifft tuned variants for gfx950 (written by paper_2203_09384_amd.tune)\n")
@@ -87,13 +132,18 @@ def main(argv=None):
     ap.add_argument("--json", default=None)
     ap.add_argument("--total-log2", type=int, default=26)
     ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--skip-c32", action="store_true")
+    ap.add_argument("--skip-ragged", action="store_true")
     args = ap.parse_args(argv)
-    best, rec = tune_c32(1 << args.total_log2, args.steps, log=lambda m: print(m, file=sys.stderr, flush=True))
-    write_table(args.out, best)
+    log = lambda m: print(m, file=sys.stderr, flush=True)
+    best, rec = ({}, []) if args.skip_c32 else tune_c32(1 << args.total_log2, args.steps, log=log)
+    rbest, rrec = (None, []) if args.skip_ragged else tune_ragged(log=log)
+    write_table(args.out, best, rbest)
     if args.json:
         with open(args.json, "w") as f:
-            json.dump({"c32": rec, "best": {L: best[L][:3] for L in best}}, f, indent=1)
-    print(json.dumps({L: best[L][:3] for L in best}))
+            json.dump({"c32": rec, "best": {L: best[L][:3] for L in best}, "ragged": rrec,
+                       "ragged_best": rbest}, f, indent=1)
+    print(json.dumps({"c32": {L: best[L][:3] for L in best}, "ragged": rbest}))
 
 
 if __name__ == "__main__":
