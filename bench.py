@@ -98,6 +98,26 @@ def cpu_baseline(n, batch, budget_s=12.0):
             "seconds": round(dt, 2)}
 
 
+def bench_half(api, synth, torch, dev, steps, ms_fp32, x_all):
+    """FP16 / BF16 block-floating-point forward FFT, N = 2048, batch 32768,
+    against the FP32 kernel at the same shape (ms_fp32)."""
+    n, batch = 2048, 32768
+    res = {"workload": "C2C forward FFT, N=2048, batch 32768, FP16/BF16 storage (4 B per element), "
+                       "per-transform int32 exponents, radix-16 passes on MFMA"}
+    for dt, tdt in (("c16", torch.float16), ("cbf16", torch.bfloat16)):
+        xh = torch.view_as_real(x_all.view(batch, n)).to(tdt).contiguous()
+        yh = torch.empty_like(xh)
+        ex = torch.empty(batch, dtype=torch.int32, device=dev)
+        p = api.Plan(n, batch, -1, dtype=dt)
+        m = time_launches(lambda: p.execute_scaled(xh, out=yh, out_exp=ex), steps, 20, torch)
+        alg = 8.0 * n * batch + 4.0 * batch
+        res[dt] = {"us": round(m * 1e3, 2), "GBps": round(alg / (m * 1e-3) / 1e9, 1),
+                   "GFLOPs": round(5.0 * n * 11 * batch / (m * 1e-3) / 1e9, 1),
+                   "speedup_vs_fp32": round(ms_fp32 / m, 3)}
+        del xh, yh
+    return res
+
+
 def bench_ragged(api, synth, torch, dev, iters):
     """One persistent launch over 4096 mixed-length transforms (eager and
     graph-replayed) against per-length plain launches (eager and in one
@@ -303,6 +323,10 @@ def main():
                 sweep.append(row)
                 log(f"[bench] sweep {row}")
             out["sweep"] = sweep
+
+        # ------------------------------------------------------------ FP16 / BF16
+        out["half"] = bench_half(api, synth, torch, dev, args.steps, ms, x_all)
+        log(f"[bench] half {out['half']}")
 
         # ------------------------------------------------------------ ragged
         out["ragged"] = bench_ragged(api, synth, torch, dev, max(200, args.steps * 5))

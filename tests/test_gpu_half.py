@@ -1,0 +1,126 @@
+"""FP16 / BF16 block-floating-point path (N = 2048, radix-16 passes on MFMA)
+against the FP64 oracle.
+
+The oracle transforms the stored half-precision input values (times
+2^in_exp) in FP64; the GPU output is de-scaled (stored * 2^out_exp) in FP64.
+Bar: per-transform relative L2 <= 3e-3 for each dtype and input class
+(uniform[-1,1) re/im; log-uniform magnitude 1e-3..1e3 with uniform phase).
+The error against the raw FP64 draw (which adds input quantisation) is
+printed as a second figure.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2203_09384_amd import api, synth
+from gpu_util import need_gpu
+
+pytestmark = pytest.mark.gpu
+N = 2048
+TOL = 3e-3
+TORCH = {"c16": torch.float16, "cbf16": torch.bfloat16}
+
+
+@pytest.fixture(autouse=True)
+def _gpu():
+    need_gpu()
+
+
+def draw(cls, batch, key=0):
+    if cls == "uniform":
+        return synth.uniform_complex(synth.SEED_HALF, (batch, N), key=(key, 0), dtype=np.complex128)
+    return synth.log_uniform_polar(synth.SEED_HALF, (batch, N), key=(key, 1))
+
+
+def to_half(x, dtype):
+    t = torch.from_numpy(np.stack([x.real, x.imag], -1).astype(np.float32)).to(TORCH[dtype])
+    return t.cuda().contiguous()
+
+
+def from_half(t, exps=None):
+    a = t.float().cpu().numpy().astype(np.float64)
+    z = a[..., 0] + 1j * a[..., 1]
+    if exps is not None:
+        z = z * np.exp2(exps.cpu().numpy().astype(np.float64))[:, None]
+    return z
+
+
+def rel(y, ref):
+    return float(np.max(np.linalg.norm(y - ref, axis=-1) / np.linalg.norm(ref, axis=-1)))
+
+
+@pytest.mark.parametrize("dtype", ["c16", "cbf16"])
+@pytest.mark.parametrize("cls", ["uniform", "loguniform"])
+@pytest.mark.parametrize("sign", [-1, 1])
+def test_parity_small_batch(dtype, cls, sign):
+    batch = 257
+    x = draw(cls, batch)
+    xh = to_half(x, dtype)
+    p = api.Plan(N, batch, sign, dtype=dtype)
+    print(f"[case] half {dtype} {cls} sign={sign} {p.describe()}", flush=True)
+    yh, ex = p.execute_scaled(xh)
+    torch.cuda.synchronize()
+    y = from_half(yh, ex)
+    xs = from_half(xh)
+    ref = oracle.forward(xs) if sign < 0 else oracle.inverse(xs)
+    ref_raw = oracle.forward(x) if sign < 0 else oracle.inverse(x)
+    e, e_raw = rel(y, ref), rel(y, ref_raw)
+    print(f"{dtype} {cls} sign={sign}: vs stored input {e:.3e}, vs raw draw {e_raw:.3e}")
+    assert np.all(np.isfinite(y))
+    assert e <= TOL
+
+
+@pytest.mark.parametrize("dtype", ["c16", "cbf16"])
+@pytest.mark.parametrize("cls", ["uniform", "loguniform"])
+def test_full_size_sampled(dtype, cls):
+    """The reduced-precision workload of record: N=2048, batch 32768."""
+    batch = 32768
+    x = draw(cls, batch, key=1)
+    xh = to_half(x, dtype)
+    del x
+    p = api.Plan(N, batch, -1, dtype=dtype)
+    print(f"[case] half full {dtype} {cls}", flush=True)
+    yh, ex = p.execute_scaled(xh)
+    torch.cuda.synchronize()
+    assert bool(torch.isfinite(yh.float()).all())
+    rng = np.random.default_rng(5)
+    idx = np.unique(np.concatenate([[0, batch - 1], rng.integers(0, batch, 62)]))
+    it = torch.from_numpy(idx).cuda()
+    y = from_half(yh[it], ex[it])
+    xs = from_half(xh[it])
+    e = rel(y, oracle.forward(xs))
+    print(f"full {dtype} {cls}: sampled max rel L2 {e:.3e}")
+    assert e <= TOL
+    # exponents: the stored output's largest component lies in [2^-1, 2^15)
+    mx = yh.float().abs().amax(dim=(1, 2))
+    assert float(mx.max()) < 2.0 ** 15 and float(mx.min()) >= 0.5
+
+
+@pytest.mark.parametrize("dtype", ["c16", "cbf16"])
+def test_input_exponent_is_exact(dtype):
+    """Scaling the input by 2^k per transform changes only the exponent."""
+    batch = 64
+    xh = to_half(draw("uniform", batch, key=2), dtype)
+    p = api.Plan(N, batch, -1, dtype=dtype)
+    y0, e0 = p.execute_scaled(xh)
+    k = torch.from_numpy(np.random.default_rng(0).integers(-20, 20, batch).astype(np.int32)).cuda()
+    y1, e1 = p.execute_scaled(xh, in_exp=k)
+    torch.cuda.synchronize()
+    assert torch.equal(y0, y1)
+    assert torch.equal(e1, e0 + k)
+
+
+@pytest.mark.parametrize("dtype", ["c16", "cbf16"])
+def test_unit_scale_execute_and_determinism(dtype):
+    batch = 32
+    x = 1e-2 * draw("uniform", batch, key=3)
+    xh = to_half(x, dtype)
+    p = api.Plan(N, batch, -1, dtype=dtype)
+    out = p.execute(xh)  # unit-scale output, no exponent array
+    y, ex = p.execute_scaled(xh)
+    y2, _ = p.execute_scaled(xh)
+    torch.cuda.synchronize()
+    assert torch.equal(y, y2)
+    ref = oracle.forward(from_half(xh))
+    assert rel(from_half(out), ref) <= TOL
