@@ -25,6 +25,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "device_fft.hpp"
 #include "half.hpp"
 
@@ -38,46 +40,36 @@ typedef uint32_t v4u __attribute__((ext_vector_type(4)));
 
 constexpr int HN = 2048;
 constexpr int HWG = 256;
-// LDS planes: index i -> i + 16 (i >> 10); the imaginary plane starts 32
-// banks after the real one, so the four 16-lane groups of an MFMA operand
-// gather hit disjoint banks.
-constexpr int PLANE = HN + 16 + 16;
-constexpr int IM_OFF = PLANE + 32 - (PLANE % 64);
 
-__device__ __forceinline__ int hp(int i) { return i + ((i >> 10) << 4); }
+// LDS layouts, one per exchange, each conflict-free for both its writer and
+// its reader and affine in the per-instruction indices (so every access is
+// a per-thread base plus an immediate offset).  Real and imaginary parts
+// are separate planes; IM_* is the imaginary plane's offset.
+//   A -> B : d + (d >> 6)
+//   B -> C : d + 8 (d >> 6) + 16 (d >> 10)
+//   C -> store : d + (d >> 6) + 4 (d >> 8)
+__device__ __forceinline__ int fA(int d) { return d + (d >> 6); }
+__device__ __forceinline__ int fB(int d) { return d + 8 * (d >> 6) + 16 * (d >> 10); }
+__device__ __forceinline__ int fC(int d) { return d + (d >> 6) + 4 * (d >> 8); }
+constexpr int IM_A = 2080, IM_B = 2336, IM_C = 2112;
+constexpr int BUF = 2 * IM_B;  // floats per buffer (largest layout)
 
-// ---- conversions (round to nearest even) ----
-__device__ __forceinline__ uint16_t f32_to_bf16_bits(float f)
-{
-    uint32_t u = __builtin_bit_cast(uint32_t, f);
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
-}
-__device__ __forceinline__ float bf16_bits_to_f32(uint16_t h)
-{
-    return __builtin_bit_cast(float, (uint32_t)h << 16);
-}
-__device__ __forceinline__ uint16_t f32_to_f16_bits(float f)
-{
-    return __builtin_bit_cast(uint16_t, (_Float16)f);
-}
-__device__ __forceinline__ float f16_bits_to_f32(uint16_t h) { return (float)__builtin_bit_cast(_Float16, h); }
-
+// ---- conversions (round to nearest even)
 template <bool BF>
 __device__ __forceinline__ float to_f32(uint16_t h)
 {
     if constexpr (BF)
-        return bf16_bits_to_f32(h);
+        return __builtin_bit_cast(float, (uint32_t)h << 16);
     else
-        return f16_bits_to_f32(h);
+        return (float)__builtin_bit_cast(_Float16, h);
 }
 template <bool BF>
 __device__ __forceinline__ uint16_t from_f32(float f)
 {
     if constexpr (BF)
-        return f32_to_bf16_bits(f);
+        return __builtin_bit_cast(uint16_t, (__bf16)f);
     else
-        return f32_to_f16_bits(f);
+        return __builtin_bit_cast(uint16_t, (_Float16)f);
 }
 
 // MFMA operand of 8 values (hi part, and for BF16 the lo remainder).
@@ -93,9 +85,9 @@ struct Op8<true> {
     v8bf hi, lo;
     __device__ __forceinline__ void set(int i, float x)
     {
-        const uint16_t h = f32_to_bf16_bits(x);
-        hi[i] = __builtin_bit_cast(__bf16, h);
-        lo[i] = __builtin_bit_cast(__bf16, f32_to_bf16_bits(x - bf16_bits_to_f32(h)));
+        const __bf16 h = (__bf16)x;
+        hi[i] = h;
+        lo[i] = (__bf16)(x - (float)h);
     }
 };
 
@@ -121,38 +113,29 @@ __device__ __forceinline__ void dft16_operands(Op8<BF>& are, Op8<BF>& aim, int l
     for (int i = 0; i < 8; i++) {
         const int r = (kq & 1) * 8 + i;
         const int e = (m * r) & 15;
-        const float c = kCos16[e], s = (float)S * kSin16[e];
+        // cos / sin of 2 pi e / 16 from the first quadrant by symmetry
+        const int q = e & 3, quad = e >> 2;
+        const float c0 = q == 0 ? 1.0f : (q == 1 ? kCos16[1] : (q == 2 ? kCos16[2] : kCos16[3]));
+        const float s0 = q == 0 ? 0.0f : (q == 1 ? kSin16[1] : (q == 2 ? kSin16[2] : kSin16[3]));
+        float c = c0, sn = s0;
+        if (quad == 1) {
+            c = -s0;
+            sn = c0;
+        } else if (quad == 2) {
+            c = -c0;
+            sn = -s0;
+        } else if (quad == 3) {
+            c = s0;
+            sn = -c0;
+        }
+        sn *= (float)S;
         if (kq < 2) {
             are.set(i, c);
-            aim.set(i, s);
+            aim.set(i, sn);
         } else {
-            are.set(i, -s);
+            are.set(i, -sn);
             aim.set(i, c);
         }
-    }
-}
-
-// One radix-16 pass on MFMA over the 128 butterflies of the transform in
-// LDS (butterfly j reads x[j + 128 r], r < 16).  Wave w handles butterfly
-// groups 2w and 2w+1 (16 butterflies each).  Returns, per group, the lane's
-// 4 outputs Y[m], m = 4 (lane / 16) + i, of butterfly j = 16 g + lane % 16.
-template <bool BF>
-__device__ __forceinline__ void mfma_pass(const float* lds, const Op8<BF>& are, const Op8<BF>& aim, int wave,
-                                          int lane, v4f (&yre)[2], v4f (&yim)[2])
-{
-    const int n = lane & 15, kq = lane >> 4;
-    const float* plane = lds + ((kq >> 1) ? IM_OFF : 0);
-    const int r0 = (kq & 1) * 8;
-#pragma unroll
-    for (int gg = 0; gg < 2; gg++) {
-        const int j = 16 * (2 * wave + gg) + n;
-        Op8<BF> b;
-#pragma unroll
-        for (int i = 0; i < 8; i++)
-            b.set(i, plane[hp(j + 128 * (r0 + i))]);
-        const v4f z = {0.f, 0.f, 0.f, 0.f};
-        yre[gg] = mfma(are, b, z);
-        yim[gg] = mfma(aim, b, z);
     }
 }
 
@@ -165,124 +148,203 @@ __device__ __forceinline__ cf tw_at(const cf* __restrict__ tw, int idx)
     return w;
 }
 
+template <bool BF>
+__device__ __forceinline__ void unpack8(const uint32_t (&u)[8], cf (&v)[8])
+{
+#pragma unroll
+    for (int m = 0; m < 8; m++)
+        v[m] = cf{to_f32<BF>((uint16_t)(u[m] & 0xffffu)), to_f32<BF>((uint16_t)(u[m] >> 16))};
+}
+
+// Persistent: workgroup walks transforms blockIdx.x, + gridDim.x, ...;
+// the next transform's input is loaded while the current one is computed.
+// LDS buffers X and Y alternate: A->B and C->store use one, B->C the other.
 template <int S, bool BF>
 __global__ __launch_bounds__(HWG) void k_fft_half_2048(const uint32_t* __restrict__ in,
                                                        const int32_t* __restrict__ in_exp,
                                                        uint32_t* __restrict__ out, int32_t* __restrict__ out_exp,
-                                                       const cf* __restrict__ tw, int scale_log2)
+                                                       const cf* __restrict__ tw, int64_t batch, int scale_log2)
 {
-    __shared__ float lds[IM_OFF + PLANE];
-    __shared__ float s_red[HWG / 64];
+    __shared__ float lds[2 * BUF];
+    __shared__ float s_red[2][HWG / 64];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int64_t b = blockIdx.x;
+    const int n = lane & 15, kq = lane >> 4;
+    int64_t b = blockIdx.x;
+    if (b >= batch)
+        return;
 
-    // ---- load: thread t holds x[t + 256 m], m < 8 (4-byte pairs, coalesced)
-    const uint32_t* src = in + b * HN;
-    cf v[8];
-    float mx = 0.f;
-#pragma unroll
-    for (int m = 0; m < 8; m++) {
-        const uint32_t u = src[tid + 256 * m];
-        v[m] = cf{to_f32<BF>((uint16_t)(u & 0xffffu)), to_f32<BF>((uint16_t)(u >> 16))};
-        mx = fmaxf(mx, fmaxf(fabsf(v[m].x), fabsf(v[m].y)));
-    }
-    // ---- block maximum -> power-of-two scale (largest component in [8, 16))
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1)
-        mx = fmaxf(mx, __shfl_xor(mx, off));
-    if (lane == 0)
-        s_red[wave] = mx;
-    __syncthreads();
-    mx = fmaxf(fmaxf(s_red[0], s_red[1]), fmaxf(s_red[2], s_red[3]));
-    int e_max = 0;
-    if (mx > 0.f && mx <= 3.4e38f)
-        (void)frexpf(mx, &e_max);  // mx < 2^e_max
-    const float sc = ldexpf(1.0f, 4 - e_max);
-    const int e_in = in_exp ? in_exp[b] : 0;
-    const int e_out = e_in + e_max - 4 + scale_log2;
-
-    // ---- pass A: radix 8 on VALU, FP32; outputs to LDS with pass B's twiddles
-#pragma unroll
-    for (int m = 0; m < 8; m++)
-        v[m] = cscale(v[m], sc);
-    dft8<S>(v);
-#pragma unroll
-    for (int r = 0; r < 8; r++) {
-        const int d = tid * 8 + r;               // Stockham destination, NS = 1, R = 8
-        const int jb = d & 127, rb = d >> 7;     // pass B: d = j + 128 r, k = j mod 8
-        const cf w = tw_at<S>(tw, (rb * (jb & 7)) << 4);
-        const cf y = cmul(v[r], w);
-        lds[hp(d)] = y.x;
-        lds[IM_OFF + hp(d)] = y.y;
-    }
-    __syncthreads();
-
+    // ---- per-thread constants, hoisted out of the transform loop
     Op8<BF> are, aim;
     dft16_operands<S, BF>(are, aim, lane);
-    const int n = lane & 15, kq = lane >> 4;
-    v4f yre[2], yim[2];
-
-    // ---- pass B: radix 16 on MFMA (NS = 8); outputs with pass C's twiddles
-    mfma_pass<BF>(lds, are, aim, wave, lane, yre, yim);
-    __syncthreads();
+    cf twA[8];  // pass B twiddle of pass A output r: w_128^{(tid >> 4) r}
+#pragma unroll
+    for (int r = 0; r < 8; r++)
+        twA[r] = tw_at<S>(tw, ((tid >> 4) * r) << 4);
+    cf twB[2][4];  // pass C twiddle of pass B output (gg, i): w_2048^{(j >> 3) ((j & 7) + 8 m)}
 #pragma unroll
     for (int gg = 0; gg < 2; gg++) {
         const int j = 16 * (2 * wave + gg) + n;
 #pragma unroll
-        for (int i = 0; i < 4; i++) {
-            const int m = 4 * kq + i;
-            const int d = ((j >> 3) << 7) + (j & 7) + 8 * m;  // Stockham destination, NS = 8
-            const int jc = d & 127, rc = d >> 7;              // pass C: d = j + 128 r, k = j
-            const cf w = tw_at<S>(tw, rc * jc);
-            const cf y = cmul(cf{yre[gg][i], yim[gg][i]}, w);
-            lds[hp(d)] = y.x;
-            lds[IM_OFF + hp(d)] = y.y;
-        }
+        for (int i = 0; i < 4; i++)
+            twB[gg][i] = tw_at<S>(tw, (j >> 3) * ((j & 7) + 8 * (4 * kq + i)));
     }
-    __syncthreads();
-
-    // ---- pass C: radix 16 on MFMA (NS = 128); natural-order outputs
-    mfma_pass<BF>(lds, are, aim, wave, lane, yre, yim);
-    __syncthreads();
+    const int oWA = fA(8 * tid);
+    const int r0 = (kq & 1) * 8;
+    int oRB[2], oWB[2], oRC[2], oWC[2];
 #pragma unroll
     for (int gg = 0; gg < 2; gg++) {
         const int j = 16 * (2 * wave + gg) + n;
-#pragma unroll
-        for (int i = 0; i < 4; i++) {
-            const int d = j + 128 * (4 * kq + i);
-            lds[hp(d)] = yre[gg][i];
-            lds[IM_OFF + hp(d)] = yim[gg][i];
-        }
+        oRB[gg] = ((kq >> 1) ? IM_A : 0) + fA(j + 128 * r0);
+        oWB[gg] = fB(((j >> 3) << 7) + (j & 7) + 32 * kq);
+        oRC[gg] = ((kq >> 1) ? IM_B : 0) + fB(j + 128 * r0);
+        oWC[gg] = fC(j + 512 * kq);
     }
-    __syncthreads();
+    const int oRS0 = fC(4 * tid), oRS1 = fC(4 * (tid + HWG));
+    constexpr int dWC[4] = {0, 130, 264, 394};  // fC(d0 + 128 i) - fC(d0)
 
-    // ---- store: 4 consecutive elements (16 bytes) per lane and instruction
-    const float osc = out_exp ? 1.0f : ldexpf(1.0f, e_out);
-    v4u* dst = reinterpret_cast<v4u*>(out + b * HN);
+    uint32_t cur[8], nxt[8];
+    {
+        const uint32_t* src = in + b * HN;
 #pragma unroll
-    for (int h = 0; h < 2; h++) {
-        const int q = tid + HWG * h;  // 16-byte chunk index, 512 per transform
-        v4u o;
-#pragma unroll
-        for (int i = 0; i < 4; i++) {
-            const int d = 4 * q + i;
-            const float re = lds[hp(d)] * osc, im = lds[IM_OFF + hp(d)] * osc;
-            o[i] = (uint32_t)from_f32<BF>(re) | ((uint32_t)from_f32<BF>(im) << 16);
-        }
-        dst[q] = o;
+        for (int m = 0; m < 8; m++)
+            cur[m] = __builtin_nontemporal_load(src + tid + 256 * m);
     }
-    if (out_exp && tid == 0)
-        out_exp[b] = e_out;
+    int it = 0;
+    while (true) {
+        const int64_t b1 = b + gridDim.x;
+        if (b1 < batch) {
+            const uint32_t* src = in + b1 * HN;
+#pragma unroll
+            for (int m = 0; m < 8; m++)
+                nxt[m] = __builtin_nontemporal_load(src + tid + 256 * m);
+        }
+        float* X = lds + (it & 1) * BUF;
+        float* Y = lds + ((it & 1) ^ 1) * BUF;
+        float* red = s_red[it & 1];
+
+        // ---- pass A: radix 8 on VALU in FP32 over x[tid + 256 m]
+        cf v[8];
+        unpack8<BF>(cur, v);
+        float mx = 0.f;
+#pragma unroll
+        for (int m = 0; m < 8; m++)
+            mx = fmaxf(mx, fmaxf(fabsf(v[m].x), fabsf(v[m].y)));
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1)
+            mx = fmaxf(mx, __shfl_xor(mx, off));
+        if (lane == 0)
+            red[wave] = mx;
+        dft8<S>(v);
+        // outputs to the Stockham position d = 8 tid + r, times pass B's twiddle
+        float* wa = X + oWA;
+#pragma unroll
+        for (int r = 0; r < 8; r++) {
+            const cf y = cmul(v[r], twA[r]);
+            wa[r] = y.x;
+            wa[IM_A + r] = y.y;
+        }
+        __syncthreads();
+
+        // ---- block maximum -> power-of-two scale (largest input component in [8, 16))
+        mx = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+        int e_max = 0;
+        if (mx > 0.f && mx <= 3.4e38f)
+            (void)frexpf(mx, &e_max);  // mx < 2^e_max
+        const float sc = ldexpf(1.0f, 4 - e_max);
+        const int e_in = in_exp ? in_exp[b] : 0;
+        const int e_out = e_in + e_max - 4 + scale_log2;
+
+        // ---- pass B: radix 16 on MFMA (NS = 8); butterfly j reads x[j + 128 r]
+        v4f yre[2], yim[2];
+#pragma unroll
+        for (int gg = 0; gg < 2; gg++) {
+            const float* rb = X + oRB[gg];
+            Op8<BF> bo;
+#pragma unroll
+            for (int i = 0; i < 8; i++)
+                bo.set(i, rb[130 * i] * sc);
+            const v4f z = {0.f, 0.f, 0.f, 0.f};
+            yre[gg] = mfma(are, bo, z);
+            yim[gg] = mfma(aim, bo, z);
+        }
+        // outputs to d = ((j >> 3) << 7) + (j & 7) + 8 m, times pass C's twiddle
+#pragma unroll
+        for (int gg = 0; gg < 2; gg++) {
+            float* wb = Y + oWB[gg];
+#pragma unroll
+            for (int i = 0; i < 4; i++) {
+                const cf y = cmul(cf{yre[gg][i], yim[gg][i]}, twB[gg][i]);
+                wb[8 * i] = y.x;
+                wb[IM_B + 8 * i] = y.y;
+            }
+        }
+        __syncthreads();
+
+        // ---- pass C: radix 16 on MFMA (NS = 128); natural-order outputs d = j + 128 m
+#pragma unroll
+        for (int gg = 0; gg < 2; gg++) {
+            const float* rc = Y + oRC[gg];
+            Op8<BF> bo;
+#pragma unroll
+            for (int i = 0; i < 8; i++)
+                bo.set(i, rc[144 * i]);
+            const v4f z = {0.f, 0.f, 0.f, 0.f};
+            yre[gg] = mfma(are, bo, z);
+            yim[gg] = mfma(aim, bo, z);
+        }
+#pragma unroll
+        for (int gg = 0; gg < 2; gg++) {
+            float* wc = X + oWC[gg];
+#pragma unroll
+            for (int i = 0; i < 4; i++) {
+                wc[dWC[i]] = yre[gg][i];
+                wc[IM_C + dWC[i]] = yim[gg][i];
+            }
+        }
+        __syncthreads();
+
+        // ---- store: 4 consecutive elements (16 bytes) per lane and instruction
+        const float osc = out_exp ? 1.0f : ldexpf(1.0f, e_out);
+        v4u* dst = reinterpret_cast<v4u*>(out + b * HN);
+#pragma unroll
+        for (int h = 0; h < 2; h++) {
+            const float* rs = X + (h ? oRS1 : oRS0);
+            v4u o;
+#pragma unroll
+            for (int i = 0; i < 4; i++)
+                o[i] = (uint32_t)from_f32<BF>(rs[i] * osc) | ((uint32_t)from_f32<BF>(rs[IM_C + i] * osc) << 16);
+            __builtin_nontemporal_store(o, dst + tid + HWG * h);
+        }
+        if (out_exp && tid == 0)
+            out_exp[b] = e_out;
+        if (b1 >= batch)
+            break;
+#pragma unroll
+        for (int m = 0; m < 8; m++)
+            cur[m] = nxt[m];
+        b = b1;
+        it++;
+    }
 }
 
 template <int S, bool BF>
 hipError_t launch_half(const void* in, const int32_t* in_exp, void* out, int32_t* out_exp, const void* tw,
-                       int64_t batch, int scale_log2, hipStream_t stream)
+                       int64_t batch, int scale_log2, int64_t grid_limit, hipStream_t stream)
 {
-    hipLaunchKernelGGL((k_fft_half_2048<S, BF>), dim3((unsigned)batch), dim3(HWG), 0, stream,
+    const int64_t grid = grid_limit > 0 && batch > grid_limit ? grid_limit : batch;
+    hipLaunchKernelGGL((k_fft_half_2048<S, BF>), dim3((unsigned)grid), dim3(HWG), 0, stream,
                        static_cast<const uint32_t*>(in), in_exp, static_cast<uint32_t*>(out), out_exp,
-                       static_cast<const cf*>(tw), scale_log2);
+                       static_cast<const cf*>(tw), batch, scale_log2);
     return hipGetLastError();
+}
+
+template <int S, bool BF>
+int occupancy_half()
+{
+    int blocks = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_fft_half_2048<S, BF>, HWG, 0) != hipSuccess)
+        return 0;
+    return blocks;
 }
 
 thread_local char g_hmsg[256] = "";
@@ -292,6 +354,7 @@ thread_local char g_hmsg[256] = "";
 struct HalfPlan {
     int64_t n = 0, batch = 0;
     int dtype = FFT_C16;
+    int64_t grid_limit = 0;  // CUs x resident workgroups
 };
 
 bool half_supported(int64_t n) { return n == HN; }
@@ -313,6 +376,16 @@ int half_create(HalfPlan** out, int64_t n, int64_t batch, int dtype)
     hp->n = n;
     hp->batch = batch;
     hp->dtype = dtype;
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+        snprintf(g_hmsg, sizeof g_hmsg, "cannot query the device's compute units");
+        delete hp;
+        return FFT_EHIP;
+    }
+    const int occ = dtype == FFT_CBF16 ? std::min(occupancy_half<-1, true>(), occupancy_half<1, true>())
+                                       : std::min(occupancy_half<-1, false>(), occupancy_half<1, false>());
+    hp->grid_limit = (int64_t)cus * std::max(occ, 1);
     *out = hp;
     return FFT_OK;
 }
@@ -324,11 +397,11 @@ int half_execute(HalfPlan* hp, const void* in, const int32_t* in_exp, void* out,
     hipError_t e;
     const bool bf = hp->dtype == FFT_CBF16;
     if (sign < 0)
-        e = bf ? launch_half<-1, true>(in, in_exp, out, out_exp, tw, hp->batch, sl, stream)
-               : launch_half<-1, false>(in, in_exp, out, out_exp, tw, hp->batch, sl, stream);
+        e = bf ? launch_half<-1, true>(in, in_exp, out, out_exp, tw, hp->batch, sl, hp->grid_limit, stream)
+               : launch_half<-1, false>(in, in_exp, out, out_exp, tw, hp->batch, sl, hp->grid_limit, stream);
     else
-        e = bf ? launch_half<+1, true>(in, in_exp, out, out_exp, tw, hp->batch, sl, stream)
-               : launch_half<+1, false>(in, in_exp, out, out_exp, tw, hp->batch, sl, stream);
+        e = bf ? launch_half<+1, true>(in, in_exp, out, out_exp, tw, hp->batch, sl, hp->grid_limit, stream)
+               : launch_half<+1, false>(in, in_exp, out, out_exp, tw, hp->batch, sl, hp->grid_limit, stream);
     if (e != hipSuccess) {
         snprintf(g_hmsg, sizeof g_hmsg, "half-precision kernel launch: %s", hipGetErrorString(e));
         return FFT_EHIP;
@@ -350,11 +423,16 @@ void half_query(int64_t n, int64_t batch, fft_plan_desc* d)
     d->radices[0] = 8;
     d->radices[1] = 16;
     d->radices[2] = 16;
-    d->lds_bytes = (int)((IM_OFF + PLANE + HWG / 64) * sizeof(float));
+    d->lds_bytes = (int)((2 * BUF + 2 * HWG / 64) * sizeof(float));
     d->kind = 0;
     d->variant = 0;
 }
 
-void half_describe(const HalfPlan* hp, fft_plan_desc* d) { half_query(hp->n, hp->batch, d); }
+void half_describe(const HalfPlan* hp, fft_plan_desc* d)
+{
+    half_query(hp->n, hp->batch, d);
+    if (hp->grid_limit > 0 && d->grid > hp->grid_limit)
+        d->grid = hp->grid_limit;
+}
 
 }  // namespace mifft
