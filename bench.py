@@ -293,12 +293,23 @@ def main():
             loss = (w * (yy.real ** 2 + yy.imag ** 2)).sum()
             loss.backward()
         ms_step = time_launches(step, max(20, args.steps // 5), 3, torch)
+        lossv = torch.empty(nb, dtype=torch.float32, device=dev)
+        ms_fused = time_launches(lambda: pa.loss_grad(xa, w, za, lossv), args.steps, args.warmup, torch)
+
+        def fused_step():
+            xg.grad = None
+            api.weighted_power_loss(xg, w).backward()
+        ms_fused_step = time_launches(fused_step, max(20, args.steps // 5), 3, torch)
         out["fwd_adjoint"] = {
             "workload": "N=2048 batch 16384 (256 MiB per pass)",
             "fwd_ms": round(ms_f, 5), "fwd_GBps": round(b1 / (ms_f * 1e-3) / 1e9, 1),
             "fwd_adj_ms": round(ms_fa, 5), "fwd_adj_GBps": round(2 * b1 / (ms_fa * 1e-3) / 1e9, 1),
             "ratio_fwd_adj_over_fwd": round(ms_fa / ms_f, 3),
             "autograd_step_ms": round(ms_step, 5),
+            "fused_loss_grad_ms": round(ms_fused, 5),
+            "fused_loss_grad_GBps": round((20.0 * nb * n + 4.0 * nb) / (ms_fused * 1e-3) / 1e9, 1),
+            "fused_autograd_step_ms": round(ms_fused_step, 5),
+            "note": "fused: loss[b] = sum w|Fx|^2 and grad = F^H(2w Fx) in one kernel, 20 B per element",
         }
         log(f"[bench] fwd+adj {out['fwd_adjoint']}")
         del xg, w

@@ -171,6 +171,20 @@ int fft_execute_adjoint(fft_plan p, const void *in, void *out, void *stream);
 int fft_execute_scaled(fft_plan p, const void *in, const int32_t *in_exp, void *out,
                        int32_t *out_exp, void *stream);
 
+/*
+ * Fused weighted spectral power loss and its gradient, for batched FFT_C32
+ * plans.  With A the plan's transform (sign and scale as created) and w a
+ * device float32 array laid out like the transforms (n*batch values, w >= 0
+ * in the intended use):
+ *   loss[b] = sum_k w[b,k] |(A x_b)_k|^2          (device float32[batch])
+ *   grad_b  = A^H (2 w_b (A x_b))                  (device, like x)
+ * grad is the gradient of sum_b loss[b] with respect to x in PyTorch's
+ * complex convention (dL/dRe x + i dL/dIm x).  One pass: x and w are read
+ * once and grad written once.  x and grad must not overlap, nor w/loss
+ * overlap grad.  Used by the differentiable loss of the Python binding.
+ */
+int fft_execute_loss_grad(fft_plan p, const void *x, const float *w, void *grad, float *loss, void *stream);
+
 /* Free the plan and its device memory.  NULL is a no-op.  The caller must
  * make sure no execute of this plan is still in flight. */
 void fft_plan_destroy(fft_plan p);

@@ -7,7 +7,8 @@ the first plan does, and it raises if the library has not been built.
 
 
 def __getattr__(name):
-    if name in ("Plan", "RaggedPlan", "fft", "ifft", "FFTFn", "fft_differentiable", "query", "get_plan"):
+    if name in ("Plan", "RaggedPlan", "fft", "ifft", "FFTFn", "fft_differentiable", "query", "get_plan",
+                "weighted_power_loss", "WeightedPowerLossFn"):
         from . import api
         return getattr(api, name)
     raise AttributeError(name)

@@ -104,6 +104,22 @@ class Plan:
                                        _ptr(out), _ptr(out_exp), _stream_handle(stream)))
         return out, out_exp
 
+    def loss_grad(self, x, w, grad=None, loss=None, stream=None):
+        """Fused loss[b] = sum_k w |(A x_b)_k|^2 and grad = A^H (2 w A x) (FP32 plans)."""
+        self._check_tensor(x, "input")
+        if w.dtype != torch.float32 or not w.is_cuda or not w.is_contiguous() or w.numel() != x.numel():
+            raise ValueError("w must be a contiguous float32 GPU tensor shaped like x")
+        if grad is None:
+            grad = torch.empty_like(x)
+        self._check_tensor(grad, "grad")
+        if loss is None:
+            loss = torch.empty(self.batch, dtype=torch.float32, device=x.device)
+        if loss.dtype != torch.float32 or loss.numel() != self.batch or not loss.is_contiguous():
+            raise ValueError(f"loss must be a contiguous float32 tensor of {self.batch} values")
+        check(lib().fft_execute_loss_grad(self._h, _ptr(x), _ptr(w), _ptr(grad), _ptr(loss),
+                                          _stream_handle(stream)))
+        return loss, grad
+
     def describe(self) -> dict:
         d = native.PlanDesc()
         check(lib().fft_plan_describe(self._h, ctypes.byref(d)))
@@ -253,3 +269,28 @@ class FFTFn(torch.autograd.Function):
 
 def fft_differentiable(x, sign: int = -1):
     return FFTFn.apply(x, sign)
+
+
+class WeightedPowerLossFn(torch.autograd.Function):
+    """L = sum_b sum_k w |(A x_b)_k|^2 in one fused kernel that also produces
+    dL/dx = A^H (2 w A x) (PyTorch's complex convention); backward scales the
+    saved gradient by the incoming scalar.  w is treated as a constant."""
+
+    @staticmethod
+    def forward(ctx, x, w, sign: int = -1):
+        x = x.contiguous()
+        w = w.contiguous()
+        n = x.shape[-1]
+        plan = get_plan(n, x.numel() // n, sign, "c32", x.device.index)
+        loss, grad = plan.loss_grad(x, w)
+        ctx.save_for_backward(grad)
+        return loss.sum()
+
+    @staticmethod
+    def backward(ctx, g):
+        (grad,) = ctx.saved_tensors
+        return grad * g.to(grad.real.dtype), None, None
+
+
+def weighted_power_loss(x, w, sign: int = -1):
+    return WeightedPowerLossFn.apply(x, w, sign)

@@ -16,6 +16,7 @@
 #include <vector>
 
 #include "../../include/mifft.h"
+#include "fused_loss.hpp"
 #include "half.hpp"
 #include "ragged.hpp"
 #include "registry.hpp"
@@ -81,6 +82,19 @@ const KernelC32* find_c32(int log2n, int log2ept, int wg, int sign, int kind)
     return nullptr;
 }
 int count_c32() { return (int)c32_reg().size(); }
+static std::vector<KernelLossGrad>& lg_reg()
+{
+    static std::vector<KernelLossGrad> r;
+    return r;
+}
+void register_loss_grad(const KernelLossGrad& k) { lg_reg().push_back(k); }
+const KernelLossGrad* find_loss_grad(int log2n, int log2ept, int wg, int sign)
+{
+    for (const auto& k : lg_reg())
+        if (k.log2n == log2n && k.log2ept == log2ept && k.wg == wg && k.sign == sign)
+            return &k;
+    return nullptr;
+}
 const KernelC32* c32_at(int i) { return (i >= 0 && i < count_c32()) ? &c32_reg()[i] : nullptr; }
 }  // namespace mifft
 
@@ -176,6 +190,9 @@ struct mifft_plan_s {
     void* tw = nullptr;              // device FP32 twiddle table (2048 entries)
     void* rows = nullptr;            // per-pass twiddle rows (kind >= 1)
     int64_t grid_limit = 0;          // persistent kinds: CUs x workgroups per CU
+    const KernelLossGrad* lossgrad = nullptr;  // fused loss + gradient kernel (FP32)
+    void* lg_rows = nullptr;         // its twiddle rows when they differ from `rows`
+    int64_t lg_grid_limit = 0;
     int64_t total = 0;               // elements per execute (either kind)
     RaggedPlan* ragged = nullptr;
     HalfPlan* half = nullptr;
@@ -284,6 +301,40 @@ int make_rows(mifft_plan_s* p)
     return FFT_OK;
 }
 
+// The fused loss-gradient kernel of a batched FP32 plan: the plan's own
+// (EPT, WG) when compiled, else the first compiled one; its twiddle rows are
+// shared with the plan's when the schedules agree.
+int make_loss_grad(mifft_plan_s* p)
+{
+    const KernelLossGrad* k = find_loss_grad(p->log2n, p->var.log2ept, p->var.wg, p->sign);
+    for (int e = 4; e >= 1 && !k; e--)
+        for (int wg : {256, 128, 64})
+            if (!k)
+                k = find_loss_grad(p->log2n, e, wg, p->sign);
+    if (!k)
+        return set_err(FFT_EINVAL_CONFIG, "no fused loss kernel for n=%lld", (long long)p->n);
+    p->lossgrad = k;
+    if (k->rows > 0 && !(p->rows && p->fwd->log2ept == k->log2ept)) {
+        hipError_t e = hipMalloc(&p->lg_rows, (size_t)k->rows * sizeof(float2));
+        if (e != hipSuccess) {
+            p->lg_rows = nullptr;
+            return e == hipErrorOutOfMemory ? set_err(FFT_ENOMEM, "hipMalloc(loss rows) failed")
+                                            : hip_err(e, "hipMalloc(loss rows)");
+        }
+        e = launch_twiddle_rows(p->tw, p->lg_rows, k->log2n, k->log2ept, k->rows, nullptr);
+        if (e == hipSuccess)
+            e = hipStreamSynchronize(nullptr);
+        if (e != hipSuccess)
+            return hip_err(e, "loss twiddle rows");
+    }
+    int cus = 0;
+    hipError_t e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device);
+    if (e != hipSuccess)
+        return hip_err(e, "hipDeviceGetAttribute(CU count)");
+    p->lg_grid_limit = (int64_t)cus * std::max(k->occupancy(), 1);
+    return FFT_OK;
+}
+
 void free_plan(mifft_plan_s* p)
 {
     if (!p)
@@ -296,6 +347,8 @@ void free_plan(mifft_plan_s* p)
         (void)hipFree(p->tw);
     if (p->rows)
         (void)hipFree(p->rows);
+    if (p->lg_rows)
+        (void)hipFree(p->lg_rows);
     delete p;
 }
 
@@ -352,6 +405,10 @@ fft_plan create_batched(int64_t n, int64_t batch, int sign, int dtype, const Var
         return nullptr;
     }
     if (dtype == FFT_C32 && p->fwd->kind >= 1 && make_rows(p) != FFT_OK) {
+        free_plan(p);
+        return nullptr;
+    }
+    if (dtype == FFT_C32 && make_loss_grad(p) != FFT_OK) {
         free_plan(p);
         return nullptr;
     }
@@ -544,6 +601,32 @@ int fft_execute_scaled(fft_plan p, const void* in, const int32_t* in_exp, void* 
     rc = half_execute(p->half, in, in_exp, out, out_exp, p->tw, p->sign, static_cast<hipStream_t>(stream));
     if (rc != FFT_OK)
         return set_err(rc, "%s", half_last_message());
+    return ok();
+}
+
+int fft_execute_loss_grad(fft_plan p, const void* x, const float* w, void* grad, float* loss, void* stream)
+{
+    int rc = check_exec(p, x, grad);
+    if (rc != FFT_OK)
+        return rc;
+    if (!w || !loss)
+        return set_err(FFT_ENULL, "w/loss pointer is NULL");
+    if (p->kind != 0 || p->dtype != FFT_C32 || !p->lossgrad)
+        return set_err(FFT_EINVAL_DTYPE, "the fused loss is provided for batched FFT_C32 plans");
+    if ((reinterpret_cast<uintptr_t>(w) | reinterpret_cast<uintptr_t>(loss)) & 3)
+        return set_err(FFT_EALIGN, "w/loss must be 4-byte aligned");
+    const uintptr_t wb = reinterpret_cast<uintptr_t>(w), gb = reinterpret_cast<uintptr_t>(grad);
+    const uintptr_t wbytes = (uintptr_t)p->total * 4, gbytes = (uintptr_t)p->total * 8;
+    if (wb < gb + gbytes && gb < wb + wbytes)
+        return set_err(FFT_EOVERLAP, "w and grad overlap");
+    const uintptr_t lb = reinterpret_cast<uintptr_t>(loss), lbytes = (uintptr_t)p->batch * 4;
+    if (lb < gb + gbytes && gb < lb + lbytes)
+        return set_err(FFT_EOVERLAP, "loss and grad overlap");
+    const void* rows = p->lg_rows ? p->lg_rows : p->rows;
+    hipError_t e = p->lossgrad->fn(x, w, grad, loss, rows, p->batch, p->scale, p->lg_grid_limit,
+                                   static_cast<hipStream_t>(stream));
+    if (e != hipSuccess)
+        return hip_err(e, "fused loss kernel launch");
     return ok();
 }
 

@@ -467,6 +467,83 @@ __device__ __forceinline__ void exchange2(cf (&v)[1 << E], int t, cf* lds)
         v[m] = rb[m * DM];
 }
 
+// ---------------------------------------------------------------- global data access
+typedef float v2f __attribute__((ext_vector_type(2)));
+
+// Transform data is streamed: read once, written once.  Nontemporal
+// accesses (NT) keep it from displacing the twiddle tables in the caches
+// and measured 5-7% faster at N = 2048 on MI355X -- but only when every
+// wave-wide load/store instruction covers whole 128-byte lines.  When a
+// line is split across instructions (runs of fewer than 16 consecutive
+// complex values per transform) the streamed line is fetched again for the
+// second instruction, and plain accesses are much faster.
+template <int N, int TPT>
+constexpr bool stream_nt()
+{
+    return TPT >= 16 || (TPT == 1 && N == 2);
+}
+
+template <bool NT>
+__device__ __forceinline__ cf ld_data(const char* p)
+{
+    if constexpr (NT) {
+        const v2f v = __builtin_nontemporal_load(reinterpret_cast<const v2f*>(p));
+        return cf{v.x, v.y};
+    } else {
+        return *reinterpret_cast<const cf*>(p);
+    }
+}
+
+template <bool NT>
+__device__ __forceinline__ void st_data(char* p, cf v)
+{
+    if constexpr (NT) {
+        v2f w;
+        w.x = v.x;
+        w.y = v.y;
+        __builtin_nontemporal_store(w, reinterpret_cast<v2f*>(p));
+    } else {
+        *reinterpret_cast<cf*>(p) = v;
+    }
+}
+
+template <int L, int E, int TPB>
+__device__ __forceinline__ void load_group(cf (&v)[1 << E], const cf* __restrict__ in, int64_t g, int64_t batch,
+                                           int tb, unsigned toff8)
+{
+    using SC = Sched<L, E>;
+    constexpr int N = SC::N, EPT = SC::EPT, TPT = SC::TPT;
+    constexpr bool NT = stream_nt<N, TPT>();
+    const int64_t first = g * TPB;
+    const char* gb = reinterpret_cast<const char*>(in + first * N);
+    if (first + TPB <= batch) {
+#pragma unroll
+        for (int m = 0; m < EPT; m++)
+            v[m] = ld_data<NT>(gb + (toff8 + (unsigned)(m * TPT * 8)));
+    } else {
+        const bool live = first + tb < batch;
+#pragma unroll
+        for (int m = 0; m < EPT; m++)
+            v[m] = live ? ld_data<NT>(gb + (toff8 + (unsigned)(m * TPT * 8))) : cf{0.f, 0.f};
+    }
+}
+
+template <int L, int E, int TPB>
+__device__ __forceinline__ void store_group(const cf (&v)[1 << E], cf* __restrict__ out, int64_t g, int64_t batch,
+                                            int tb, unsigned toff8, float scale)
+{
+    using SC = Sched<L, E>;
+    constexpr int N = SC::N, EPT = SC::EPT, TPT = SC::TPT;
+    constexpr bool NT = stream_nt<N, TPT>();
+    const int64_t first = g * TPB;
+    char* gb = reinterpret_cast<char*>(out + first * N);
+    if (first + TPB <= batch || first + tb < batch) {
+#pragma unroll
+        for (int m = 0; m < EPT; m++)
+            st_data<NT>(gb + (toff8 + (unsigned)(m * TPT * 8)), cscale(v[m], scale));
+    }
+}
+
 // ---------------------------------------------------------------- pass runner
 template <int L, int E>
 using TwRegs = cf[Sched<L, E>::NP][1 << E];

@@ -19,21 +19,7 @@
 namespace mifft {
 namespace {
 
-typedef float v2f __attribute__((ext_vector_type(2)));
 typedef float v4f __attribute__((ext_vector_type(4)));
-
-// Transform data is streamed: read once, written once.  Nontemporal
-// accesses (NT) keep it from displacing the twiddle tables in the caches
-// and measured 5-7% faster at N = 2048 on MI355X -- but only when every
-// wave-wide load/store instruction covers whole 128-byte lines.  When a
-// line is split across instructions (runs of fewer than 16 consecutive
-// complex values per transform) the streamed line is fetched again for the
-// second instruction, and plain accesses are much faster.
-template <int N, int TPT>
-constexpr bool stream_nt()
-{
-    return TPT >= 16 || (TPT == 1 && N == 2);
-}
 
 template <bool NT>
 __device__ __forceinline__ v4f ld_data4(const v4f* p)
@@ -51,30 +37,6 @@ __device__ __forceinline__ void st_data4(v4f* p, v4f v)
         __builtin_nontemporal_store(v, p);
     else
         *p = v;
-}
-
-template <bool NT>
-__device__ __forceinline__ cf ld_data(const char* p)
-{
-    if constexpr (NT) {
-        const v2f v = __builtin_nontemporal_load(reinterpret_cast<const v2f*>(p));
-        return cf{v.x, v.y};
-    } else {
-        return *reinterpret_cast<const cf*>(p);
-    }
-}
-
-template <bool NT>
-__device__ __forceinline__ void st_data(char* p, cf v)
-{
-    if constexpr (NT) {
-        v2f w;
-        w.x = v.x;
-        w.y = v.y;
-        __builtin_nontemporal_store(w, reinterpret_cast<v2f*>(p));
-    } else {
-        *reinterpret_cast<cf*>(p) = v;
-    }
 }
 
 template <int LOG2N, int LOG2EPT, int WG, int S>
@@ -147,43 +109,6 @@ __global__ __launch_bounds__(WG) void k_fft_c32(const cf* __restrict__ in, cf* _
 //           while the current group is transformed and stored.
 // Global addresses are a uniform (SGPR) group base plus a 32-bit per-thread
 // byte offset; LDS addresses are one per-thread base plus immediates.
-
-template <int L, int E, int TPB>
-__device__ __forceinline__ void load_group(cf (&v)[1 << E], const cf* __restrict__ in, int64_t g, int64_t batch,
-                                           int tb, unsigned toff8)
-{
-    using SC = Sched<L, E>;
-    constexpr int N = SC::N, EPT = SC::EPT, TPT = SC::TPT;
-    constexpr bool NT = stream_nt<N, TPT>();
-    const int64_t first = g * TPB;
-    const char* gb = reinterpret_cast<const char*>(in + first * N);
-    if (first + TPB <= batch) {
-#pragma unroll
-        for (int m = 0; m < EPT; m++)
-            v[m] = ld_data<NT>(gb + (toff8 + (unsigned)(m * TPT * 8)));
-    } else {
-        const bool live = first + tb < batch;
-#pragma unroll
-        for (int m = 0; m < EPT; m++)
-            v[m] = live ? ld_data<NT>(gb + (toff8 + (unsigned)(m * TPT * 8))) : cf{0.f, 0.f};
-    }
-}
-
-template <int L, int E, int TPB>
-__device__ __forceinline__ void store_group(const cf (&v)[1 << E], cf* __restrict__ out, int64_t g, int64_t batch,
-                                            int tb, unsigned toff8, float scale)
-{
-    using SC = Sched<L, E>;
-    constexpr int N = SC::N, EPT = SC::EPT, TPT = SC::TPT;
-    constexpr bool NT = stream_nt<N, TPT>();
-    const int64_t first = g * TPB;
-    char* gb = reinterpret_cast<char*>(out + first * N);
-    if (first + TPB <= batch || first + tb < batch) {
-#pragma unroll
-        for (int m = 0; m < EPT; m++)
-            st_data<NT>(gb + (toff8 + (unsigned)(m * TPT * 8)), cscale(v[m], scale));
-    }
-}
 
 template <int L, int E, int WG, int S, int TW, int PF, bool WAVE>
 __global__ __launch_bounds__(WG) void k_fft_c32_v2(const cf* __restrict__ in, cf* __restrict__ out,

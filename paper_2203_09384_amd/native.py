@@ -24,6 +24,7 @@ EXPORTS = [
     "fft_plan_create_ragged_config", "fft_execute", "fft_execute_adjoint",
     "fft_execute_scaled", "fft_plan_destroy", "fft_plan_describe", "fft_plan_query",
     "fft_plan_twiddles", "fft_last_error", "fft_last_error_string", "fft_version",
+    "fft_execute_loss_grad",
 ]
 
 
@@ -82,6 +83,8 @@ def _declare(L):
     L.fft_execute_adjoint.restype = i32
     L.fft_execute_scaled.argtypes = [vp, vp, vp, vp, vp, vp]
     L.fft_execute_scaled.restype = i32
+    L.fft_execute_loss_grad.argtypes = [vp, vp, vp, vp, vp, vp]
+    L.fft_execute_loss_grad.restype = i32
     L.fft_plan_destroy.argtypes = [vp]
     L.fft_plan_destroy.restype = None
     L.fft_plan_describe.argtypes = [vp, ctypes.POINTER(PlanDesc)]

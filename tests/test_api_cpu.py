@@ -97,3 +97,37 @@ def test_no_device_is_reported_as_hip_error():
     assert L.fft_plan_create(256, 4, -1, 0) is None
     assert L.fft_last_error() == 8
     assert b"hipGetDevice" in L.fft_last_error_string()
+
+
+def test_half_precision_queries():
+    rc, d = q(2048, 32768, -1, 1)
+    assert rc == 0 and d.radices[:3] == [8, 16, 16] and d.wg == 256
+    rc, d = q(2048, 4, 1, 2)
+    assert rc == 0 and d.scale == np.float32(1.0 / 2048)
+    assert q(1024, 4, -1, 1)[0] == 4   # FP16/BF16 plans are N=2048 only
+    L = native.lib()
+    assert L.fft_execute_scaled(None, None, None, None, None, None) == 5
+
+
+def test_fused_loss_argument_checks():
+    L = native.lib()
+    assert L.fft_execute_loss_grad(None, None, None, None, None, None) == 5
+
+
+def test_tune_table_is_read(tmp_path):
+    """MIFFT_TUNE_TABLE overrides the built-in variant choice (host-only query)."""
+    import subprocess
+    import sys
+    table = tmp_path / "tune.txt"
+    table.write_text("# test table\nc32 8 4 64 2\nc32 11 8 256 4  # comment\nragged 5 8\n")
+    code = ("import ctypes, sys; sys.path.insert(0, %r);"
+            "from paper_2203_09384_amd import native;"
+            "L = native.lib(); d = native.PlanDesc();"
+            "assert L.fft_plan_query(256, 10, -1, 0, ctypes.byref(d)) == 0;"
+            "print(d.ept, d.wg, d.variant);"
+            "assert L.fft_plan_query(2048, 10, -1, 0, ctypes.byref(d)) == 0;"
+            "print(d.ept, d.wg, d.variant)") % ROOT
+    env = dict(os.environ, MIFFT_TUNE_TABLE=str(table))
+    out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=120)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.split() == ["4", "64", "2", "8", "256", "4"]

@@ -110,3 +110,67 @@ def test_inverse_fft_differentiable():
     yy = oracle.inverse(x64)
     ref = oracle.adjoint(2.0 * w * yy, sign=+1, scale=1.0 / n)
     assert per_transform_relerr(xg.grad.cpu().numpy(), ref) <= TOL
+
+
+# ---------------------------------------------------------------- fused loss
+@pytest.mark.parametrize("n", [2, 4, 8, 16, 64, 256, 2048])
+@pytest.mark.parametrize("sign", [-1, 1])
+def test_fused_loss_grad_vs_oracle(n, sign):
+    """One kernel: loss[b] = sum w |A x_b|^2 and grad = A^H (2 w A x)."""
+    batch = 3 * max(1, 2048 // n) + 1
+    x = synth.uniform_complex(41, (batch, n), key=(n, sign + 1))
+    w = synth.uniform_weights(41, (batch, n), key=(n, sign + 2))
+    plan = api.Plan(n, batch, sign)
+    loss, grad = plan.loss_grad(to_gpu(x), to_gpu(w))
+    torch.cuda.synchronize()
+    x64, w64 = x.astype(np.complex128), w.astype(np.float64)
+    scale = 1.0 if sign < 0 else 1.0 / n
+    y = oracle.fft(x64, sign, scale)
+    ref_loss = np.sum(w64 * np.abs(y) ** 2, axis=-1)
+    ref_grad = oracle.adjoint(2.0 * w64 * y, sign, scale)
+    assert np.max(np.abs(loss.cpu().numpy() - ref_loss) / ref_loss) <= TOL
+    assert per_transform_relerr(grad.cpu().numpy(), ref_grad) <= TOL
+
+
+def test_fused_loss_full_size_and_autograd():
+    """The differentiable workload (N=2048, batch 16384) through the fused
+    autograd function, against the oracle on sampled transforms and against
+    the unfused FFT -> torch loss -> adjoint path."""
+    n, batch = 2048, 16384
+    x = synth.uniform_complex(synth.SEED_AUTOGRAD, (batch, n))
+    w = synth.uniform_weights(synth.SEED_AUTOGRAD, (batch, n), key=(1,))
+    xg = to_gpu(x).requires_grad_(True)
+    wg = to_gpu(w)
+    L = api.weighted_power_loss(xg, wg)
+    L.backward()
+    torch.cuda.synchronize()
+    g = xg.grad.cpu().numpy()
+    rng = np.random.default_rng(4)
+    idx = np.unique(np.concatenate([[0, batch - 1], rng.integers(0, batch, 62)]))
+    _, g_ref = oracle.loss_grad(x[idx].astype(np.complex128), w[idx].astype(np.float64))
+    assert per_transform_relerr(g[idx], g_ref) <= TOL
+    loss2, g2 = gpu_loss_grad(x, w)
+    assert abs(float(L) - loss2) / loss2 < 1e-5
+    assert per_transform_relerr(g, g2) <= TOL
+
+
+def test_fused_loss_gradient_vs_finite_differences():
+    n, batch, h = 16, 4, 1e-2
+    x = synth.uniform_complex(43, (batch, n))
+    w = synth.uniform_weights(43, (batch, n), key=(1,))
+    xg = to_gpu(x).requires_grad_(True)
+    api.weighted_power_loss(xg, to_gpu(w)).backward()
+    g = xg.grad.cpu().numpy()
+    x64, w64 = x.astype(np.complex128), w.astype(np.float64)
+
+    def loss(z):
+        return float(np.sum(w64 * np.abs(oracle.forward(z)) ** 2))
+
+    fd = np.zeros_like(x64)
+    for b in range(batch):
+        for i in range(n):
+            for unit in (1.0, 1j):
+                e = np.zeros_like(x64)
+                e[b, i] = unit * h
+                fd[b, i] += unit * (loss(x64 + e) - loss(x64 - e)) / (2 * h)
+    assert per_transform_relerr(g, fd) <= TOL
