@@ -42,17 +42,18 @@ constexpr int HN = 2048;
 constexpr int HWG = 256;
 
 // LDS layouts, one per exchange, each conflict-free for both its writer and
-// its reader and affine in the per-instruction indices (so every access is
-// a per-thread base plus an immediate offset).  Real and imaginary parts
-// are separate planes; IM_* is the imaginary plane's offset.
-//   A -> B : d + (d >> 6)
-//   B -> C : d + 8 (d >> 6) + 16 (d >> 10)
-//   C -> store : d + (d >> 6) + 4 (d >> 8)
-__device__ __forceinline__ int fA(int d) { return d + (d >> 6); }
-__device__ __forceinline__ int fB(int d) { return d + 8 * (d >> 6) + 16 * (d >> 10); }
+// its reader (modelled on the 64 banks) and affine in the per-instruction
+// indices, so every access is a per-thread base plus an immediate offset.
+// Real and imaginary parts are separate planes; IM_* is the imaginary
+// plane's offset.
+//   A -> B      : d + (d >> 3) + 16 (d >> 10)
+//   B -> C      : d + (d >> 6)
+//   C -> store  : d + (d >> 6) + 4 (d >> 8)
+__device__ __forceinline__ int fA(int d) { return d + (d >> 3) + 16 * (d >> 10); }
+__device__ __forceinline__ int fB(int d) { return d + (d >> 6); }
 __device__ __forceinline__ int fC(int d) { return d + (d >> 6) + 4 * (d >> 8); }
-constexpr int IM_A = 2080, IM_B = 2336, IM_C = 2112;
-constexpr int BUF = 2 * IM_B;  // floats per buffer (largest layout)
+constexpr int IM_A = 2336, IM_B = 2080, IM_C = 2112;
+constexpr int BUF = 2 * IM_A;  // floats per buffer (largest layout)
 
 // ---- conversions (round to nearest even)
 template <bool BF>
@@ -102,33 +103,24 @@ __device__ __forceinline__ v4f mfma(const Op8<true>& a, const Op8<true>& b, v4f 
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.lo, b.hi, c, 0, 0, 0);
 }
 
-// This lane's rows of the two A operands: A_re[m] = [Re F[m][.] | -Im F[m][.]],
-// A_im[m] = [Im F[m][.] | Re F[m][.]], F[m][r] = exp(S 2 pi i m r / 16);
-// lane l holds row m = l % 16, columns k = 8 (l / 16) + i.
+// This lane's rows of the A operands of the 16-point DFT with the twiddles
+// of a Stockham pass folded in: A[m][r] = exp(S 2 pi i r (8 m + g) / 128),
+// i.e. F[m][r] w_128^{g r} (g = 0: the plain DFT).  Real form over K = 32:
+// A_re[m] = [Re A[m][.] | -Im A[m][.]], A_im[m] = [Im A[m][.] | Re A[m][.]];
+// lane l holds row m = l % 16, columns k = 8 (l / 16) + i.  Entries are
+// single lookups of the FP32 table w_2048^{16 e}, rounded once to the
+// operand type.
 template <int S, bool BF>
-__device__ __forceinline__ void dft16_operands(Op8<BF>& are, Op8<BF>& aim, int lane)
+__device__ __forceinline__ void dft16_operands(Op8<BF>& are, Op8<BF>& aim, int lane, int g,
+                                               const cf* __restrict__ tw)
 {
     const int m = lane & 15, kq = lane >> 4;
 #pragma unroll
     for (int i = 0; i < 8; i++) {
         const int r = (kq & 1) * 8 + i;
-        const int e = (m * r) & 15;
-        // cos / sin of 2 pi e / 16 from the first quadrant by symmetry
-        const int q = e & 3, quad = e >> 2;
-        const float c0 = q == 0 ? 1.0f : (q == 1 ? kCos16[1] : (q == 2 ? kCos16[2] : kCos16[3]));
-        const float s0 = q == 0 ? 0.0f : (q == 1 ? kSin16[1] : (q == 2 ? kSin16[2] : kSin16[3]));
-        float c = c0, sn = s0;
-        if (quad == 1) {
-            c = -s0;
-            sn = c0;
-        } else if (quad == 2) {
-            c = -c0;
-            sn = -s0;
-        } else if (quad == 3) {
-            c = s0;
-            sn = -c0;
-        }
-        sn *= (float)S;
+        const int e = (r * (8 * m + g)) & 127;
+        const cf z = tw[16 * e];
+        const float c = z.x, sn = (float)(-S) * z.y;  // exp(S 2 pi i e / 128)
         if (kq < 2) {
             are.set(i, c);
             aim.set(i, sn);
@@ -156,174 +148,191 @@ __device__ __forceinline__ void unpack8(const uint32_t (&u)[8], cf (&v)[8])
         v[m] = cf{to_f32<BF>((uint16_t)(u[m] & 0xffffu)), to_f32<BF>((uint16_t)(u[m] >> 16))};
 }
 
-// Persistent: workgroup walks transforms blockIdx.x, + gridDim.x, ...;
-// the next transform's input is loaded while the current one is computed.
-// LDS buffers X and Y alternate: A->B and C->store use one, B->C the other.
+// Per-thread constants of the kernel: MFMA operands, twiddles, LDS bases.
+template <bool BF>
+struct HalfCtx {
+    Op8<BF> a_re[2], a_im[2];  // pass B, group g = 2 wave + gg, twiddles folded
+    Op8<BF> f_re, f_im;        // pass C, plain DFT
+    cf twB[2][4];              // pass C twiddle of pass B output (gg, i)
+    int oWA, oRB[2], oWB[2], oRC[2], oWC[2], oRS0, oRS1;
+    int tid, lane, wave;
+};
+
+// One transform: raw input `cur` (thread t holds x[t + 256 m]) -> stored
+// output and exponent.  X holds the A->B and C->store exchanges, Y the B->C
+// exchange; `red` the per-wave maxima.
 template <int S, bool BF>
-__global__ __launch_bounds__(HWG) void k_fft_half_2048(const uint32_t* __restrict__ in,
+__device__ __forceinline__ void half_transform(const HalfCtx<BF>& c, const uint32_t (&cur)[8], float* X, float* Y,
+                                               float* red, const int32_t* __restrict__ in_exp,
+                                               uint32_t* __restrict__ out, int32_t* __restrict__ out_exp,
+                                               int64_t b, int scale_log2)
+{
+    constexpr int dWC[4] = {0, 130, 264, 394};  // fC(d0 + 128 i) - fC(d0)
+    // ---- pass A: radix 8 on the VALU in FP32 over x[tid + 256 m]
+    cf v[8];
+    unpack8<BF>(cur, v);
+    float mx = 0.f;
+#pragma unroll
+    for (int m = 0; m < 8; m++)
+        mx = fmaxf(mx, fmaxf(fabsf(v[m].x), fabsf(v[m].y)));
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+        mx = fmaxf(mx, __shfl_xor(mx, off));
+    if (c.lane == 0)
+        red[c.wave] = mx;
+    dft8<S>(v);
+    // outputs to the Stockham position d = 8 tid + r (pass B's twiddles are in its operands)
+    float* wa = X + c.oWA;
+#pragma unroll
+    for (int r = 0; r < 8; r++) {
+        wa[r] = v[r].x;
+        wa[IM_A + r] = v[r].y;
+    }
+    __syncthreads();
+
+    // ---- block maximum -> power-of-two scale (largest input component in [8, 16))
+    mx = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+    int e_max = 0;
+    if (mx > 0.f && mx <= 3.4e38f)
+        (void)frexpf(mx, &e_max);  // mx < 2^e_max
+    const float sc = ldexpf(1.0f, 4 - e_max);
+    const int e_in = in_exp ? in_exp[b] : 0;
+    const int e_out = e_in + e_max - 4 + scale_log2;
+
+    // ---- pass B: radix 16 (NS = 8) on MFMA.  Group g holds the 16 butterflies
+    // j = g + 8 n (all with j mod 8 = g, so one twiddled DFT matrix serves them);
+    // butterfly j reads x[j + 128 r].
+    v4f yre[2], yim[2];
+#pragma unroll
+    for (int gg = 0; gg < 2; gg++) {
+        const float* rb = X + c.oRB[gg];
+        Op8<BF> bo;
+#pragma unroll
+        for (int i = 0; i < 8; i++)
+            bo.set(i, rb[144 * i] * sc);
+        const v4f z = {0.f, 0.f, 0.f, 0.f};
+        yre[gg] = mfma(c.a_re[gg], bo, z);
+        yim[gg] = mfma(c.a_im[gg], bo, z);
+    }
+    // outputs Y[m] of butterfly j = g + 8 n to d = 128 n + g + 8 m, times pass C's twiddle
+#pragma unroll
+    for (int gg = 0; gg < 2; gg++) {
+        float* wb = Y + c.oWB[gg];
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+            const cf y = cmul(cf{yre[gg][i], yim[gg][i]}, c.twB[gg][i]);
+            wb[8 * i] = y.x;
+            wb[IM_B + 8 * i] = y.y;
+        }
+    }
+    __syncthreads();
+
+    // ---- pass C: radix 16 (NS = 128) on MFMA over butterflies j = 16 g + n;
+    // natural-order outputs d = j + 128 m
+#pragma unroll
+    for (int gg = 0; gg < 2; gg++) {
+        const float* rc = Y + c.oRC[gg];
+        Op8<BF> bo;
+#pragma unroll
+        for (int i = 0; i < 8; i++)
+            bo.set(i, rc[130 * i]);
+        const v4f z = {0.f, 0.f, 0.f, 0.f};
+        yre[gg] = mfma(c.f_re, bo, z);
+        yim[gg] = mfma(c.f_im, bo, z);
+    }
+#pragma unroll
+    for (int gg = 0; gg < 2; gg++) {
+        float* wc = X + c.oWC[gg];
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+            wc[dWC[i]] = yre[gg][i];
+            wc[IM_C + dWC[i]] = yim[gg][i];
+        }
+    }
+    __syncthreads();
+
+    // ---- store: 4 consecutive elements (16 bytes) per lane and instruction
+    const float osc = out_exp ? 1.0f : ldexpf(1.0f, e_out);
+    v4u* dst = reinterpret_cast<v4u*>(out + b * HN);
+#pragma unroll
+    for (int h = 0; h < 2; h++) {
+        const float* rs = X + (h ? c.oRS1 : c.oRS0);
+        v4u o;
+#pragma unroll
+        for (int i = 0; i < 4; i++)
+            o[i] = (uint32_t)from_f32<BF>(rs[i] * osc) | ((uint32_t)from_f32<BF>(rs[IM_C + i] * osc) << 16);
+        __builtin_nontemporal_store(o, dst + c.tid + HWG * h);
+    }
+    if (out_exp && c.tid == 0)
+        out_exp[b] = e_out;
+}
+
+__device__ __forceinline__ void load_raw(uint32_t (&u)[8], const uint32_t* __restrict__ in, int64_t b, int tid)
+{
+    const uint32_t* src = in + b * HN;
+#pragma unroll
+    for (int m = 0; m < 8; m++)
+        u[m] = __builtin_nontemporal_load(src + tid + 256 * m);
+}
+
+// Persistent: a workgroup walks transforms blockIdx.x, + gridDim.x, ...,
+// loading the next transform's input while the current one is computed.
+// Two LDS buffers alternate between consecutive transforms (loop unrolled
+// twice so each body's buffer roles are fixed), so three barriers suffice.
+template <int S, bool BF>
+__global__ __launch_bounds__(HWG, BF ? 3 : 4) void k_fft_half_2048(const uint32_t* __restrict__ in,
                                                        const int32_t* __restrict__ in_exp,
                                                        uint32_t* __restrict__ out, int32_t* __restrict__ out_exp,
                                                        const cf* __restrict__ tw, int64_t batch, int scale_log2)
 {
     __shared__ float lds[2 * BUF];
     __shared__ float s_red[2][HWG / 64];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int n = lane & 15, kq = lane >> 4;
     int64_t b = blockIdx.x;
     if (b >= batch)
         return;
-
-    // ---- per-thread constants, hoisted out of the transform loop
-    Op8<BF> are, aim;
-    dft16_operands<S, BF>(are, aim, lane);
-    cf twA[8];  // pass B twiddle of pass A output r: w_128^{(tid >> 4) r}
-#pragma unroll
-    for (int r = 0; r < 8; r++)
-        twA[r] = tw_at<S>(tw, ((tid >> 4) * r) << 4);
-    cf twB[2][4];  // pass C twiddle of pass B output (gg, i): w_2048^{(j >> 3) ((j & 7) + 8 m)}
+    HalfCtx<BF> c;
+    c.tid = threadIdx.x;
+    c.lane = c.tid & 63;
+    c.wave = c.tid >> 6;
+    const int n = c.lane & 15, kq = c.lane >> 4, r0 = (kq & 1) * 8;
+    dft16_operands<S, BF>(c.f_re, c.f_im, c.lane, 0, tw);
 #pragma unroll
     for (int gg = 0; gg < 2; gg++) {
-        const int j = 16 * (2 * wave + gg) + n;
+        const int g = 2 * c.wave + gg;
+        dft16_operands<S, BF>(c.a_re[gg], c.a_im[gg], c.lane, g, tw);
 #pragma unroll
-        for (int i = 0; i < 4; i++)
-            twB[gg][i] = tw_at<S>(tw, (j >> 3) * ((j & 7) + 8 * (4 * kq + i)));
+        for (int i = 0; i < 4; i++)  // w_2048^{n (g + 8 m)}, m = 4 kq + i
+            c.twB[gg][i] = tw_at<S>(tw, n * (g + 8 * (4 * kq + i)));
+        c.oRB[gg] = ((kq >> 1) ? IM_A : 0) + fA(g + 8 * n + 128 * r0);
+        c.oWB[gg] = fB(128 * n + g + 32 * kq);
+        const int j = 16 * g + n;
+        c.oRC[gg] = ((kq >> 1) ? IM_B : 0) + fB(j + 128 * r0);
+        c.oWC[gg] = fC(j + 512 * kq);
     }
-    const int oWA = fA(8 * tid);
-    const int r0 = (kq & 1) * 8;
-    int oRB[2], oWB[2], oRC[2], oWC[2];
-#pragma unroll
-    for (int gg = 0; gg < 2; gg++) {
-        const int j = 16 * (2 * wave + gg) + n;
-        oRB[gg] = ((kq >> 1) ? IM_A : 0) + fA(j + 128 * r0);
-        oWB[gg] = fB(((j >> 3) << 7) + (j & 7) + 32 * kq);
-        oRC[gg] = ((kq >> 1) ? IM_B : 0) + fB(j + 128 * r0);
-        oWC[gg] = fC(j + 512 * kq);
-    }
-    const int oRS0 = fC(4 * tid), oRS1 = fC(4 * (tid + HWG));
-    constexpr int dWC[4] = {0, 130, 264, 394};  // fC(d0 + 128 i) - fC(d0)
+    c.oWA = fA(8 * c.tid);
+    c.oRS0 = fC(4 * c.tid);
+    c.oRS1 = fC(4 * (c.tid + HWG));
 
-    uint32_t cur[8], nxt[8];
-    {
-        const uint32_t* src = in + b * HN;
-#pragma unroll
-        for (int m = 0; m < 8; m++)
-            cur[m] = __builtin_nontemporal_load(src + tid + 256 * m);
-    }
-    int it = 0;
+    float* const buf0 = lds;
+    float* const buf1 = lds + BUF;
+    uint32_t ua[8], ub[8];
+    load_raw(ua, in, b, c.tid);
+    const int64_t stride = gridDim.x;
     while (true) {
-        const int64_t b1 = b + gridDim.x;
-        if (b1 < batch) {
-            const uint32_t* src = in + b1 * HN;
-#pragma unroll
-            for (int m = 0; m < 8; m++)
-                nxt[m] = __builtin_nontemporal_load(src + tid + 256 * m);
-        }
-        float* X = lds + (it & 1) * BUF;
-        float* Y = lds + ((it & 1) ^ 1) * BUF;
-        float* red = s_red[it & 1];
-
-        // ---- pass A: radix 8 on VALU in FP32 over x[tid + 256 m]
-        cf v[8];
-        unpack8<BF>(cur, v);
-        float mx = 0.f;
-#pragma unroll
-        for (int m = 0; m < 8; m++)
-            mx = fmaxf(mx, fmaxf(fabsf(v[m].x), fabsf(v[m].y)));
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1)
-            mx = fmaxf(mx, __shfl_xor(mx, off));
-        if (lane == 0)
-            red[wave] = mx;
-        dft8<S>(v);
-        // outputs to the Stockham position d = 8 tid + r, times pass B's twiddle
-        float* wa = X + oWA;
-#pragma unroll
-        for (int r = 0; r < 8; r++) {
-            const cf y = cmul(v[r], twA[r]);
-            wa[r] = y.x;
-            wa[IM_A + r] = y.y;
-        }
-        __syncthreads();
-
-        // ---- block maximum -> power-of-two scale (largest input component in [8, 16))
-        mx = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
-        int e_max = 0;
-        if (mx > 0.f && mx <= 3.4e38f)
-            (void)frexpf(mx, &e_max);  // mx < 2^e_max
-        const float sc = ldexpf(1.0f, 4 - e_max);
-        const int e_in = in_exp ? in_exp[b] : 0;
-        const int e_out = e_in + e_max - 4 + scale_log2;
-
-        // ---- pass B: radix 16 on MFMA (NS = 8); butterfly j reads x[j + 128 r]
-        v4f yre[2], yim[2];
-#pragma unroll
-        for (int gg = 0; gg < 2; gg++) {
-            const float* rb = X + oRB[gg];
-            Op8<BF> bo;
-#pragma unroll
-            for (int i = 0; i < 8; i++)
-                bo.set(i, rb[130 * i] * sc);
-            const v4f z = {0.f, 0.f, 0.f, 0.f};
-            yre[gg] = mfma(are, bo, z);
-            yim[gg] = mfma(aim, bo, z);
-        }
-        // outputs to d = ((j >> 3) << 7) + (j & 7) + 8 m, times pass C's twiddle
-#pragma unroll
-        for (int gg = 0; gg < 2; gg++) {
-            float* wb = Y + oWB[gg];
-#pragma unroll
-            for (int i = 0; i < 4; i++) {
-                const cf y = cmul(cf{yre[gg][i], yim[gg][i]}, twB[gg][i]);
-                wb[8 * i] = y.x;
-                wb[IM_B + 8 * i] = y.y;
-            }
-        }
-        __syncthreads();
-
-        // ---- pass C: radix 16 on MFMA (NS = 128); natural-order outputs d = j + 128 m
-#pragma unroll
-        for (int gg = 0; gg < 2; gg++) {
-            const float* rc = Y + oRC[gg];
-            Op8<BF> bo;
-#pragma unroll
-            for (int i = 0; i < 8; i++)
-                bo.set(i, rc[144 * i]);
-            const v4f z = {0.f, 0.f, 0.f, 0.f};
-            yre[gg] = mfma(are, bo, z);
-            yim[gg] = mfma(aim, bo, z);
-        }
-#pragma unroll
-        for (int gg = 0; gg < 2; gg++) {
-            float* wc = X + oWC[gg];
-#pragma unroll
-            for (int i = 0; i < 4; i++) {
-                wc[dWC[i]] = yre[gg][i];
-                wc[IM_C + dWC[i]] = yim[gg][i];
-            }
-        }
-        __syncthreads();
-
-        // ---- store: 4 consecutive elements (16 bytes) per lane and instruction
-        const float osc = out_exp ? 1.0f : ldexpf(1.0f, e_out);
-        v4u* dst = reinterpret_cast<v4u*>(out + b * HN);
-#pragma unroll
-        for (int h = 0; h < 2; h++) {
-            const float* rs = X + (h ? oRS1 : oRS0);
-            v4u o;
-#pragma unroll
-            for (int i = 0; i < 4; i++)
-                o[i] = (uint32_t)from_f32<BF>(rs[i] * osc) | ((uint32_t)from_f32<BF>(rs[IM_C + i] * osc) << 16);
-            __builtin_nontemporal_store(o, dst + tid + HWG * h);
-        }
-        if (out_exp && tid == 0)
-            out_exp[b] = e_out;
+        int64_t b1 = b + stride;
+        if (b1 < batch)
+            load_raw(ub, in, b1, c.tid);
+        half_transform<S, BF>(c, ua, buf0, buf1, s_red[0], in_exp, out, out_exp, b, scale_log2);
         if (b1 >= batch)
             break;
-#pragma unroll
-        for (int m = 0; m < 8; m++)
-            cur[m] = nxt[m];
         b = b1;
-        it++;
+        b1 = b + stride;
+        if (b1 < batch)
+            load_raw(ua, in, b1, c.tid);
+        half_transform<S, BF>(c, ub, buf1, buf0, s_red[1], in_exp, out, out_exp, b, scale_log2);
+        if (b1 >= batch)
+            break;
+        b = b1;
     }
 }
 
@@ -354,7 +363,7 @@ thread_local char g_hmsg[256] = "";
 struct HalfPlan {
     int64_t n = 0, batch = 0;
     int dtype = FFT_C16;
-    int64_t grid_limit = 0;  // CUs x resident workgroups
+    int64_t grid_limit[2] = {0, 0};  // CUs x resident workgroups, forward / inverse kernel
 };
 
 bool half_supported(int64_t n) { return n == HN; }
@@ -383,9 +392,10 @@ int half_create(HalfPlan** out, int64_t n, int64_t batch, int dtype)
         delete hp;
         return FFT_EHIP;
     }
-    const int occ = dtype == FFT_CBF16 ? std::min(occupancy_half<-1, true>(), occupancy_half<1, true>())
-                                       : std::min(occupancy_half<-1, false>(), occupancy_half<1, false>());
-    hp->grid_limit = (int64_t)cus * std::max(occ, 1);
+    const int occ_f = dtype == FFT_CBF16 ? occupancy_half<-1, true>() : occupancy_half<-1, false>();
+    const int occ_i = dtype == FFT_CBF16 ? occupancy_half<1, true>() : occupancy_half<1, false>();
+    hp->grid_limit[0] = (int64_t)cus * std::max(occ_f, 1);
+    hp->grid_limit[1] = (int64_t)cus * std::max(occ_i, 1);
     *out = hp;
     return FFT_OK;
 }
@@ -397,11 +407,11 @@ int half_execute(HalfPlan* hp, const void* in, const int32_t* in_exp, void* out,
     hipError_t e;
     const bool bf = hp->dtype == FFT_CBF16;
     if (sign < 0)
-        e = bf ? launch_half<-1, true>(in, in_exp, out, out_exp, tw, hp->batch, sl, hp->grid_limit, stream)
-               : launch_half<-1, false>(in, in_exp, out, out_exp, tw, hp->batch, sl, hp->grid_limit, stream);
+        e = bf ? launch_half<-1, true>(in, in_exp, out, out_exp, tw, hp->batch, sl, hp->grid_limit[0], stream)
+               : launch_half<-1, false>(in, in_exp, out, out_exp, tw, hp->batch, sl, hp->grid_limit[0], stream);
     else
-        e = bf ? launch_half<+1, true>(in, in_exp, out, out_exp, tw, hp->batch, sl, hp->grid_limit, stream)
-               : launch_half<+1, false>(in, in_exp, out, out_exp, tw, hp->batch, sl, hp->grid_limit, stream);
+        e = bf ? launch_half<+1, true>(in, in_exp, out, out_exp, tw, hp->batch, sl, hp->grid_limit[1], stream)
+               : launch_half<+1, false>(in, in_exp, out, out_exp, tw, hp->batch, sl, hp->grid_limit[1], stream);
     if (e != hipSuccess) {
         snprintf(g_hmsg, sizeof g_hmsg, "half-precision kernel launch: %s", hipGetErrorString(e));
         return FFT_EHIP;
@@ -431,8 +441,9 @@ void half_query(int64_t n, int64_t batch, fft_plan_desc* d)
 void half_describe(const HalfPlan* hp, fft_plan_desc* d)
 {
     half_query(hp->n, hp->batch, d);
-    if (hp->grid_limit > 0 && d->grid > hp->grid_limit)
-        d->grid = hp->grid_limit;
+    const int64_t lim = hp->grid_limit[d->sign > 0 ? 1 : 0];
+    if (lim > 0 && d->grid > lim)
+        d->grid = lim;
 }
 
 }  // namespace mifft

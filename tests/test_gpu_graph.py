@@ -1,0 +1,78 @@
+"""Every execute entry point only enqueues work, so it can be captured into a
+graph.  Each graph is replayed several times with unrelated eager work and
+synchronisations in between, and every replay must equal the eager result
+bit for bit."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2203_09384_amd import api, synth
+from gpu_util import need_gpu, to_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(autouse=True)
+def _gpu():
+    need_gpu()
+
+
+def capture(fn):
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        fn()  # warm-up outside the graph
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        fn()
+    return g
+
+
+def replay_and_check(g, outs, refs, scratch):
+    for i in range(4):
+        for o in outs:
+            o.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        for o, r in zip(outs, refs):
+            assert torch.equal(o, r), i
+        _ = (scratch * 3).sum().item()
+
+
+@pytest.mark.parametrize("n", [2, 64, 2048])
+def test_plain_and_adjoint_in_graph(n):
+    batch = (1 << 20) // n
+    x = to_gpu(synth.uniform_complex(51, (batch, n), key=(n,)))
+    p = api.Plan(n, batch, -1)
+    ref_y, ref_a = p.execute(x), p.adjoint(x)
+    y, a = torch.empty_like(x), torch.empty_like(x)
+
+    def fn():
+        p.execute(x, y)
+        p.adjoint(x, a)
+    replay_and_check(capture(fn), [y, a], [ref_y, ref_a], x)
+
+
+def test_fused_loss_in_graph():
+    n, batch = 2048, 512
+    x = to_gpu(synth.uniform_complex(53, (batch, n)))
+    w = to_gpu(synth.uniform_weights(53, (batch, n), key=(1,)))
+    p = api.Plan(n, batch, -1)
+    ref_l, ref_g = p.loss_grad(x, w)
+    ref_l, ref_g = ref_l.clone(), ref_g.clone()
+    lv, gr = torch.empty_like(ref_l), torch.empty_like(ref_g)
+    replay_and_check(capture(lambda: p.loss_grad(x, w, gr, lv)), [lv, gr], [ref_l, ref_g], x)
+
+
+@pytest.mark.parametrize("dtype,tdt", [("c16", torch.float16), ("cbf16", torch.bfloat16)])
+def test_half_in_graph(dtype, tdt):
+    n, batch = 2048, 1000
+    x = synth.uniform_complex(55, (batch, n), dtype=np.complex128)
+    xh = torch.from_numpy(np.stack([x.real, x.imag], -1).astype(np.float32)).to(tdt).cuda().contiguous()
+    p = api.Plan(n, batch, -1, dtype=dtype)
+    ry, re = p.execute_scaled(xh)
+    ry, re = ry.clone(), re.clone()
+    y, e = torch.empty_like(ry), torch.empty_like(re)
+    replay_and_check(capture(lambda: p.execute_scaled(xh, out=y, out_exp=e)), [y, e], [ry, re], xh.float())
