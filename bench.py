@@ -335,6 +335,22 @@ def main():
                 log(f"[bench] sweep {row}")
             out["sweep"] = sweep
 
+        # ------------------------------------------------------------ lengths above 2048
+        large = []
+        for L in (12, 16, 20):
+            nn = 1 << L
+            bb = total // nn
+            p = api.Plan(nn, bb, -1)
+            m = time_launches(lambda: p.execute(x_all.view(bb, nn), y_all.view(bb, nn)),
+                              max(20, args.steps // 4), 5, torch)
+            large.append({"n": nn, "batch": bb, "us": round(m * 1e3, 2),
+                          "GFLOPs": round(5.0 * nn * L * bb / (m * 1e-3) / 1e9, 1),
+                          "GBps_algorithmic": round(bytes_alg / (m * 1e-3) / 1e9, 1),
+                          "passes_over_hbm": 2})
+            p.close()
+        out["large_n"] = large
+        log(f"[bench] large {large}")
+
         # ------------------------------------------------------------ FP16 / BF16
         out["half"] = bench_half(api, synth, torch, dev, args.steps, ms, x_all)
         log(f"[bench] half {out['half']}")

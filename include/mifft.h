@@ -8,7 +8,8 @@
  * for every transform of a batch, by Cooley-Tukey / Stockham passes of
  * radix 2..16 (section "Implementation": radix-2/4/8 stages selected on
  * the host from N; single precision, complex-to-complex, out of place,
- * N up to 2^11).  Both input and output are in natural order.
+ * N up to 2^11), extended here to 2^20 by the four-step split.  Both
+ * input and output are in natural order.
  *
  * Conventions shared by every entry point
  *   - Data are interleaved (re, im) pairs.  FFT_C32: two float32 per element
@@ -53,7 +54,7 @@ enum {
 /* status codes */
 enum {
     FFT_OK = 0,
-    FFT_EINVAL_N = 1,       /* n not a power of two in [2, 2048]               */
+    FFT_EINVAL_N = 1,       /* n not a supported power of two (see create)     */
     FFT_EINVAL_BATCH = 2,   /* batch < 1, or the batch does not fit one launch  */
     FFT_EINVAL_SIGN = 3,    /* sign not -1 or +1                               */
     FFT_EINVAL_DTYPE = 4,   /* unknown dtype, or dtype not valid for the call   */
@@ -95,8 +96,12 @@ typedef struct {
 
 /*
  * Create a plan for `batch` transforms of length n.
- *   n      power of two in [2, 2048] (section "Implementation": lengths up
- *          to 2^11; lengths below 2^3 extend the paper's measured range).
+ *   n      power of two.  FFT_C32: [2, 2^20].  Lengths up to 2^11 (the
+ *          paper's range, section "Implementation") run one single-pass
+ *          kernel; 2^12 .. 2^20 (the paper's future work, section
+ *          "Conclusions") use the four-step split N = N1 N2: a column pass
+ *          with the w_N^{n2 k1} twiddles, then an in-place row pass in
+ *          `out` (two kernels on the stream).  FFT_C16 / FFT_CBF16: 2048.
  *   batch  >= 1.
  *   sign   -1: forward transform Eq. (dft), scale 1.
  *          +1: inverse transform Eq. (idft), scale 1/n.

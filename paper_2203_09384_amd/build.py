@@ -28,6 +28,7 @@ def _units():
         units.append(("fft_c32.hip", f"fft_c32_L{L}.o", [f"-DMIFFT_LOG2N={L}"]))
         units.append(("fused_loss.hip", f"fused_loss_L{L}.o", [f"-DMIFFT_LOG2N={L}"]))
     units.append(("twiddle.hip", "twiddle.o", []))
+    units.append(("fourstep.hip", "fourstep.o", []))
     for wg in (64, 128, 256):
         units.append(("ragged.hip", f"ragged_wg{wg}.o", [f"-DMIFFT_RAGGED_WG={wg}"]))
     units.append(("ragged_plan.cpp", "ragged_plan.o", ["-x", "hip"]))

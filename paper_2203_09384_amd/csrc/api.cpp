@@ -16,6 +16,7 @@
 #include <vector>
 
 #include "../../include/mifft.h"
+#include "fourstep.hpp"
 #include "fused_loss.hpp"
 #include "half.hpp"
 #include "ragged.hpp"
@@ -82,6 +83,19 @@ const KernelC32* find_c32(int log2n, int log2ept, int wg, int sign, int kind)
     return nullptr;
 }
 int count_c32() { return (int)c32_reg().size(); }
+static std::vector<FourStep>& fs_reg()
+{
+    static std::vector<FourStep> r;
+    return r;
+}
+void register_fourstep(const FourStep& f) { fs_reg().push_back(f); }
+const FourStep* find_fourstep(int log2n)
+{
+    for (const auto& f : fs_reg())
+        if (f.log2n == log2n)
+            return &f;
+    return nullptr;
+}
 static std::vector<KernelLossGrad>& lg_reg()
 {
     static std::vector<KernelLossGrad> r;
@@ -190,6 +204,10 @@ struct mifft_plan_s {
     void* tw = nullptr;              // device FP32 twiddle table (2048 entries)
     void* rows = nullptr;            // per-pass twiddle rows (kind >= 1)
     int64_t grid_limit = 0;          // persistent kinds: CUs x workgroups per CU
+    const FourStep* fs = nullptr;    // lengths above 2048: two-pass four-step
+    void* fs_rows1 = nullptr;
+    void* fs_rows2 = nullptr;
+    void* fs_tw = nullptr;           // two-level w_N table: 1024 + N/1024 entries
     const KernelLossGrad* lossgrad = nullptr;  // fused loss + gradient kernel (FP32)
     void* lg_rows = nullptr;         // its twiddle rows when they differ from `rows`
     int64_t lg_grid_limit = 0;
@@ -199,12 +217,16 @@ struct mifft_plan_s {
 };
 
 namespace {
+constexpr int64_t kMaxN = int64_t(1) << 20;
+
 int check_common(int64_t n, int64_t batch, int sign, int dtype)
 {
     if (dtype != FFT_C32 && dtype != FFT_C16 && dtype != FFT_CBF16)
         return set_err(FFT_EINVAL_DTYPE, "dtype %d is not FFT_C32, FFT_C16 or FFT_CBF16", dtype);
-    if (!is_pow2(n) || n < 2 || n > 2048)
-        return set_err(FFT_EINVAL_N, "n=%lld is not a power of two in [2, 2048]", (long long)n);
+    if (!is_pow2(n) || n < 2 || n > kMaxN)
+        return set_err(FFT_EINVAL_N, "n=%lld is not a power of two in [2, 2^20]", (long long)n);
+    if (n > 2048 && dtype != FFT_C32)
+        return set_err(FFT_EINVAL_N, "n=%lld: lengths above 2048 are FFT_C32 only", (long long)n);
     if (batch < 1)
         return set_err(FFT_EINVAL_BATCH, "batch=%lld must be >= 1", (long long)batch);
     if (batch > (int64_t(1) << 40) / n)
@@ -215,8 +237,36 @@ int check_common(int64_t n, int64_t batch, int sign, int dtype)
     return FFT_OK;
 }
 
+int fill_desc_fourstep(int64_t n, int64_t batch, int sign, int dtype, fft_plan_desc* d)
+{
+    memset(d, 0, sizeof *d);
+    const FourStep* f = find_fourstep(ilog2(n));
+    d->n = n;
+    d->batch = batch;
+    d->sign = sign;
+    d->dtype = dtype;
+    d->scale = sign > 0 ? 1.0f / (float)n : 1.0f;
+    d->kind = 0;
+    d->variant = 9;
+    if (!f)
+        return FFT_OK;
+    d->ept = 1 << f->log2e1;
+    d->wg = 16 * (int)((1 << f->log2n1) >> f->log2e1);
+    d->transforms_per_wg = 16;
+    d->grid = batch * ((int64_t(1) << f->log2n2) / 16);
+    int r1[8], r2[8];
+    const int n1 = schedule(f->log2n1, f->log2e1, r1), n2 = schedule(f->log2n2, f->log2e2, r2);
+    d->npasses = std::min(8, n1 + n2);
+    for (int i = 0; i < d->npasses; i++)
+        d->radices[i] = i < n1 ? r1[i] : r2[i - n1];
+    d->lds_bytes = std::max(f->lds1, f->lds2);
+    return FFT_OK;
+}
+
 int fill_desc_c32(int64_t n, int64_t batch, int sign, int dtype, Variant v, int64_t grid_limit, fft_plan_desc* d)
 {
+    if (n > 2048)
+        return fill_desc_fourstep(n, batch, sign, dtype, d);
     memset(d, 0, sizeof *d);
     const int log2n = ilog2(n);
     d->n = n;
@@ -268,6 +318,33 @@ int make_twiddles(mifft_plan_s* p)
     e = hipStreamSynchronize(nullptr);
     if (e != hipSuccess)
         return hip_err(e, "twiddle kernel");
+    return FFT_OK;
+}
+
+// Tables of a four-step plan: rows of both inner transforms and the two-level
+// w_N table.
+int make_fourstep(mifft_plan_s* p)
+{
+    const FourStep* f = find_fourstep(p->log2n);
+    p->fs = f;
+    const size_t nt = 1024 + ((size_t)1 << (p->log2n - 10));
+    hipError_t e = hipMalloc(&p->fs_rows1, std::max(f->rows1, 1) * sizeof(float2));
+    if (e == hipSuccess)
+        e = hipMalloc(&p->fs_rows2, std::max(f->rows2, 1) * sizeof(float2));
+    if (e == hipSuccess)
+        e = hipMalloc(&p->fs_tw, nt * sizeof(float2));
+    if (e != hipSuccess)
+        return e == hipErrorOutOfMemory ? set_err(FFT_ENOMEM, "hipMalloc(four-step tables) failed")
+                                        : hip_err(e, "hipMalloc(four-step tables)");
+    e = launch_twiddle_rows(p->tw, p->fs_rows1, f->log2n1, f->log2e1, f->rows1, nullptr);
+    if (e == hipSuccess)
+        e = launch_twiddle_rows(p->tw, p->fs_rows2, f->log2n2, f->log2e2, f->rows2, nullptr);
+    if (e == hipSuccess)
+        e = launch_twiddle_big(p->fs_tw, static_cast<float2*>(p->fs_tw) + 1024, p->log2n, nullptr);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(nullptr);
+    if (e != hipSuccess)
+        return hip_err(e, "four-step tables");
     return FFT_OK;
 }
 
@@ -349,6 +426,9 @@ void free_plan(mifft_plan_s* p)
         (void)hipFree(p->rows);
     if (p->lg_rows)
         (void)hipFree(p->lg_rows);
+    for (void* q : {p->fs_rows1, p->fs_rows2, p->fs_tw})
+        if (q)
+            (void)hipFree(q);
     delete p;
 }
 
@@ -358,7 +438,22 @@ fft_plan create_batched(int64_t n, int64_t batch, int sign, int dtype, const Var
         return nullptr;
     const int log2n = ilog2(n);
     Variant v{};
-    if (dtype == FFT_C32) {
+    if (dtype == FFT_C32 && n > 2048) {
+        if (force) {
+            set_err(FFT_EINVAL_CONFIG, "lengths above 2048 have a single kernel variant");
+            return nullptr;
+        }
+        const FourStep* f = find_fourstep(log2n);
+        if (!f) {
+            set_err(FFT_EINVAL_N, "no four-step kernels for n=%lld", (long long)n);
+            return nullptr;
+        }
+        if (batch > 0x7fffffffLL / ((int64_t(1) << f->log2n2) / 16)) {
+            set_err(FFT_EINVAL_BATCH, "batch=%lld needs more than 2^31-1 workgroups", (long long)batch);
+            return nullptr;
+        }
+        v = Variant{f->log2e1, 0, 9};
+    } else if (dtype == FFT_C32) {
         if (force) {
             v = *force;
             if (!find_c32(log2n, v.log2ept, v.wg, -1, v.kind) || !find_c32(log2n, v.log2ept, v.wg, +1, v.kind)) {
@@ -396,13 +491,21 @@ fft_plan create_batched(int64_t n, int64_t batch, int sign, int dtype, const Var
     p->log2n = log2n;
     p->var = v;
     p->total = n * batch;
-    if (dtype == FFT_C32) {
+    if (dtype == FFT_C32 && n <= 2048) {
         p->fwd = find_c32(log2n, v.log2ept, v.wg, -1, v.kind);
         p->bwd = find_c32(log2n, v.log2ept, v.wg, +1, v.kind);
     }
     if (make_twiddles(p) != FFT_OK) {
         free_plan(p);
         return nullptr;
+    }
+    if (dtype == FFT_C32 && n > 2048) {
+        if (make_fourstep(p) != FFT_OK) {
+            free_plan(p);
+            return nullptr;
+        }
+        ok();
+        return p;
     }
     if (dtype == FFT_C32 && p->fwd->kind >= 1 && make_rows(p) != FFT_OK) {
         free_plan(p);
@@ -453,6 +556,14 @@ int exec_c32(fft_plan p, const void* in, void* out, int sign, float scale, hipSt
         int rc = ragged_execute(p->ragged, in, out, p->tw, sign, p->sign > 0, st);
         if (rc != FFT_OK)
             return set_err(rc, "%s", ragged_last_message());
+        return ok();
+    }
+    if (p->fs) {
+        const LaunchFourStep fn = sign < 0 ? p->fs->fwd : p->fs->bwd;
+        hipError_t e = fn(in, out, p->fs_rows1, p->fs_rows2, p->fs_tw, static_cast<const float2*>(p->fs_tw) + 1024,
+                          p->batch, scale, st);
+        if (e != hipSuccess)
+            return hip_err(e, "four-step kernel launch");
         return ok();
     }
     const KernelC32* k = sign < 0 ? p->fwd : p->bwd;
@@ -612,7 +723,7 @@ int fft_execute_loss_grad(fft_plan p, const void* x, const float* w, void* grad,
     if (!w || !loss)
         return set_err(FFT_ENULL, "w/loss pointer is NULL");
     if (p->kind != 0 || p->dtype != FFT_C32 || !p->lossgrad)
-        return set_err(FFT_EINVAL_DTYPE, "the fused loss is provided for batched FFT_C32 plans");
+        return set_err(FFT_EINVAL_DTYPE, "the fused loss is provided for batched FFT_C32 plans of n <= 2048");
     if ((reinterpret_cast<uintptr_t>(w) | reinterpret_cast<uintptr_t>(loss)) & 3)
         return set_err(FFT_EALIGN, "w/loss must be 4-byte aligned");
     const uintptr_t wb = reinterpret_cast<uintptr_t>(w), gb = reinterpret_cast<uintptr_t>(grad);

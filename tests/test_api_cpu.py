@@ -36,9 +36,18 @@ def q(n, batch=1, sign=-1, dtype=0):
     return rc, d
 
 
-@pytest.mark.parametrize("n", [0, 1, 3, 12, 4096, -8, 2049])
+@pytest.mark.parametrize("n", [0, 1, 3, 12, 1 << 21, -8, 2049, 4097])
 def test_bad_n(n):
     assert q(n)[0] == 1
+
+
+@pytest.mark.parametrize("L", range(12, 21))
+def test_large_lengths_plan_as_four_step(L):
+    n = 1 << L
+    rc, d = q(n, 3, -1)
+    assert rc == 0 and d.variant == 9
+    assert int(np.prod(list(d.radices)[: d.npasses])) == n
+    assert q(n, 3, -1, 1)[0] == 1  # above 2048 only FP32
 
 
 def test_bad_batch_sign_dtype_null():
