@@ -24,8 +24,9 @@ DEVICE_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
 
 def _units():
     units = []
-    for L in range(1, 12):
+    for L in range(1, 15):
         units.append(("fft_c32.hip", f"fft_c32_L{L}.o", [f"-DMIFFT_LOG2N={L}"]))
+    for L in range(1, 12):
         units.append(("fused_loss.hip", f"fused_loss_L{L}.o", [f"-DMIFFT_LOG2N={L}"]))
     units.append(("twiddle.hip", "twiddle.o", []))
     units.append(("fourstep.hip", "fourstep.o", []))

@@ -120,24 +120,29 @@ struct Variant {
 
 // Built-in choice per log2 N (index 1..11) for FP32: the autotuner's pick on
 // MI355X at 2^26 elements per launch (log2 EPT, workgroup size, variant).
-const Variant kDefaultC32[12] = {
-    {0, 0, 0},    // unused
-    {1, 64, 0},   // N=2     one thread per transform
-    {2, 128, 0},  // N=4
-    {3, 256, 0},  // N=8
-    {2, 256, 2},  // N=16
-    {3, 256, 1},  // N=32
-    {2, 128, 6},  // N=64    wavefront-local exchanges
-    {3, 64, 6},   // N=128
-    {3, 64, 6},   // N=256
-    {3, 64, 5},   // N=512
-    {4, 64, 3},   // N=1024  persistent, next-group prefetch
-    {4, 128, 3},  // N=2048  persistent, next-group prefetch
+const Variant kDefaultC32[21] = {
+    {0, 0, 0},     // unused
+    {1, 64, 0},    // N=2     one thread per transform
+    {2, 128, 0},   // N=4
+    {2, 256, 2},   // N=8
+    {2, 256, 2},   // N=16
+    {2, 256, 2},   // N=32
+    {2, 64, 6},    // N=64    wavefront-local exchanges
+    {3, 64, 6},    // N=128
+    {4, 256, 6},   // N=256
+    {3, 64, 6},    // N=512
+    {4, 64, 3},    // N=1024  persistent, next-group prefetch
+    {4, 128, 3},   // N=2048  persistent, next-group prefetch
+    {3, 512, 3},   // N=2^12  one transform per workgroup
+    {3, 1024, 3},  // N=2^13
+    {4, 1024, 2},  // N=2^14  135 KiB LDS
+    {0, 0, 9},     // N=2^15 .. 2^20: four-step (column + row pass)
+    {0, 0, 9}, {0, 0, 9}, {0, 0, 9}, {0, 0, 9}, {0, 0, 9},
 };
 
 std::once_flag g_tune_once;
-Variant g_tuned_c32[12];
-bool g_have_tuned_c32[12];
+Variant g_tuned_c32[21];
+bool g_have_tuned_c32[21];
 
 // MIFFT_TUNE_TABLE: text lines "c32 <log2n> <ept> <wg> <kind>"; '#' starts a comment.
 void load_tune_table()
@@ -158,8 +163,8 @@ void load_tune_table()
             continue;
         if (!(ss >> kind))
             kind = 0;
-        if (dt == "c32" && l >= 1 && l <= 11 && is_pow2(ept) && ept >= 2 && ept <= 16) {
-            g_tuned_c32[l] = Variant{ilog2(ept), wg, kind};
+        if (dt == "c32" && l >= 1 && l <= 20 && ((is_pow2(ept) && ept >= 2 && ept <= 16) || kind == 9)) {
+            g_tuned_c32[l] = Variant{kind == 9 ? 0 : ilog2(ept), wg, kind};
             g_have_tuned_c32[l] = true;
         }
     }
@@ -170,7 +175,7 @@ Variant choose_c32(int log2n)
     std::call_once(g_tune_once, load_tune_table);
     if (g_have_tuned_c32[log2n]) {
         const Variant v = g_tuned_c32[log2n];
-        if (find_c32(log2n, v.log2ept, v.wg, -1, v.kind))
+        if ((v.kind == 9 && log2n > 11) || find_c32(log2n, v.log2ept, v.wg, -1, v.kind))
             return v;
     }
     return kDefaultC32[log2n];
@@ -265,7 +270,7 @@ int fill_desc_fourstep(int64_t n, int64_t batch, int sign, int dtype, fft_plan_d
 
 int fill_desc_c32(int64_t n, int64_t batch, int sign, int dtype, Variant v, int64_t grid_limit, fft_plan_desc* d)
 {
-    if (n > 2048)
+    if (v.kind == 9)
         return fill_desc_fourstep(n, batch, sign, dtype, d);
     memset(d, 0, sizeof *d);
     const int log2n = ilog2(n);
@@ -438,11 +443,9 @@ fft_plan create_batched(int64_t n, int64_t batch, int sign, int dtype, const Var
         return nullptr;
     const int log2n = ilog2(n);
     Variant v{};
-    if (dtype == FFT_C32 && n > 2048) {
-        if (force) {
-            set_err(FFT_EINVAL_CONFIG, "lengths above 2048 have a single kernel variant");
-            return nullptr;
-        }
+    const bool four_step = dtype == FFT_C32 && n > 2048 &&
+                           (force ? force->kind == 9 : choose_c32(log2n).kind == 9);
+    if (four_step) {
         const FourStep* f = find_fourstep(log2n);
         if (!f) {
             set_err(FFT_EINVAL_N, "no four-step kernels for n=%lld", (long long)n);
@@ -491,7 +494,7 @@ fft_plan create_batched(int64_t n, int64_t batch, int sign, int dtype, const Var
     p->log2n = log2n;
     p->var = v;
     p->total = n * batch;
-    if (dtype == FFT_C32 && n <= 2048) {
+    if (dtype == FFT_C32 && !four_step) {
         p->fwd = find_c32(log2n, v.log2ept, v.wg, -1, v.kind);
         p->bwd = find_c32(log2n, v.log2ept, v.wg, +1, v.kind);
     }
@@ -499,7 +502,7 @@ fft_plan create_batched(int64_t n, int64_t batch, int sign, int dtype, const Var
         free_plan(p);
         return nullptr;
     }
-    if (dtype == FFT_C32 && n > 2048) {
+    if (four_step) {
         if (make_fourstep(p) != FFT_OK) {
             free_plan(p);
             return nullptr;
@@ -511,7 +514,7 @@ fft_plan create_batched(int64_t n, int64_t batch, int sign, int dtype, const Var
         free_plan(p);
         return nullptr;
     }
-    if (dtype == FFT_C32 && make_loss_grad(p) != FFT_OK) {
+    if (dtype == FFT_C32 && n <= 2048 && make_loss_grad(p) != FFT_OK) {
         free_plan(p);
         return nullptr;
     }
@@ -590,13 +593,17 @@ fft_plan fft_plan_create_config(int64_t n, int64_t batch, int sign, int dtype, i
         set_err(FFT_EINVAL_DTYPE, "fft_plan_create_config selects FP32 variants only");
         return nullptr;
     }
-    if (!is_pow2(ept) || ept < 2 || ept > 16 || !is_pow2(wg) || wg < 64 || wg > 512 || variant < 0 ||
-        variant > 8) {
-        set_err(FFT_EINVAL_CONFIG, "ept=%d must be 2..16, wg=%d 64..512 (powers of two), variant=%d 0..8", ept,
-                wg, variant);
+    if (variant != 9 && (!is_pow2(ept) || ept < 2 || ept > 16 || !is_pow2(wg) || wg < 64 || wg > 1024 ||
+                         variant < 0 || variant > 8)) {
+        set_err(FFT_EINVAL_CONFIG, "ept=%d must be 2..16, wg=%d 64..1024 (powers of two), variant=%d 0..9",
+                ept, wg, variant);
         return nullptr;
     }
-    Variant v{ilog2(ept), wg, variant};
+    if (variant == 9 && n <= 2048) {
+        set_err(FFT_EINVAL_CONFIG, "the four-step variant is for n > 2048");
+        return nullptr;
+    }
+    Variant v{variant == 9 ? 0 : ilog2(ept), variant == 9 ? 0 : wg, variant};
     return create_batched(n, batch, sign, dtype, &v);
 }
 

@@ -237,6 +237,7 @@ __device__ __forceinline__ void pass_compute(cf (&v)[1 << LOG2EPT], int t, const
     constexpr int EPT = SC::EPT, TPT = SC::TPT, Q = EPT / R;
     if constexpr (NS > 1) {
         constexpr int SHIFT = 11 - LNS - LR;
+        static_assert(SHIFT >= 0, "the 2048-entry table resolves twiddles of passes up to NS R = 2048");
 #pragma unroll
         for (int q = 0; q < Q; q++) {
             const int j = t + q * TPT;
@@ -318,6 +319,9 @@ constexpr int pad_bits(int L, int E, int P)
         if (L == 9) return 5;
         if (L == 10) return P == 0 ? 5 : 6;
         if (L == 11) return P == 0 ? 5 : 3;
+        if (L == 12) return P == 0 ? 5 : 4;
+        if (L == 13) return 5;
+        if (L == 14) return P == 1 ? 6 : 5;
     } else if (E == 3) {
         if (L == 4) return 1;
         if (L == 5) return 2;
@@ -327,6 +331,9 @@ constexpr int pad_bits(int L, int E, int P)
         if (L == 9) return P == 0 ? 5 : 3;
         if (L == 10) return P == 2 ? 7 : 5;
         if (L == 11) return P == 1 ? 2 : 5;
+        if (L == 12) return P == 1 ? 3 : 5;
+        if (L == 13) return P == 2 ? 7 : 5;
+        if (L == 14) return P == 1 ? 2 : 5;
     } else if (E == 2) {
         if (L == 3) return 1;
         if (L == 4) return 2;

@@ -13,7 +13,7 @@
 #include "registry.hpp"
 
 #ifndef MIFFT_LOG2N
-#error "compile with -DMIFFT_LOG2N=<1..11>"
+#error "compile with -DMIFFT_LOG2N=<1..14>"
 #endif
 
 namespace mifft {
@@ -137,6 +137,12 @@ __global__ __launch_bounds__(WG) void k_fft_c32_v2(const cf* __restrict__ in, cf
         load_all_rows<L, E, S>(tws, rows, t);
     cf a[EPT], b[EPT];
     load_group<L, E, TPB>(a, in, g, batch, tb, toff8);
+    if constexpr (!PF) {
+        // one group per workgroup (the grid covers every group)
+        run2<L, E, S, TW, WAVE>(a, t, rows, tws, my);
+        store_group<L, E, TPB>(a, out, g, batch, tb, toff8, scale);
+        return;
+    }
     const int64_t stride = gridDim.x;
     while (true) {
         int64_t g1 = g + stride;
@@ -207,7 +213,7 @@ int occupancy_v2()
 template <int LOG2N, int LOG2EPT, int WG>
 constexpr bool valid_cfg()
 {
-    if constexpr (LOG2EPT > LOG2N) {
+    if constexpr (LOG2EPT > LOG2N || LOG2N > 11) {
         return false;
     } else {
         constexpr int TPT = (1 << LOG2N) >> LOG2EPT;
@@ -219,11 +225,18 @@ constexpr bool valid_cfg()
     }
 }
 
-// v2: EPT in {4, 8, 16}, at least two threads per transform, WG <= 256.
+// v2: EPT in {4, 8, 16}, at least two threads per transform, WG <= 256
+// and LDS <= 64 KiB; lengths above 2048 (up to 2^14): EPT 8 or 16, one
+// transform per workgroup of up to 1024 threads and up to 160 KiB of LDS.
 template <int L, int E, int WG>
 constexpr bool valid_v2()
 {
-    if constexpr (E < 2 || E >= L || WG > 256) {
+    if constexpr (E < 2 || E >= L) {
+        return false;
+    } else if constexpr (L > 11) {
+        constexpr int TPT = (1 << L) >> E;
+        return E >= 3 && TPT == WG && WG <= 1024 && Layout2<L, E>::region() * 8 <= 160 * 1024;
+    } else if constexpr (WG > 256) {
         return false;
     } else {
         constexpr int TPT = (1 << L) >> E;
@@ -280,6 +293,7 @@ void add_wgs()
     add_signs<LOG2N, LOG2EPT, 128>();
     add_signs<LOG2N, LOG2EPT, 256>();
     add_signs<LOG2N, LOG2EPT, 512>();
+    add_signs<LOG2N, LOG2EPT, 1024>();
 }
 
 struct Registrar {

@@ -61,9 +61,10 @@ namespace mifft {
 
 // Per-pass twiddle rows of a (log2 N, log2 EPT) Stockham schedule: for each
 // pass with NS > 1 (radix EPT), NS rows of EPT entries, row k holding
-// w_{NS EPT}^{r k} = tw[(r k) * 2048 / (NS EPT)], r < EPT.  The entries are
-// copies of the 2048-entry table, so both kernel families use identical
-// twiddle values.
+// w_M^{r k}, M = NS EPT, r < EPT.  When M <= 2048 the entry is the copy
+// tw[(r k) * 2048 / M] of the 2048-entry table, so every kernel family uses
+// identical twiddles; for longer transforms (M > 2048, which the table does
+// not resolve) it is evaluated here in FP64 with sincospi and rounded once.
 __global__ void k_twiddle_rows(const float2* __restrict__ tw, float2* __restrict__ rows, int L, int E, int total)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -80,7 +81,14 @@ __global__ void k_twiddle_rows(const float2* __restrict__ tw, float2* __restrict
         if (i < off + size) {
             const int k = (i - off) >> E;
             const int r = (i - off) & ((1 << E) - 1);
-            rows[i] = tw[(r * k) << (11 - lns - E)];
+            const int shift = 11 - lns - E;
+            if (shift >= 0) {
+                rows[i] = tw[(r * k) << shift];
+            } else {
+                double sn, cs;
+                sincospi(2.0 * (double)(r * k) / (double)(1 << (lns + E)), &sn, &cs);
+                rows[i] = float2{(float)cs, (float)(-sn)};
+            }
             return;
         }
         off += size;

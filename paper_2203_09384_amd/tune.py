@@ -20,8 +20,8 @@ import math
 import sys
 
 EPTS = (2, 4, 8, 16)
-WGS = (64, 128, 256, 512)
-VARIANTS = tuple(range(9))
+WGS = (64, 128, 256, 512, 1024)
+VARIANTS = tuple(range(10))  # 9: four-step, lengths above 2048 only
 
 
 def _time(fn, steps, warmup, torch):
@@ -38,7 +38,7 @@ def _time(fn, steps, warmup, torch):
     return a.elapsed_time(b) / steps
 
 
-def tune_c32(total: int = 1 << 26, steps: int = 30, warmup: int = 5, log2ns=range(1, 12), log=print):
+def tune_c32(total: int = 1 << 26, steps: int = 30, warmup: int = 5, log2ns=range(1, 15), log=print):
     import torch
     from . import api, synth
     from .native import MifftError
@@ -52,6 +52,8 @@ def tune_c32(total: int = 1 << 26, steps: int = 30, warmup: int = 5, log2ns=rang
         for ept in EPTS:
             for wg in WGS:
                 for var in VARIANTS:
+                    if var == 9 and (L <= 11 or ept != EPTS[0] or wg != WGS[0]):
+                        continue
                     try:
                         p = api.Plan(n, b, -1, ept=ept, wg=wg, variant=var)
                     except MifftError:

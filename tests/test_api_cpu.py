@@ -42,10 +42,12 @@ def test_bad_n(n):
 
 
 @pytest.mark.parametrize("L", range(12, 21))
-def test_large_lengths_plan_as_four_step(L):
+def test_large_lengths_plan(L):
+    """2^12..2^14: one pass with the whole transform in one workgroup's LDS;
+    above: the two-pass four-step split (variant 9)."""
     n = 1 << L
     rc, d = q(n, 3, -1)
-    assert rc == 0 and d.variant == 9
+    assert rc == 0 and (d.variant == 9) == (L > 14)
     assert int(np.prod(list(d.radices)[: d.npasses])) == n
     assert q(n, 3, -1, 1)[0] == 1  # above 2048 only FP32
 
