@@ -19,6 +19,11 @@ subsection), plus the compositions the hot path needs:
                             batch of mixed power-of-two lengths
 * ``loss_grad``             L = sum w |F x|^2 and its PyTorch-convention
                             gradient F^H (2 w * F x)
+* ``rfft`` / ``irfft``      real input: the first N/2 + 1 bins of Eq. (dft)
+                            of x + 0i; its inverse, Eq. (idft) of the
+                            Hermitian extension of N/2 + 1 bins, real part
+* ``rfft_adjoint`` / ``irfft_adjoint``  the adjoints of those two real-linear
+                            maps (the gradients PyTorch takes through them)
 
 Readings of the paper that these functions take (the inverse carries 1/N,
 the adjoint keeps the plan's scale, inputs and outputs in natural order)
@@ -131,6 +136,61 @@ class Oracle:
         grad = self.adjoint(2.0 * w * y, sign=-1, scale=1.0, threads=threads)
         return loss, grad
 
+    # -------------------------------------------------------- real input
+    # A real sequence is a complex one with zero imaginary parts (the paper
+    # allows real- or complex-valued input to Eq. (dft)); its spectrum is
+    # Hermitian, X_{N-k} = conj(X_k), so bins 0..N/2 determine it.
+
+    def rfft(self, x, threads=None):
+        """X_k = sum_n x_n w_N^{kn} for real x and k = 0..N/2."""
+        x = np.asarray(x, dtype=np.float64)
+        n = x.shape[-1]
+        return self.forward(x.astype(np.complex128), threads)[..., : n // 2 + 1]
+
+    @staticmethod
+    def hermitian_extension(X, n: int):
+        """The length-n spectrum whose bins 0..n/2 are X (Im of bins 0 and
+        n/2 dropped: a real sequence has them real) and whose bins
+        n/2+1..n-1 are conj(X_{n-k})."""
+        X = np.asarray(X, dtype=np.complex128)
+        m = n // 2
+        if X.shape[-1] != m + 1:
+            raise ValueError(f"{X.shape[-1]} bins given, n={n} needs {m + 1}")
+        full = np.empty(X.shape[:-1] + (n,), np.complex128)
+        full[..., : m + 1] = X
+        full[..., 0] = X[..., 0].real
+        full[..., m] = X[..., m].real
+        full[..., m + 1:] = np.conj(X[..., 1:m][..., ::-1])
+        return full
+
+    def irfft(self, X, n: int, threads=None):
+        """x_j = (1/n) sum_k Xfull_k w_n^{-jk} (Eq. (idft)) over the
+        Hermitian extension Xfull of X; the result is real."""
+        return self.inverse(self.hermitian_extension(X, n), threads).real
+
+    def rfft_adjoint(self, g, n: int, threads=None):
+        """Adjoint of x -> rfft(x) from real n-vectors to complex
+        (n/2+1)-vectors under Re<a, b>: x_j = Re sum_{k<=n/2} g_k w_n^{-jk}."""
+        g = np.asarray(g, dtype=np.complex128)
+        padded = np.zeros(g.shape[:-1] + (n,), np.complex128)
+        padded[..., : n // 2 + 1] = g
+        return self.fft(padded, +1, 1.0, threads).real
+
+    def irfft_adjoint(self, v, threads=None):
+        """Adjoint of X -> irfft(X, n), composed from the adjoints of its
+        three steps: real part (embed v as complex), the inverse DFT
+        (adjoint: sign -1, scale 1/n) and the Hermitian extension (adjoint:
+        Y_k + conj(Y_{n-k}) for 0 < k < n/2, Re Y_k at k = 0 and n/2)."""
+        v = np.asarray(v, dtype=np.float64)
+        n = v.shape[-1]
+        m = n // 2
+        Y = self.adjoint(v.astype(np.complex128), +1, 1.0 / n, threads)
+        out = np.empty(v.shape[:-1] + (m + 1,), np.complex128)
+        out[..., 1:m] = Y[..., 1:m] + np.conj(Y[..., n - 1:m:-1])
+        out[..., 0] = Y[..., 0].real
+        out[..., m] = Y[..., m].real
+        return out
+
     def mutant_id(self) -> int:
         return int(self.h.oracle_mutant_id())
 
@@ -142,3 +202,8 @@ inverse = _default.inverse
 adjoint = _default.adjoint
 fft_ragged = _default.fft_ragged
 loss_grad = _default.loss_grad
+rfft = _default.rfft
+irfft = _default.irfft
+rfft_adjoint = _default.rfft_adjoint
+irfft_adjoint = _default.irfft_adjoint
+hermitian_extension = Oracle.hermitian_extension

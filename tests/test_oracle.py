@@ -224,3 +224,184 @@ def test_pins_catch_planted_mistakes(mutant, mutant_libs):
         except AssertionError:
             caught.append(pin.__name__)
     assert caught, f"mutant {mutant} passed every pin"
+
+
+# ---------------------------------------------------------------- real input
+# rfft / irfft and their adjoints are compositions over the complex oracle
+# (Eq. (dft) of x + 0i, Hermitian extension, Eq. (idft)).  They get pins of
+# their own, and planted mistakes in those compositions must fail one.
+
+REAL_N = [2, 4, 8, 16, 64, 2048]
+
+
+def _real_direct_forward(x):
+    """Eq. (dft) for real x, bins 0..N/2 only, as an explicit O(N^2) sum."""
+    n = x.shape[-1]
+    kn = np.outer(np.arange(n // 2 + 1), np.arange(n)) % n
+    return x @ np.exp(-2j * np.pi * kn / n).T
+
+
+def _real_direct_inverse(X, n):
+    """The textbook real inverse: x_j = (1/N)[Re X_0 + Re X_{N/2} (-1)^j
+    + 2 sum_{0<k<N/2} Re(X_k e^{2 pi i jk/N})], as an explicit sum."""
+    m = n // 2
+    j = np.arange(n)
+    out = X[..., :1].real + X[..., m:m + 1].real * ((-1.0) ** j)
+    if m > 1:
+        kj = np.outer(np.arange(1, m), j) % n
+        out = out + 2.0 * (X[..., 1:m] @ np.exp(2j * np.pi * kj / n)).real
+    return out / n
+
+
+def rpin_brute_force(orc):
+    for n in REAL_N[:5]:
+        x = synth.uniform_complex(47, (3, n), key=(n,), dtype=np.complex128).real.copy()
+        assert relerr(orc.rfft(x), _real_direct_forward(x)) < 1e-13, n
+        X = synth.uniform_complex(47, (3, n // 2 + 1), key=(n, 1), dtype=np.complex128)
+        assert relerr(orc.irfft(X, n), _real_direct_inverse(X, n)) < 1e-13, n
+
+
+def rpin_numpy_library(orc):
+    for n in REAL_N:
+        x = synth.uniform_complex(53, (4, n), key=(n,), dtype=np.complex128).real.copy()
+        assert relerr(orc.rfft(x), np.fft.rfft(x, axis=-1)) < 1e-13, n
+        # edge bins with nonzero imaginary parts: numpy ignores them too
+        X = synth.uniform_complex(53, (4, n // 2 + 1), key=(n, 1), dtype=np.complex128)
+        assert relerr(orc.irfft(X, n), np.fft.irfft(X, n, axis=-1)) < 1e-13, n
+
+
+def rpin_ramp_closed_form(orc):
+    """The paper's f(x) = x is real: X_0 = N(N-1)/2, X_k = -N/2 + i (N/2) cot(pi k/N)."""
+    for n in POW2_ALL:
+        k = np.arange(1, n // 2 + 1)
+        want = np.empty(n // 2 + 1, np.complex128)
+        want[0] = n * (n - 1) / 2
+        want[1:] = -n / 2 + 1j * (n / 2) * np.cos(np.pi * k / n) / np.sin(np.pi * k / n)
+        got = orc.rfft(np.arange(n, dtype=np.float64))
+        assert relerr(got, want) < 1e-13, n
+        assert np.max(np.abs(orc.irfft(want, n) - np.arange(n))) < 1e-10 * n, n
+
+
+def rpin_adjoint_identities(orc):
+    """Re<R x, g> = <x, R^H g> and <C X, v> = Re<X, C^H v> (real inner products)."""
+    for n in REAL_N:
+        x = synth.uniform_complex(59, (3, n), key=(n, 0), dtype=np.complex128).real.copy()
+        g = synth.uniform_complex(59, (3, n // 2 + 1), key=(n, 1), dtype=np.complex128)
+        lhs = np.sum((orc.rfft(x) * np.conj(g)).real)
+        rhs = np.sum(x * orc.rfft_adjoint(g, n))
+        assert abs(lhs - rhs) < 1e-12 * max(abs(lhs), 1.0), n
+        X = synth.uniform_complex(59, (3, n // 2 + 1), key=(n, 2), dtype=np.complex128)
+        v = synth.uniform_complex(59, (3, n), key=(n, 3), dtype=np.complex128).real.copy()
+        lhs = np.sum(orc.irfft(X, n) * v)
+        rhs = np.sum((X * np.conj(orc.irfft_adjoint(v))).real)
+        assert abs(lhs - rhs) < 1e-12 * max(abs(lhs), 1e-3), n
+
+
+def rpin_gradient_fd(orc):
+    """Finite differences of quadratic losses through rfft and irfft (exact up
+    to rounding for any step) pin the adjoints in PyTorch's convention."""
+    n, h = 16, 1e-2
+    x = synth.uniform_complex(61, (2, n), dtype=np.complex128).real.copy()
+    w = synth.uniform_weights(61, (2, n // 2 + 1), key=(1,), dtype=np.float64)
+    g = orc.rfft_adjoint(2.0 * w * _real_direct_forward(x), n)
+    fd = np.zeros_like(x)
+    for b in range(2):
+        for i in range(n):
+            e = np.zeros_like(x)
+            e[b, i] = h
+            fd[b, i] = (np.sum(w * np.abs(_real_direct_forward(x + e)) ** 2)
+                        - np.sum(w * np.abs(_real_direct_forward(x - e)) ** 2)) / (2 * h)
+    assert relerr(g, fd) < 1e-11
+    X = synth.uniform_complex(61, (2, n // 2 + 1), key=(2,), dtype=np.complex128)
+    u = synth.uniform_weights(61, (2, n), key=(3,), dtype=np.float64)
+    gX = orc.irfft_adjoint(2.0 * u * _real_direct_inverse(X, n))
+    fdX = np.zeros_like(X)
+    for b in range(2):
+        for i in range(n // 2 + 1):
+            for unit in (1.0, 1j):
+                e = np.zeros_like(X)
+                e[b, i] = unit * h
+                d = (np.sum(u * _real_direct_inverse(X + e, n) ** 2)
+                     - np.sum(u * _real_direct_inverse(X - e, n) ** 2)) / (2 * h)
+                fdX[b, i] += unit * d
+    assert relerr(gX, fdX) < 1e-11
+
+
+REAL_PINS = [rpin_brute_force, rpin_numpy_library, rpin_ramp_closed_form,
+             rpin_adjoint_identities, rpin_gradient_fd]
+
+
+@pytest.mark.parametrize("pin", REAL_PINS, ids=lambda p: p.__name__)
+def test_real_oracle_pin(pin):
+    pin(Oracle())
+
+
+class _ExtNoConj(Oracle):
+    @staticmethod
+    def hermitian_extension(X, n):
+        full = Oracle.hermitian_extension(X, n)
+        m = n // 2
+        full[..., m + 1:] = X[..., 1:m][..., ::-1]
+        return full
+
+
+class _ExtMirrorOffByOne(Oracle):
+    @staticmethod
+    def hermitian_extension(X, n):
+        full = Oracle.hermitian_extension(X, n)
+        m = n // 2
+        full[..., m + 1:] = np.conj(X[..., 2:m + 1][..., ::-1])
+        return full
+
+
+class _ExtNoReversal(Oracle):
+    @staticmethod
+    def hermitian_extension(X, n):
+        full = Oracle.hermitian_extension(X, n)
+        m = n // 2
+        full[..., m + 1:] = np.conj(X[..., 1:m])
+        return full
+
+
+class _RfftAdjointWrongSign(Oracle):
+    def rfft_adjoint(self, g, n, threads=None):
+        padded = np.zeros(np.shape(g)[:-1] + (n,), np.complex128)
+        padded[..., : n // 2 + 1] = g
+        return self.fft(padded, -1, 1.0, threads).real
+
+
+class _IrfftAdjointOneSided(Oracle):
+    def irfft_adjoint(self, v, threads=None):
+        out = Oracle.irfft_adjoint(self, v, threads)
+        n = np.shape(v)[-1]
+        Y = self.adjoint(np.asarray(v, np.complex128), +1, 1.0 / n, threads)
+        out[..., 1:n // 2] = Y[..., 1:n // 2]
+        return out
+
+
+class _IrfftAdjointNoScale(Oracle):
+    def irfft_adjoint(self, v, threads=None):
+        return Oracle.irfft_adjoint(self, v, threads) * np.shape(v)[-1]
+
+
+class _RfftDropsNyquist(Oracle):
+    def rfft(self, x, threads=None):
+        X = Oracle.rfft(self, x, threads)
+        X[..., -1] = 0
+        return X
+
+
+REAL_MUTANTS = [_ExtNoConj, _ExtMirrorOffByOne, _ExtNoReversal, _RfftAdjointWrongSign,
+                _IrfftAdjointOneSided, _IrfftAdjointNoScale, _RfftDropsNyquist]
+
+
+@pytest.mark.parametrize("mutant", REAL_MUTANTS, ids=lambda m: m.__name__)
+def test_real_pins_catch_planted_mistakes(mutant):
+    orc = mutant()
+    caught = []
+    for pin in REAL_PINS:
+        try:
+            pin(orc)
+        except AssertionError:
+            caught.append(pin.__name__)
+    assert caught, f"{mutant.__name__} passed every real-input pin"
