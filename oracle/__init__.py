@@ -24,6 +24,10 @@ subsection), plus the compositions the hot path needs:
                             Hermitian extension of N/2 + 1 bins, real part
 * ``rfft_adjoint`` / ``irfft_adjoint``  the adjoints of those two real-linear
                             maps (the gradients PyTorch takes through them)
+* ``fftn``                  multidimensional transform over the trailing
+                            axes: the kernel exp(sign 2 pi i sum_a k_a n_a / N_a)
+                            factors into one per axis, so it is the 1D
+                            transform applied along each axis in turn
 
 Readings of the paper that these functions take (the inverse carries 1/N,
 the adjoint keeps the plan's scale, inputs and outputs in natural order)
@@ -191,6 +195,16 @@ class Oracle:
         out[..., m] = Y[..., m].real
         return out
 
+    # -------------------------------------------------------- multidimensional
+    def fftn(self, x, ndim: int, sign: int = -1, scale: float = 1.0, threads=None):
+        """X[k] = scale * sum_n x[n] prod_a exp(sign 2 pi i k_a n_a / N_a) over
+        the last `ndim` axes of x (the leading axes are the batch)."""
+        y = np.asarray(x, dtype=np.complex128)
+        for ax in range(y.ndim - ndim, y.ndim):
+            moved = np.moveaxis(y, ax, -1)
+            y = np.moveaxis(self.fft(moved, sign, 1.0, threads), -1, ax)
+        return y * scale
+
     def mutant_id(self) -> int:
         return int(self.h.oracle_mutant_id())
 
@@ -207,3 +221,4 @@ irfft = _default.irfft
 rfft_adjoint = _default.rfft_adjoint
 irfft_adjoint = _default.irfft_adjoint
 hermitian_extension = Oracle.hermitian_extension
+fftn = _default.fftn

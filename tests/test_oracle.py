@@ -405,3 +405,95 @@ def test_real_pins_catch_planted_mistakes(mutant):
         except AssertionError:
             caught.append(pin.__name__)
     assert caught, f"{mutant.__name__} passed every real-input pin"
+
+
+# ---------------------------------------------------------------- multidimensional
+def _direct_dft2(x, sign):
+    """The 2D DFT as one explicit double sum over (n1, n2) for each (k1, k2),
+    the exponents k_a n_a reduced modulo N_a in integers."""
+    n1, n2 = x.shape[-2:]
+    out = np.zeros(x.shape, np.complex128)
+    a1 = np.arange(n1)
+    a2 = np.arange(n2)
+    for k1 in range(n1):
+        for k2 in range(n2):
+            ph = (np.outer((k1 * a1) % n1, np.ones(n2)) / n1 + np.outer(np.ones(n1), (k2 * a2) % n2) / n2)
+            out[..., k1, k2] = np.sum(x * np.exp(sign * 2j * np.pi * ph), axis=(-2, -1))
+    return out
+
+
+def npin_brute_force(orc):
+    for shape in ((2, 2), (4, 8), (8, 2), (16, 4)):
+        x = synth.uniform_complex(67, (3,) + shape, key=shape, dtype=np.complex128)
+        assert relerr(orc.fftn(x, 2), _direct_dft2(x, -1)) < 1e-13, shape
+        n = shape[0] * shape[1]
+        assert relerr(orc.fftn(x, 2, +1, 1.0 / n), _direct_dft2(x, +1) / n) < 1e-13, shape
+
+
+def npin_numpy_library(orc):
+    for shape in ((32, 64), (2, 1024), (8, 4, 16), (2, 2, 2)):
+        x = synth.uniform_complex(71, (2,) + shape, key=shape, dtype=np.complex128)
+        axes = tuple(range(1, 1 + len(shape)))
+        assert relerr(orc.fftn(x, len(shape)), np.fft.fftn(x, axes=axes)) < 1e-13, shape
+        n = int(np.prod(shape))
+        assert relerr(orc.fftn(x, len(shape), +1, 1.0 / n), np.fft.ifftn(x, axes=axes)) < 1e-13, shape
+
+
+def npin_separable_and_invariants(orc):
+    """An outer product of 1D signals has the outer product of their 1D
+    spectra; impulses give plane waves; Parseval; round trip."""
+    for n1, n2 in ((8, 16), (64, 32)):
+        u = synth.uniform_complex(73, (n1,), key=(n1, n2, 0), dtype=np.complex128)
+        v = synth.uniform_complex(73, (n2,), key=(n1, n2, 1), dtype=np.complex128)
+        want = np.outer(np.fft.fft(u), np.fft.fft(v))
+        assert relerr(orc.fftn(np.outer(u, v), 2), want) < 1e-13
+        x = np.zeros((n1, n2), np.complex128)
+        x[3, 5] = 1.0
+        k1, k2 = np.meshgrid(np.arange(n1), np.arange(n2), indexing="ij")
+        plane = np.exp(-2j * np.pi * (((3 * k1) % n1) / n1 + ((5 * k2) % n2) / n2))
+        assert np.max(np.abs(orc.fftn(x, 2) - plane)) < 1e-13
+        y = synth.uniform_complex(73, (2, n1, n2), key=(n1, n2, 2), dtype=np.complex128)
+        Y = orc.fftn(y, 2)
+        assert np.max(np.abs(np.sum(np.abs(Y) ** 2, axis=(1, 2)) / (n1 * n2 * np.sum(np.abs(y) ** 2, axis=(1, 2))) - 1)) < 1e-13
+        assert relerr(orc.fftn(Y, 2, +1, 1.0 / (n1 * n2)), y) < 1e-14
+
+
+ND_PINS = [npin_brute_force, npin_numpy_library, npin_separable_and_invariants]
+
+
+@pytest.mark.parametrize("pin", ND_PINS, ids=lambda p: p.__name__)
+def test_nd_oracle_pin(pin):
+    pin(Oracle())
+
+
+class _NdSkipsFirstAxis(Oracle):
+    def fftn(self, x, ndim, sign=-1, scale=1.0, threads=None):
+        return Oracle.fftn(self, x, ndim - 1, sign, scale, threads)
+
+
+class _NdSwapsSign(Oracle):
+    def fftn(self, x, ndim, sign=-1, scale=1.0, threads=None):
+        y = np.asarray(x, dtype=np.complex128)
+        for i, ax in enumerate(range(y.ndim - ndim, y.ndim)):
+            moved = np.moveaxis(y, ax, -1)
+            y = np.moveaxis(self.fft(moved, sign if i else -sign, 1.0, threads), -1, ax)
+        return y * scale
+
+
+class _NdTransposesResult(Oracle):
+    def fftn(self, x, ndim, sign=-1, scale=1.0, threads=None):
+        y = Oracle.fftn(self, x, ndim, sign, scale, threads)
+        return np.swapaxes(y, -1, -2).reshape(y.shape)
+
+
+@pytest.mark.parametrize("mutant", [_NdSkipsFirstAxis, _NdSwapsSign, _NdTransposesResult],
+                         ids=lambda m: m.__name__)
+def test_nd_pins_catch_planted_mistakes(mutant):
+    orc = mutant()
+    caught = []
+    for pin in ND_PINS:
+        try:
+            pin(orc)
+        except AssertionError:
+            caught.append(pin.__name__)
+    assert caught, f"{mutant.__name__} passed every multidimensional pin"
