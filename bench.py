@@ -118,6 +118,30 @@ def bench_half(api, synth, torch, dev, steps, ms_fp32, x_all):
     return res
 
 
+def bench_real(api, torch, dev, steps, x_all):
+    """Real-input transforms, n = 2048, batch 65536: R2C (512 MiB of float32
+    reals in, 65536 x 1025 complex64 bins out) and C2R back."""
+    n, batch = 2048, 65536
+    xr = torch.view_as_real(x_all).view(batch, n)
+    bins = torch.empty(batch, n // 2 + 1, dtype=torch.complex64, device=dev)
+    back = torch.empty(batch, n, dtype=torch.float32, device=dev)
+    alg = batch * (4.0 * n + 8.0 * (n // 2 + 1))
+    res = {"workload": "real-input FFT, n=2048, batch 65536: R2C float32 (512 MiB) -> 1025 complex64 "
+                       "bins per transform, and C2R back; one fused kernel each (half-length complex "
+                       "FFT plus the even/odd split)"}
+    for nm, sign, a, b in (("r2c", -1, xr, bins), ("c2r", +1, bins, back)):
+        p = api.Plan(n, batch, sign, dtype="r32")
+        m = time_launches(lambda: p.execute(a, b), steps, 10, torch)
+        d = p.describe()
+        res[nm] = {"us": round(m * 1e3, 2), "GBps": round(alg / (m * 1e-3) / 1e9, 1),
+                   "GFLOPs_2.5nlogn": round(2.5 * n * 11 * batch / (m * 1e-3) / 1e9, 1),
+                   "ept": d["ept"], "wg": d["wg"], "variant": d["variant"]}
+        p.close()
+    res["algorithmic_bytes_per_launch"] = alg
+    del bins, back
+    return res
+
+
 def bench_ragged(api, synth, torch, dev, iters):
     """One persistent launch over 4096 mixed-length transforms (eager and
     graph-replayed) against per-length plain launches (eager and in one
@@ -346,7 +370,7 @@ def main():
             large.append({"n": nn, "batch": bb, "us": round(m * 1e3, 2),
                           "GFLOPs": round(5.0 * nn * L * bb / (m * 1e-3) / 1e9, 1),
                           "GBps_algorithmic": round(bytes_alg / (m * 1e-3) / 1e9, 1),
-                          "passes_over_hbm": 2})
+                          "passes_over_hbm": 2 if p.describe()["variant"] == 9 else 1})
             p.close()
         out["large_n"] = large
         log(f"[bench] large {large}")
@@ -354,6 +378,10 @@ def main():
         # ------------------------------------------------------------ FP16 / BF16
         out["half"] = bench_half(api, synth, torch, dev, args.steps, ms, x_all)
         log(f"[bench] half {out['half']}")
+
+        # ------------------------------------------------------------ real input
+        out["real"] = bench_real(api, torch, dev, args.steps, x_all)
+        log(f"[bench] real {out['real']}")
 
         # ------------------------------------------------------------ ragged
         out["ragged"] = bench_ragged(api, synth, torch, dev, max(200, args.steps * 5))

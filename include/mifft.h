@@ -8,14 +8,27 @@
  * for every transform of a batch, by Cooley-Tukey / Stockham passes of
  * radix 2..16 (section "Implementation": radix-2/4/8 stages selected on
  * the host from N; single precision, complex-to-complex, out of place,
- * N up to 2^11), extended here to 2^20 by the four-step split.  Both
- * input and output are in natural order.
+ * N up to 2^11), extended here to 2^14 in one pass and to 2^20 by the
+ * four-step split.  Both input and output are in natural order.
+ *
+ * Real input (FFT_R32; the paper's inputs may be real- or complex-valued,
+ * section "Fast Fourier Transform"): a real sequence has a Hermitian
+ * spectrum, X_{n-k} = conj(X_k), so bins 0..n/2 determine it.
+ *   forward (sign -1):  X_k = sum_{j<n} x_j w_n^{jk},  k = 0..n/2
+ *   inverse (sign +1):  x_j = (1/n) sum_{k<n} X~_k w_n^{-jk},  X~ the
+ *                       Hermitian extension of X_0..X_{n/2}, with the
+ *                       imaginary parts of X_0 and X_{n/2} ignored
+ * computed as one length-n/2 complex transform of z_j = x_{2j} + i x_{2j+1}
+ * plus the even/odd split of Eq. (radix2), fused into one kernel.
  *
  * Conventions shared by every entry point
  *   - Data are interleaved (re, im) pairs.  FFT_C32: two float32 per element
  *     (8 bytes, the layout of std::complex<float> / torch.complex64).
  *     FFT_C16 / FFT_CBF16: two float16 / bfloat16 per element (4 bytes).
  *   - Transform b of a batched plan occupies elements [b*n, (b+1)*n).
+ *     FFT_R32: the real side holds n float32 values per transform
+ *     (floats [b*n, (b+1)*n)), the spectrum side n/2 + 1 complex float32
+ *     bins per transform (bins [b*(n/2+1), (b+1)*(n/2+1))).
  *   - `in` and `out` are device pointers owned by the caller, 16-byte
  *     aligned, and must not overlap (out of place only).
  *   - `stream` is a hipStream_t (NULL = the legacy default stream).  Every
@@ -48,7 +61,8 @@ typedef struct mifft_plan_s *fft_plan;
 enum {
     FFT_C32 = 0,   /* float32 re, im  */
     FFT_C16 = 1,   /* float16 re, im  */
-    FFT_CBF16 = 2  /* bfloat16 re, im */
+    FFT_CBF16 = 2, /* bfloat16 re, im */
+    FFT_R32 = 3    /* real input: float32 reals <-> float32 (re, im) bins   */
 };
 
 /* status codes */
@@ -74,16 +88,17 @@ typedef struct {
     int64_t n;          /* transform length (batched plans), 0 for ragged     */
     int64_t batch;      /* transforms per execute                             */
     int sign;           /* -1 forward (Eq. (dft)), +1 inverse (Eq. (idft))    */
-    int dtype;          /* FFT_C32 / FFT_C16 / FFT_CBF16                       */
+    int dtype;          /* FFT_C32 / FFT_C16 / FFT_CBF16 / FFT_R32             */
     float scale;        /* output scale: 1 (forward) or 1/n (inverse)         */
-    int ept;            /* complex elements held per thread                   */
+    int ept;            /* complex elements held per thread (FFT_R32: of the
+                           half-length transform, as npasses and radices)  */
     int wg;             /* threads per workgroup                              */
     int transforms_per_wg;
     int64_t grid;       /* workgroups per execute                             */
     int npasses;        /* Stockham passes                                    */
     int radices[8];     /* radix of each pass, first to last                  */
     int lds_bytes;      /* LDS per workgroup                                  */
-    int kind;           /* 0 batched, 1 ragged                                */
+    int kind;           /* 0 batched, 1 ragged, 2 multidimensional            */
     int64_t tiles;      /* ragged: work tiles                                 */
     int variant;        /* kernel family: 0 one transform group per
                            workgroup; 1..4 twiddle-row kernels (1, 2: one
@@ -92,20 +107,27 @@ typedef struct {
                            5..8 as 1..4 with wavefront-local exchanges
                            (transforms of at most 64 threads)               */
     int ept_by_log2n[12]; /* ragged: elements per thread used for length 2^L */
+    int rank;           /* multidimensional plans: number of axes (else 0)   */
+    int64_t dims[3];    /* multidimensional plans: axis lengths, first to last */
 } fft_plan_desc;
 
 /*
  * Create a plan for `batch` transforms of length n.
- *   n      power of two.  FFT_C32: [2, 2^20].  Lengths up to 2^11 (the
- *          paper's range, section "Implementation") run one single-pass
- *          kernel; 2^12 .. 2^20 (the paper's future work, section
+ *   n      power of two.  FFT_C32: [2, 2^20].  Lengths up to 2^14 run one
+ *          single-pass kernel (up to 2^11, the paper's range, section
+ *          "Implementation", several transforms per workgroup; above, one
+ *          transform per workgroup of up to 1024 threads and 160 KiB of
+ *          LDS); 2^15 .. 2^20 (the paper's future work, section
  *          "Conclusions") use the four-step split N = N1 N2: a column pass
  *          with the w_N^{n2 k1} twiddles, then an in-place row pass in
  *          `out` (two kernels on the stream).  FFT_C16 / FFT_CBF16: 2048.
+ *          FFT_R32: [2, 2^15].
  *   batch  >= 1.
  *   sign   -1: forward transform Eq. (dft), scale 1.
  *          +1: inverse transform Eq. (idft), scale 1/n.
- *   dtype  FFT_C32, FFT_C16 or FFT_CBF16.
+ *          FFT_R32: -1 maps n reals to n/2 + 1 bins (R2C), +1 maps
+ *          n/2 + 1 bins to n reals with the 1/n (C2R).
+ *   dtype  FFT_C32, FFT_C16, FFT_CBF16 or FFT_R32.
  * Binds to the current HIP device, allocates and fills the plan's twiddle
  * table (blocking, on the legacy default stream).  Returns NULL on error;
  * see fft_last_error().  The kernel variant (elements per thread and
@@ -116,10 +138,12 @@ fft_plan fft_plan_create(int64_t n, int64_t batch, int sign, int dtype);
 
 /*
  * As fft_plan_create, forcing the kernel variant: `ept` complex elements
- * per thread (2, 4, 8 or 16), `wg` threads per workgroup (64, 128, 256 or
- * 512) and the kernel family `variant` (0..8, see fft_plan_desc.variant).
- * FP32 only.  Used by the autotuner.  FFT_EINVAL_CONFIG if that variant is
- * not compiled in.
+ * per thread (2, 4, 8 or 16), `wg` threads per workgroup (64 .. 1024) and
+ * the kernel family `variant` (0..8, see fft_plan_desc.variant; 9 = the
+ * four-step split, n > 2048).  FFT_C32 and FFT_R32 only; for FFT_R32 ept
+ * and wg describe the half-length transform (ept 1..16) and variant is 0
+ * (a whole half-length transform per thread), 2, 3, 6 or 7.  Used by the
+ * autotuner.  FFT_EINVAL_CONFIG if that variant is not compiled in.
  */
 fft_plan fft_plan_create_config(int64_t n, int64_t batch, int sign, int dtype, int ept, int wg, int variant);
 
@@ -149,9 +173,29 @@ fft_plan fft_plan_create_ragged_config(int64_t count, const int64_t *offsets, in
                                        const int *ept_by_log2n, int wg, int ctas_per_cu);
 
 /*
+ * Multidimensional transforms (the paper's future work, section
+ * "Conclusions"): `batch` arrays of shape dims[0] x ... x dims[rank-1],
+ * row-major (the last axis contiguous), each transformed by
+ *   X[k] = s * sum_n x[n] prod_a exp(sign 2 pi i k_a n_a / dims[a]),
+ * s = 1 (sign -1) or 1/prod(dims) (sign +1).  The kernel factors over the
+ * axes, so the plan runs the 1D batched kernels over the last axis
+ * (in -> out) and then one in-place pass per remaining axis over `out`,
+ * each staging tiles of transforms adjacent in memory through LDS.
+ *   rank   1, 2 or 3 (rank 1 is fft_plan_create).
+ *   dims   host array of `rank` powers of two: the last in [2, 2^20], the
+ *          others in [2, 2048].  Copied into the plan.
+ *   dtype  FFT_C32 only.
+ * fft_execute / fft_execute_adjoint apply the transform / its adjoint
+ * (opposite sign, same scale) with n = prod(dims) elements per array.
+ * FFT_EINVAL_N for a bad rank or dims, FFT_ENULL for NULL dims.
+ */
+fft_plan fft_plan_create_nd(int rank, const int64_t *dims, int64_t batch, int sign, int dtype);
+
+/*
  * Apply the plan's transform: out = plan(in).  Asynchronous on `stream`.
  * Byte ranges: n*batch*elem_size (batched) or offsets[count]*elem_size
- * (ragged) for both in and out.  FP16/BF16 plans behave as
+ * (ragged) for both in and out; FFT_R32: 4*n*batch on the real side and
+ * 8*(n/2+1)*batch on the spectrum side.  FP16/BF16 plans behave as
  * fft_execute_scaled with NULL exponent arrays.
  */
 int fft_execute(fft_plan p, const void *in, void *out, void *stream);
@@ -161,6 +205,12 @@ int fft_execute(fft_plan p, const void *in, void *out, void *stream);
  * opposite sign at the SAME scale.  For a forward plan that is the
  * unnormalised inverse sum (no 1/n); for an inverse plan it is the forward
  * sum times 1/n.  Used as the backward pass of the differentiable FFT.
+ * FFT_R32 plans map the other way round (spectrum side -> real side for a
+ * sign -1 plan) and apply the adjoint under the real inner product
+ * Re<a, b>, which is the gradient PyTorch takes through the transform:
+ *   adjoint of R2C:  x_j = Re sum_{k<=n/2} g_k w_n^{-jk}
+ *   adjoint of C2R:  X_k = (c_k/n) sum_j v_j w_n^{jk},  c_k = 1 at k = 0
+ *                    and n/2, 2 in between.
  */
 int fft_execute_adjoint(fft_plan p, const void *in, void *out, void *stream);
 

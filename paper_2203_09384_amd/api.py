@@ -10,9 +10,9 @@ import threading
 import torch
 
 from . import native
-from .native import FFT_C16, FFT_C32, FFT_CBF16, MifftError, check, check_plan, lib
+from .native import FFT_C16, FFT_C32, FFT_CBF16, FFT_R32, MifftError, check, check_plan, lib
 
-DTYPES = {"c32": FFT_C32, "c16": FFT_C16, "cbf16": FFT_CBF16}
+DTYPES = {"c32": FFT_C32, "c16": FFT_C16, "cbf16": FFT_CBF16, "r32": FFT_R32}
 _HALF_TORCH = {FFT_C16: torch.float16, FFT_CBF16: torch.bfloat16}
 
 
@@ -38,7 +38,9 @@ class Plan:
     sign -1 is the forward transform of the paper's Eq. (dft); +1 the
     inverse of Eq. (idft) with its 1/n.  For dtype 'c32' tensors are
     torch.complex64 of shape (..., n) with batch = numel / n; for 'c16' /
-    'cbf16' they are float16 / bfloat16 of shape (..., n, 2).
+    'cbf16' they are float16 / bfloat16 of shape (..., n, 2).  For 'r32'
+    (real input) the real side is float32 (..., n) and the spectrum side
+    complex64 (..., n/2 + 1): sign -1 maps real -> spectrum, +1 back.
     """
 
     def __init__(self, n: int, batch: int, sign: int = -1, dtype: str = "c32",
@@ -53,12 +55,19 @@ class Plan:
         self._h = check_plan(h)
 
     # -- marshalling -------------------------------------------------------
-    def _check_tensor(self, x, what):
+    def _check_tensor(self, x, what, side=None):
         if not x.is_cuda:
             raise ValueError(f"{what} must be a GPU tensor")
         if not x.is_contiguous():
             raise ValueError(f"{what} must be contiguous")
-        if self.dtype == FFT_C32:
+        if self.dtype == FFT_R32:
+            want, count = ((torch.float32, self.n * self.batch) if side == "real"
+                           else (torch.complex64, (self.n // 2 + 1) * self.batch))
+            if x.dtype != want:
+                raise ValueError(f"{what} must be {want}, got {x.dtype}")
+            if x.numel() != count:
+                raise ValueError(f"{what} has {x.numel()} elements, plan needs {count}")
+        elif self.dtype == FFT_C32:
             if x.dtype != torch.complex64:
                 raise ValueError(f"{what} must be complex64, got {x.dtype}")
             if x.numel() != self.n * self.batch:
@@ -69,23 +78,38 @@ class Plan:
             if x.numel() != 2 * self.n * self.batch:
                 raise ValueError(f"{what} has {x.numel()} values, plan needs 2*{self.n}*{self.batch}")
 
-    def execute(self, x, out=None, stream=None):
-        """out = plan(x); allocates `out` (torch caching allocator) if not given."""
-        self._check_tensor(x, "input")
-        if out is None:
-            out = torch.empty_like(x)
-        self._check_tensor(out, "output")
-        check(lib().fft_execute(self._h, _ptr(x), _ptr(out), _stream_handle(stream)))
+    def _sides(self, to_spectrum: bool):
+        return ("real", "spectrum") if to_spectrum else ("spectrum", "real")
+
+    def _new_like_side(self, x, side):
+        lead = x.shape[:-1]
+        if side == "real":
+            return torch.empty(lead + (self.n,), dtype=torch.float32, device=x.device)
+        return torch.empty(lead + (self.n // 2 + 1,), dtype=torch.complex64, device=x.device)
+
+    def _run(self, fn, x, out, stream, to_spectrum):
+        if self.dtype == FFT_R32:
+            sin, sout = self._sides(to_spectrum)
+            self._check_tensor(x, "input", sin)
+            if out is None:
+                out = self._new_like_side(x, sout)
+            self._check_tensor(out, "output", sout)
+        else:
+            self._check_tensor(x, "input")
+            if out is None:
+                out = torch.empty_like(x)
+            self._check_tensor(out, "output")
+        check(fn(self._h, _ptr(x), _ptr(out), _stream_handle(stream)))
         return out
 
+    def execute(self, x, out=None, stream=None):
+        """out = plan(x); allocates `out` (torch caching allocator) if not given."""
+        return self._run(lib().fft_execute, x, out, stream, self.sign < 0)
+
     def adjoint(self, g, out=None, stream=None):
-        """out = plan^H(g): conjugate sign, same scale."""
-        self._check_tensor(g, "input")
-        if out is None:
-            out = torch.empty_like(g)
-        self._check_tensor(out, "output")
-        check(lib().fft_execute_adjoint(self._h, _ptr(g), _ptr(out), _stream_handle(stream)))
-        return out
+        """out = plan^H(g): conjugate sign, same scale (real-input plans: the
+        adjoint under Re<a, b>, from the spectrum side for sign -1)."""
+        return self._run(lib().fft_execute_adjoint, g, out, stream, self.sign > 0)
 
     def execute_scaled(self, x, in_exp=None, out=None, out_exp=None, stream=None):
         """Block floating point (FP16/BF16 plans): value = stored * 2^exp[b]."""
@@ -294,3 +318,144 @@ class WeightedPowerLossFn(torch.autograd.Function):
 
 def weighted_power_loss(x, w, sign: int = -1):
     return WeightedPowerLossFn.apply(x, w, sign)
+
+
+# ------------------------------------------------------------------ real input
+def rfft(x):
+    """Bins 0..n/2 of the forward transform of a real float32 GPU tensor
+    (last dimension n) as a new complex64 tensor (..., n/2 + 1)."""
+    x = x.contiguous()
+    n = x.shape[-1]
+    return get_plan(n, x.numel() // n, -1, "r32", x.device.index).execute(x)
+
+
+def irfft(X, n: int | None = None):
+    """Inverse of rfft: n reals (default 2 * (bins - 1)) from n/2 + 1 bins,
+    with the 1/n of Eq. (idft); imaginary parts of bins 0 and n/2 ignored."""
+    X = X.contiguous()
+    n = 2 * (X.shape[-1] - 1) if n is None else int(n)
+    if X.shape[-1] != n // 2 + 1:
+        raise ValueError(f"{X.shape[-1]} bins given, n={n} needs {n // 2 + 1}")
+    return get_plan(n, X.numel() // (n // 2 + 1), +1, "r32", X.device.index).execute(X)
+
+
+class RFFTFn(torch.autograd.Function):
+    """Differentiable rfft; backward is the plan's adjoint, x.grad =
+    Re sum_k g_k w^{-jk} over the n/2 + 1 bins."""
+
+    @staticmethod
+    def forward(ctx, x):
+        x = x.contiguous()
+        n = x.shape[-1]
+        ctx.plan = get_plan(n, x.numel() // n, -1, "r32", x.device.index)
+        return ctx.plan.execute(x)
+
+    @staticmethod
+    def backward(ctx, g):
+        g = g.contiguous()
+        if g.dtype != torch.complex64:
+            g = g.to(torch.complex64)
+        return ctx.plan.adjoint(g)
+
+
+class IRFFTFn(torch.autograd.Function):
+    """Differentiable irfft; backward is the plan's adjoint (an R2C with
+    the 1/n and the interior bins doubled)."""
+
+    @staticmethod
+    def forward(ctx, X, n: int):
+        X = X.contiguous()
+        ctx.plan = get_plan(n, X.numel() // (n // 2 + 1), +1, "r32", X.device.index)
+        return ctx.plan.execute(X)
+
+    @staticmethod
+    def backward(ctx, g):
+        g = g.contiguous()
+        if g.dtype != torch.float32:
+            g = g.to(torch.float32)
+        return ctx.plan.adjoint(g), None
+
+
+def rfft_differentiable(x):
+    return RFFTFn.apply(x)
+
+
+def irfft_differentiable(X, n: int | None = None):
+    n = 2 * (X.shape[-1] - 1) if n is None else int(n)
+    return IRFFTFn.apply(X, n)
+
+
+# ------------------------------------------------------------------ multidimensional
+class PlanND(Plan):
+    """fft_plan_create_nd(rank, dims, batch, sign, FFT_C32): `batch` arrays
+    of shape `dims` (row-major), transformed over all their axes."""
+
+    def __init__(self, dims, batch: int, sign: int = -1):
+        import numpy as np
+        L = lib()
+        self.dims = tuple(int(d) for d in dims)
+        self.n = int(np.prod(self.dims))
+        self.batch, self.sign, self.dtype = int(batch), int(sign), FFT_C32
+        arr = (ctypes.c_int64 * len(self.dims))(*self.dims)
+        self._h = check_plan(L.fft_plan_create_nd(len(self.dims), arr, self.batch, self.sign, FFT_C32))
+
+
+def _nd_plan(shape, batch, sign, device):
+    dev = torch.cuda.current_device() if device is None else device
+    key = (dev, "nd", tuple(shape), batch, sign)
+    with _cache_lock:
+        p = _cache.get(key)
+        if p is None:
+            with torch.cuda.device(dev):
+                p = PlanND(shape, batch, sign)
+            _cache[key] = p
+        return p
+
+
+def fftn(x, ndim: int | None = None, sign: int = -1):
+    """Transform over the last `ndim` dimensions (default all, at most 3) of
+    a complex64 GPU tensor; new tensor."""
+    x = x.contiguous()
+    ndim = x.dim() if ndim is None else int(ndim)
+    shape = tuple(x.shape[x.dim() - ndim:])
+    n = 1
+    for d in shape:
+        n *= d
+    return _nd_plan(shape, x.numel() // n, sign, x.device.index).execute(x)
+
+
+def ifftn(X, ndim: int | None = None):
+    return fftn(X, ndim, sign=+1)
+
+
+def fft2(x):
+    return fftn(x, 2)
+
+
+def ifft2(X):
+    return fftn(X, 2, sign=+1)
+
+
+class FFTNFn(torch.autograd.Function):
+    """Differentiable multidimensional FFT; backward is the plan's adjoint."""
+
+    @staticmethod
+    def forward(ctx, x, ndim: int, sign: int = -1):
+        x = x.contiguous()
+        shape = tuple(x.shape[x.dim() - ndim:])
+        n = 1
+        for d in shape:
+            n *= d
+        ctx.plan = _nd_plan(shape, x.numel() // n, sign, x.device.index)
+        return ctx.plan.execute(x)
+
+    @staticmethod
+    def backward(ctx, g):
+        g = g.contiguous()
+        if g.dtype != torch.complex64:
+            g = g.to(torch.complex64)
+        return ctx.plan.adjoint(g), None, None
+
+
+def fftn_differentiable(x, ndim: int, sign: int = -1):
+    return FFTNFn.apply(x, ndim, sign)

@@ -1,7 +1,8 @@
 """Build libmifft.so (HIP, gfx950) in-tree with hipcc.
 
 Every kernel translation unit is compiled for gfx950 only; the FP32 Stockham
-file is compiled once per transform length (-DMIFFT_LOG2N=1..11).  Objects go
+file is compiled once per transform length (-DMIFFT_LOG2N=1..14), the
+real-input file once per half length (-DMIFFT_LOG2M=0..14).  Objects go
 to ``_build/`` beside this file, the library to ``libmifft.so`` beside it.
 """
 from __future__ import annotations
@@ -28,6 +29,8 @@ def _units():
         units.append(("fft_c32.hip", f"fft_c32_L{L}.o", [f"-DMIFFT_LOG2N={L}"]))
     for L in range(1, 12):
         units.append(("fused_loss.hip", f"fused_loss_L{L}.o", [f"-DMIFFT_LOG2N={L}"]))
+    for L in range(0, 15):
+        units.append(("real.hip", f"real_M{L}.o", [f"-DMIFFT_LOG2M={L}"]))
     units.append(("twiddle.hip", "twiddle.o", []))
     units.append(("fourstep.hip", "fourstep.o", []))
     for wg in (64, 128, 256):

@@ -19,7 +19,9 @@
 #include "fourstep.hpp"
 #include "fused_loss.hpp"
 #include "half.hpp"
+#include "nd.hpp"
 #include "ragged.hpp"
+#include "real.hpp"
 #include "registry.hpp"
 
 namespace mifft {
@@ -64,7 +66,7 @@ int ilog2(int64_t v)
         l++;
     return l;
 }
-size_t elem_bytes(int dtype) { return dtype == FFT_C32 ? 8 : 4; }
+size_t elem_bytes(int dtype) { return (dtype == FFT_C32 || dtype == FFT_R32) ? 8 : 4; }
 }  // namespace
 
 // ------------------------------------------------------------------ registry
@@ -109,6 +111,32 @@ const KernelLossGrad* find_loss_grad(int log2n, int log2ept, int wg, int sign)
             return &k;
     return nullptr;
 }
+static std::vector<KernelReal>& real_reg()
+{
+    static std::vector<KernelReal> r;
+    return r;
+}
+void register_real(const KernelReal& k) { real_reg().push_back(k); }
+const KernelReal* find_real(int log2m, int log2ept, int wg, int dir, int kind)
+{
+    for (const auto& k : real_reg())
+        if (k.log2m == log2m && k.log2ept == log2ept && k.wg == wg && k.dir == dir && k.kind == kind)
+            return &k;
+    return nullptr;
+}
+static std::vector<KernelAxis>& axis_reg()
+{
+    static std::vector<KernelAxis> r;
+    return r;
+}
+void register_axis(const KernelAxis& k) { axis_reg().push_back(k); }
+const KernelAxis* find_axis(int log2n, int sign)
+{
+    for (const auto& k : axis_reg())
+        if (k.log2n == log2n && k.sign == sign)
+            return &k;
+    return nullptr;
+}
 const KernelC32* c32_at(int i) { return (i >= 0 && i < count_c32()) ? &c32_reg()[i] : nullptr; }
 }  // namespace mifft
 
@@ -140,11 +168,34 @@ const Variant kDefaultC32[21] = {
     {0, 0, 9}, {0, 0, 9}, {0, 0, 9}, {0, 0, 9}, {0, 0, 9},
 };
 
+// Real-input transforms (FFT_R32), per log2 of the half length M = n/2
+// (index 0..14): the half-length complex transform's configuration.
+const Variant kDefaultR32[15] = {
+    {0, 256, 0},   // n=2     one thread per transform, no passes
+    {1, 64, 0},    // n=4     the half-length transform inside one thread
+    {2, 128, 0},   // n=8
+    {2, 256, 2},   // n=16
+    {2, 256, 2},   // n=32
+    {2, 256, 2},   // n=64
+    {2, 64, 6},    // n=128   wavefront-local exchanges
+    {3, 64, 6},    // n=256
+    {4, 256, 6},   // n=512
+    {3, 64, 6},    // n=1024
+    {4, 64, 3},    // n=2048  persistent, next-group prefetch
+    {4, 128, 3},   // n=4096
+    {3, 512, 3},   // n=2^13  one transform per workgroup
+    {3, 1024, 3},  // n=2^14
+    {4, 1024, 2},  // n=2^15
+};
+
 std::once_flag g_tune_once;
 Variant g_tuned_c32[21];
 bool g_have_tuned_c32[21];
+Variant g_tuned_r32[15];
+bool g_have_tuned_r32[15];
 
-// MIFFT_TUNE_TABLE: text lines "c32 <log2n> <ept> <wg> <kind>"; '#' starts a comment.
+// MIFFT_TUNE_TABLE: text lines "c32 <log2n> <ept> <wg> <kind>" and
+// "r32 <log2(n/2)> <ept> <wg> <kind>"; '#' starts a comment.
 void load_tune_table()
 {
     const char* path = getenv("MIFFT_TUNE_TABLE");
@@ -167,6 +218,10 @@ void load_tune_table()
             g_tuned_c32[l] = Variant{kind == 9 ? 0 : ilog2(ept), wg, kind};
             g_have_tuned_c32[l] = true;
         }
+        if (dt == "r32" && l >= 1 && l <= 14 && is_pow2(ept) && ept >= 2 && ept <= 16) {
+            g_tuned_r32[l] = Variant{ilog2(ept), wg, kind};
+            g_have_tuned_r32[l] = true;
+        }
     }
 }
 
@@ -179,6 +234,17 @@ Variant choose_c32(int log2n)
             return v;
     }
     return kDefaultC32[log2n];
+}
+
+Variant choose_r32(int log2m)
+{
+    std::call_once(g_tune_once, load_tune_table);
+    if (g_have_tuned_r32[log2m]) {
+        const Variant v = g_tuned_r32[log2m];
+        if (find_real(log2m, v.log2ept, v.wg, 0, v.kind) && find_real(log2m, v.log2ept, v.wg, 1, v.kind))
+            return v;
+    }
+    return kDefaultR32[log2m];
 }
 
 // Stockham schedule of (log2 N, log2 EPT): a remainder pass first, then
@@ -219,19 +285,37 @@ struct mifft_plan_s {
     int64_t total = 0;               // elements per execute (either kind)
     RaggedPlan* ragged = nullptr;
     HalfPlan* half = nullptr;
+    const KernelReal* r2c = nullptr;  // FFT_R32: real -> bins kernel
+    const KernelReal* c2r = nullptr;  // FFT_R32: bins -> real kernel
+    void* wn = nullptr;               // FFT_R32: w_n^k, k < n/2
+    // multidimensional plans (kind 2): the last axis as a batched sub-plan,
+    // then in-place axis passes from the second-to-last axis to the first
+    int rank = 1;
+    int64_t dims[3] = {0, 0, 0};
+    mifft_plan_s* last = nullptr;
+    const KernelAxis* ax_same[2] = {nullptr, nullptr};  // the plan's sign
+    const KernelAxis* ax_opp[2] = {nullptr, nullptr};   // the adjoint's sign
+    void* ax_rows[2] = {nullptr, nullptr};
+    int ax_log2s[2] = {0, 0};
+    int64_t ax_count[2] = {0, 0};
+    float ax_scale[2] = {1.f, 1.f};
 };
 
 namespace {
 constexpr int64_t kMaxN = int64_t(1) << 20;
+constexpr int64_t kMaxRealN = int64_t(1) << 15;
 
 int check_common(int64_t n, int64_t batch, int sign, int dtype)
 {
-    if (dtype != FFT_C32 && dtype != FFT_C16 && dtype != FFT_CBF16)
-        return set_err(FFT_EINVAL_DTYPE, "dtype %d is not FFT_C32, FFT_C16 or FFT_CBF16", dtype);
+    if (dtype != FFT_C32 && dtype != FFT_C16 && dtype != FFT_CBF16 && dtype != FFT_R32)
+        return set_err(FFT_EINVAL_DTYPE, "dtype %d is not FFT_C32, FFT_C16, FFT_CBF16 or FFT_R32", dtype);
     if (!is_pow2(n) || n < 2 || n > kMaxN)
         return set_err(FFT_EINVAL_N, "n=%lld is not a power of two in [2, 2^20]", (long long)n);
-    if (n > 2048 && dtype != FFT_C32)
-        return set_err(FFT_EINVAL_N, "n=%lld: lengths above 2048 are FFT_C32 only", (long long)n);
+    if (dtype == FFT_R32 && n > kMaxRealN)
+        return set_err(FFT_EINVAL_N, "n=%lld: real-input (FFT_R32) lengths are powers of two in [2, 2^15]",
+                       (long long)n);
+    if (n > 2048 && dtype != FFT_C32 && dtype != FFT_R32)
+        return set_err(FFT_EINVAL_N, "n=%lld: lengths above 2048 are FFT_C32 / FFT_R32 only", (long long)n);
     if (batch < 1)
         return set_err(FFT_EINVAL_BATCH, "batch=%lld must be >= 1", (long long)batch);
     if (batch > (int64_t(1) << 40) / n)
@@ -288,6 +372,32 @@ int fill_desc_c32(int64_t n, int64_t batch, int sign, int dtype, Variant v, int6
     if (grid_limit > 0 && d->grid > grid_limit)
         d->grid = grid_limit;
     const KernelC32* k = find_c32(log2n, v.log2ept, v.wg, sign, v.kind);
+    d->lds_bytes = k ? k->lds_bytes : 0;
+    d->kind = 0;
+    d->variant = v.kind;
+    return FFT_OK;
+}
+
+// FFT_R32: the half-length (n/2) complex transform's shape; ept, radices
+// and lds describe it.
+int fill_desc_r32(int64_t n, int64_t batch, int sign, Variant v, int64_t grid_limit, fft_plan_desc* d)
+{
+    memset(d, 0, sizeof *d);
+    const int log2m = ilog2(n) - 1;
+    d->n = n;
+    d->batch = batch;
+    d->sign = sign;
+    d->dtype = FFT_R32;
+    d->scale = sign > 0 ? 1.0f / (float)n : 1.0f;
+    d->ept = 1 << v.log2ept;
+    d->wg = v.wg;
+    const int tpt = (int)((n / 2) >> v.log2ept);
+    d->transforms_per_wg = v.wg / std::max(tpt, 1);
+    d->grid = (batch + d->transforms_per_wg - 1) / d->transforms_per_wg;
+    if (grid_limit > 0 && d->grid > grid_limit)
+        d->grid = grid_limit;
+    d->npasses = log2m > 0 ? schedule(log2m, v.log2ept, d->radices) : 0;
+    const KernelReal* k = find_real(log2m, v.log2ept, v.wg, sign < 0 ? 0 : 1, v.kind);
     d->lds_bytes = k ? k->lds_bytes : 0;
     d->kind = 0;
     d->variant = v.kind;
@@ -417,10 +527,54 @@ int make_loss_grad(mifft_plan_s* p)
     return FFT_OK;
 }
 
+// Tables of an FFT_R32 plan: the half-length transform's twiddle rows, the
+// w_n^k of the even/odd split, and the persistent grid size.
+int make_real(mifft_plan_s* p)
+{
+    const KernelReal* k = p->r2c;
+    hipError_t e = hipSuccess;
+    if (k->rows > 0) {
+        e = hipMalloc(&p->rows, (size_t)k->rows * sizeof(float2));
+        if (e != hipSuccess)
+            p->rows = nullptr;
+    }
+    if (e == hipSuccess) {
+        e = hipMalloc(&p->wn, (size_t)(p->n / 2) * sizeof(float2));
+        if (e != hipSuccess)
+            p->wn = nullptr;
+    }
+    if (e != hipSuccess)
+        return e == hipErrorOutOfMemory ? set_err(FFT_ENOMEM, "hipMalloc(real-input tables) failed")
+                                        : hip_err(e, "hipMalloc(real-input tables)");
+    if (k->rows > 0)
+        e = launch_twiddle_rows(p->tw, p->rows, k->log2m, k->log2ept, k->rows, nullptr);
+    if (e == hipSuccess)
+        e = launch_twiddle_real(p->tw, p->wn, p->log2n, nullptr);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(nullptr);
+    if (e != hipSuccess)
+        return hip_err(e, "real-input tables");
+    p->grid_limit = 0;
+    if ((k->kind == 3 || k->kind == 7) && k->occupancy) {
+        int cus = 0;
+        e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device);
+        if (e != hipSuccess)
+            return hip_err(e, "hipDeviceGetAttribute(CU count)");
+        const int occ = std::max(std::max(k->occupancy(), p->c2r->occupancy ? p->c2r->occupancy() : 1), 1);
+        p->grid_limit = (int64_t)cus * occ;
+    }
+    return FFT_OK;
+}
+
 void free_plan(mifft_plan_s* p)
 {
     if (!p)
         return;
+    if (p->last)
+        free_plan(p->last);
+    for (void* q : {p->ax_rows[0], p->ax_rows[1]})
+        if (q)
+            (void)hipFree(q);
     if (p->ragged)
         ragged_destroy(p->ragged);
     if (p->half)
@@ -431,16 +585,62 @@ void free_plan(mifft_plan_s* p)
         (void)hipFree(p->rows);
     if (p->lg_rows)
         (void)hipFree(p->lg_rows);
-    for (void* q : {p->fs_rows1, p->fs_rows2, p->fs_tw})
+    for (void* q : {p->fs_rows1, p->fs_rows2, p->fs_tw, p->wn})
         if (q)
             (void)hipFree(q);
     delete p;
+}
+
+fft_plan create_real(int64_t n, int64_t batch, int sign, const Variant* force)
+{
+    const int log2m = ilog2(n) - 1;
+    const Variant v = force ? *force : choose_r32(log2m);
+    const KernelReal* r2c = find_real(log2m, v.log2ept, v.wg, 0, v.kind);
+    const KernelReal* c2r = find_real(log2m, v.log2ept, v.wg, 1, v.kind);
+    if (!r2c || !c2r) {
+        set_err(FFT_EINVAL_CONFIG, "no real-input kernel for n=%lld ept=%d wg=%d kind=%d", (long long)n,
+                1 << v.log2ept, v.wg, v.kind);
+        return nullptr;
+    }
+    const int tpb = v.wg / (int)std::max<int64_t>((n / 2) >> v.log2ept, 1);
+    if ((batch + tpb - 1) / tpb > 0x7fffffffLL) {
+        set_err(FFT_EINVAL_BATCH, "batch=%lld needs more than 2^31-1 workgroups", (long long)batch);
+        return nullptr;
+    }
+    int dev = -1;
+    if (current_gfx950(&dev) != FFT_OK)
+        return nullptr;
+    auto* p = new (std::nothrow) mifft_plan_s();
+    if (!p) {
+        set_err(FFT_ENOMEM, "out of host memory");
+        return nullptr;
+    }
+    p->kind = 0;
+    p->n = n;
+    p->batch = batch;
+    p->sign = sign;
+    p->dtype = FFT_R32;
+    p->scale = sign > 0 ? 1.0f / (float)n : 1.0f;
+    p->device = dev;
+    p->log2n = ilog2(n);
+    p->var = v;
+    p->total = n * batch;
+    p->r2c = r2c;
+    p->c2r = c2r;
+    if (make_twiddles(p) != FFT_OK || make_real(p) != FFT_OK) {
+        free_plan(p);
+        return nullptr;
+    }
+    ok();
+    return p;
 }
 
 fft_plan create_batched(int64_t n, int64_t batch, int sign, int dtype, const Variant* force)
 {
     if (check_common(n, batch, sign, dtype) != FFT_OK)
         return nullptr;
+    if (dtype == FFT_R32)
+        return create_real(n, batch, sign, force);
     const int log2n = ilog2(n);
     Variant v{};
     const bool four_step = dtype == FFT_C32 && n > 2048 &&
@@ -530,7 +730,125 @@ fft_plan create_batched(int64_t n, int64_t batch, int sign, int dtype, const Var
     return p;
 }
 
-int check_exec(fft_plan p, const void* in, const void* out)
+constexpr int64_t kMaxAxisN = 2048;
+
+fft_plan create_nd(int rank, const int64_t* dims, int64_t batch, int sign, int dtype)
+{
+    if (!dims) {
+        set_err(FFT_ENULL, "dims is NULL");
+        return nullptr;
+    }
+    if (rank < 1 || rank > 3) {
+        set_err(FFT_EINVAL_N, "rank=%d must be 1, 2 or 3", rank);
+        return nullptr;
+    }
+    if (dtype != FFT_C32) {
+        set_err(FFT_EINVAL_DTYPE, "multidimensional plans are FFT_C32 only");
+        return nullptr;
+    }
+    int64_t n = 1;
+    for (int a = 0; a < rank; a++) {
+        const int64_t d = dims[a];
+        const int64_t hi = a == rank - 1 ? kMaxN : kMaxAxisN;
+        if (!is_pow2(d) || d < 2 || d > hi) {
+            set_err(FFT_EINVAL_N, "dims[%d]=%lld must be a power of two in [2, %lld]", a, (long long)d,
+                    (long long)hi);
+            return nullptr;
+        }
+        if (n > (int64_t(1) << 40) / d) {
+            set_err(FFT_EINVAL_N, "the transform has more than 2^40 elements");
+            return nullptr;
+        }
+        n *= d;
+    }
+    if (batch < 1) {
+        set_err(FFT_EINVAL_BATCH, "batch=%lld must be >= 1", (long long)batch);
+        return nullptr;
+    }
+    if (batch > (int64_t(1) << 40) / n) {
+        set_err(FFT_EINVAL_BATCH, "n*batch=%lld*%lld exceeds 2^40 elements", (long long)n, (long long)batch);
+        return nullptr;
+    }
+    if (sign != -1 && sign != 1) {
+        set_err(FFT_EINVAL_SIGN, "sign=%d must be -1 (forward) or +1 (inverse)", sign);
+        return nullptr;
+    }
+    if (rank == 1)
+        return create_batched(dims[0], batch, sign, dtype, nullptr);
+    for (int a = 0; a + 1 < rank; a++) {
+        const KernelAxis* k = find_axis(ilog2(dims[a]), sign);
+        if (!k || (batch * (n / dims[a]) + k->tile - 1) / k->tile > 0x7fffffffLL - 16) {
+            set_err(FFT_EINVAL_BATCH, "axis %d: batch=%lld needs more than 2^31-1 workgroups", a,
+                    (long long)batch);
+            return nullptr;
+        }
+    }
+    mifft_plan_s* last = create_batched(dims[rank - 1], batch * (n / dims[rank - 1]), sign, dtype, nullptr);
+    if (!last)
+        return nullptr;
+    auto* p = new (std::nothrow) mifft_plan_s();
+    if (!p) {
+        free_plan(last);
+        set_err(FFT_ENOMEM, "out of host memory");
+        return nullptr;
+    }
+    p->kind = 2;
+    p->n = n;
+    p->batch = batch;
+    p->sign = sign;
+    p->dtype = dtype;
+    p->scale = sign > 0 ? 1.0f / (float)n : 1.0f;
+    p->device = last->device;
+    p->log2n = ilog2(n);
+    p->total = n * batch;
+    p->rank = rank;
+    p->last = last;
+    for (int a = 0; a < rank; a++)
+        p->dims[a] = dims[a];
+    if (make_twiddles(p) != FFT_OK) {
+        free_plan(p);
+        return nullptr;
+    }
+    int log2s = ilog2(dims[rank - 1]);
+    for (int a = rank - 2; a >= 0; a--) {
+        const int L = ilog2(dims[a]);
+        p->ax_same[a] = find_axis(L, sign);
+        p->ax_opp[a] = find_axis(L, -sign);
+        p->ax_log2s[a] = log2s;
+        p->ax_count[a] = batch * (n / dims[a]);
+        p->ax_scale[a] = sign > 0 ? 1.0f / (float)dims[a] : 1.0f;
+        log2s += L;
+        const KernelAxis* k = p->ax_same[a];
+        if (k->rows > 0) {
+            hipError_t e = hipMalloc(&p->ax_rows[a], (size_t)k->rows * sizeof(float2));
+            if (e != hipSuccess) {
+                p->ax_rows[a] = nullptr;
+                e == hipErrorOutOfMemory ? set_err(FFT_ENOMEM, "hipMalloc(axis twiddle rows) failed")
+                                         : hip_err(e, "hipMalloc(axis twiddle rows)");
+                free_plan(p);
+                return nullptr;
+            }
+            e = launch_twiddle_rows(p->tw, p->ax_rows[a], L, k->log2ept, k->rows, nullptr);
+            if (e == hipSuccess)
+                e = hipStreamSynchronize(nullptr);
+            if (e != hipSuccess) {
+                hip_err(e, "axis twiddle rows");
+                free_plan(p);
+                return nullptr;
+            }
+        }
+    }
+    ok();
+    return p;
+}
+
+// Byte sizes of an FFT_R32 plan's two sides: n float32 reals and n/2 + 1
+// complex bins per transform.
+uintptr_t real_side_bytes(fft_plan p) { return (uintptr_t)p->batch * (uintptr_t)p->n * 4; }
+uintptr_t bins_side_bytes(fft_plan p) { return (uintptr_t)p->batch * (uintptr_t)(p->n / 2 + 1) * 8; }
+
+// to_bins: for FFT_R32 plans, whether `in` holds reals and `out` bins.
+int check_exec(fft_plan p, const void* in, const void* out, bool to_bins = false)
 {
     if (!p)
         return set_err(FFT_ENULL, "plan is NULL");
@@ -538,11 +856,15 @@ int check_exec(fft_plan p, const void* in, const void* out)
         return set_err(FFT_ENULL, "in/out pointer is NULL");
     if ((reinterpret_cast<uintptr_t>(in) | reinterpret_cast<uintptr_t>(out)) & 15)
         return set_err(FFT_EALIGN, "in/out must be 16-byte aligned");
-    const uintptr_t bytes = (uintptr_t)p->total * elem_bytes(p->dtype);
+    uintptr_t in_bytes = (uintptr_t)p->total * elem_bytes(p->dtype), out_bytes = in_bytes;
+    if (p->dtype == FFT_R32) {
+        in_bytes = to_bins ? real_side_bytes(p) : bins_side_bytes(p);
+        out_bytes = to_bins ? bins_side_bytes(p) : real_side_bytes(p);
+    }
     const uintptr_t a = reinterpret_cast<uintptr_t>(in), b = reinterpret_cast<uintptr_t>(out);
-    if (a < b + bytes && b < a + bytes)
+    if (a < b + out_bytes && b < a + in_bytes)
         return set_err(FFT_EOVERLAP, "in [%p, +%zu) and out [%p, +%zu) overlap (out of place only)", in,
-                       (size_t)bytes, out, (size_t)bytes);
+                       (size_t)in_bytes, out, (size_t)out_bytes);
     int dev = -1;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess)
@@ -552,9 +874,33 @@ int check_exec(fft_plan p, const void* in, const void* out)
     return FFT_OK;
 }
 
+// FFT_R32: to_bins selects the real -> bins kernel; we / wi weight the
+// edge and interior bins (see real.hip).
+int exec_real(fft_plan p, const void* in, void* out, bool to_bins, float we, float wi, hipStream_t st)
+{
+    const KernelReal* k = to_bins ? p->r2c : p->c2r;
+    hipError_t e = k->fn(in, out, p->rows, p->wn, p->batch, we, wi, p->grid_limit, st);
+    if (e != hipSuccess)
+        return hip_err(e, "real-input FFT kernel launch");
+    return ok();
+}
+
 // direction: the sign of the exponent actually applied; scale as given.
 int exec_c32(fft_plan p, const void* in, void* out, int sign, float scale, hipStream_t st)
 {
+    if (p->kind == 2) {
+        // last axis (batched 1D), then the other axes in place in `out`
+        int rc = exec_c32(p->last, in, out, sign, p->last->scale, st);
+        if (rc != FFT_OK)
+            return rc;
+        for (int a = p->rank - 2; a >= 0; a--) {
+            const KernelAxis* k = sign == p->sign ? p->ax_same[a] : p->ax_opp[a];
+            hipError_t e = k->fn(out, p->ax_rows[a], p->ax_count[a], p->ax_log2s[a], p->ax_scale[a], st);
+            if (e != hipSuccess)
+                return hip_err(e, "axis kernel launch");
+        }
+        return ok();
+    }
     if (p->kind == 1) {
         int rc = ragged_execute(p->ragged, in, out, p->tw, sign, p->sign > 0, st);
         if (rc != FFT_OK)
@@ -585,10 +931,24 @@ fft_plan fft_plan_create(int64_t n, int64_t batch, int sign, int dtype)
     return create_batched(n, batch, sign, dtype, nullptr);
 }
 
+fft_plan fft_plan_create_nd(int rank, const int64_t* dims, int64_t batch, int sign, int dtype)
+{
+    return create_nd(rank, dims, batch, sign, dtype);
+}
+
 fft_plan fft_plan_create_config(int64_t n, int64_t batch, int sign, int dtype, int ept, int wg, int variant)
 {
     if (check_common(n, batch, sign, dtype) != FFT_OK)
         return nullptr;
+    if (dtype == FFT_R32) {
+        if (!is_pow2(ept) || ept < 1 || ept > 16 || !is_pow2(wg) || wg < 64 || wg > 1024 ||
+            !(variant == 0 || variant == 2 || variant == 3 || variant == 6 || variant == 7)) {
+            set_err(FFT_EINVAL_CONFIG, "real-input configs: ept 1..16, wg 64..1024 (powers of two), variant 0, 2, 3, 6 or 7");
+            return nullptr;
+        }
+        Variant v{ilog2(ept), wg, variant};
+        return create_batched(n, batch, sign, dtype, &v);
+    }
     if (dtype != FFT_C32) {
         set_err(FFT_EINVAL_DTYPE, "fft_plan_create_config selects FP32 variants only");
         return nullptr;
@@ -688,9 +1048,13 @@ fft_plan fft_plan_create_ragged(int64_t count, const int64_t* offsets, int sign,
 
 int fft_execute(fft_plan p, const void* in, void* out, void* stream)
 {
-    int rc = check_exec(p, in, out);
+    int rc = check_exec(p, in, out, p && p->sign < 0);
     if (rc != FFT_OK)
         return rc;
+    if (p->dtype == FFT_R32) {
+        const float s = p->scale;
+        return exec_real(p, in, out, p->sign < 0, s, s, static_cast<hipStream_t>(stream));
+    }
     if (p->dtype != FFT_C32)
         return fft_execute_scaled(p, in, nullptr, out, nullptr, stream);
     return exec_c32(p, in, out, p->sign, p->scale, static_cast<hipStream_t>(stream));
@@ -698,9 +1062,17 @@ int fft_execute(fft_plan p, const void* in, void* out, void* stream)
 
 int fft_execute_adjoint(fft_plan p, const void* in, void* out, void* stream)
 {
-    int rc = check_exec(p, in, out);
+    int rc = check_exec(p, in, out, p && p->sign > 0);
     if (rc != FFT_OK)
         return rc;
+    if (p->dtype == FFT_R32) {
+        // adjoint of real -> bins: bins -> real with interior bins halved;
+        // adjoint of bins -> real (scale 1/n): real -> bins, interior doubled
+        if (p->sign < 0)
+            return exec_real(p, in, out, false, 1.0f, 0.5f, static_cast<hipStream_t>(stream));
+        const float s = p->scale;
+        return exec_real(p, in, out, true, s, 2.0f * s, static_cast<hipStream_t>(stream));
+    }
     if (p->dtype != FFT_C32)
         return set_err(FFT_EINVAL_DTYPE, "the adjoint is provided for FFT_C32 plans");
     return exec_c32(p, in, out, -p->sign, p->scale, static_cast<hipStream_t>(stream));
@@ -712,7 +1084,7 @@ int fft_execute_scaled(fft_plan p, const void* in, const int32_t* in_exp, void* 
     int rc = check_exec(p, in, out);
     if (rc != FFT_OK)
         return rc;
-    if (p->dtype == FFT_C32 || !p->half)
+    if (p->dtype == FFT_C32 || p->dtype == FFT_R32 || !p->half)
         return set_err(FFT_EINVAL_DTYPE, "fft_execute_scaled needs an FFT_C16 or FFT_CBF16 plan");
     if ((reinterpret_cast<uintptr_t>(in_exp) | reinterpret_cast<uintptr_t>(out_exp)) & 3)
         return set_err(FFT_EALIGN, "exponent arrays must be 4-byte aligned");
@@ -754,6 +1126,18 @@ int fft_plan_describe(fft_plan p, fft_plan_desc* d)
 {
     if (!p || !d)
         return set_err(FFT_ENULL, "plan or desc is NULL");
+    if (p->kind == 2) {
+        // the last axis's kernel shape, with the whole plan's sizes
+        fft_plan_describe(p->last, d);
+        d->n = p->n;
+        d->batch = p->batch;
+        d->scale = p->scale;
+        d->kind = 2;
+        d->rank = p->rank;
+        for (int a = 0; a < 3; a++)
+            d->dims[a] = a < p->rank ? p->dims[a] : 0;
+        return ok();
+    }
     if (p->kind == 1) {
         memset(d, 0, sizeof *d);
         d->n = 0;
@@ -765,7 +1149,9 @@ int fft_plan_describe(fft_plan p, fft_plan_desc* d)
         ragged_describe(p->ragged, &d->wg, &d->grid, &d->tiles, &d->lds_bytes, d->ept_by_log2n);
         return ok();
     }
-    if (p->dtype == FFT_C32) {
+    if (p->dtype == FFT_R32) {
+        fill_desc_r32(p->n, p->batch, p->sign, p->var, p->grid_limit, d);
+    } else if (p->dtype == FFT_C32) {
         fill_desc_c32(p->n, p->batch, p->sign, p->dtype, p->var, p->grid_limit, d);
     } else {
         memset(d, 0, sizeof *d);
@@ -786,6 +1172,13 @@ int fft_plan_query(int64_t n, int64_t batch, int sign, int dtype, fft_plan_desc*
     int rc = check_common(n, batch, sign, dtype);
     if (rc != FFT_OK)
         return rc;
+    if (dtype == FFT_R32) {
+        const Variant v = choose_r32(ilog2(n) - 1);
+        if (!find_real(ilog2(n) - 1, v.log2ept, v.wg, sign < 0 ? 0 : 1, v.kind))
+            return set_err(FFT_EINVAL_CONFIG, "no real-input kernel compiled for n=%lld", (long long)n);
+        fill_desc_r32(n, batch, sign, v, 0, d);
+        return ok();
+    }
     if (dtype != FFT_C32) {
         if (!half_supported(n))
             return set_err(FFT_EINVAL_DTYPE, "FP16/BF16 plans support n in {%s}", half_supported_lengths());
@@ -798,7 +1191,10 @@ int fft_plan_query(int64_t n, int64_t batch, int sign, int dtype, fft_plan_desc*
         half_query(n, batch, d);
         return ok();
     }
-    fill_desc_c32(n, batch, sign, dtype, choose_c32(ilog2(n)), 0, d);
+    const Variant v = choose_c32(ilog2(n));
+    if (v.kind == 9 ? !find_fourstep(ilog2(n)) : !find_c32(ilog2(n), v.log2ept, v.wg, sign, v.kind))
+        return set_err(FFT_EINVAL_CONFIG, "no FP32 kernel compiled for n=%lld", (long long)n);
+    fill_desc_c32(n, batch, sign, dtype, v, 0, d);
     return ok();
 }
 

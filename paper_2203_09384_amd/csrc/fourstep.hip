@@ -17,26 +17,12 @@
 // FP32 table (w_N^{1024 a} and w_N^{b}, both from FP64 sincospi).
 #include "device_fft.hpp"
 #include "fourstep.hpp"
+#include "tile_fft.hpp"
 
 namespace mifft {
 namespace {
 
 constexpr int TILE = 16;
-
-// log2 EPT of an inner transform of length 2^Li: 16 threads per transform
-// up to 256 points, then 16 points per thread (at most 64 threads).
-constexpr int inner_e(int Li) { return Li <= 6 ? 2 : (Li == 7 ? 3 : 4); }
-
-// Staging stride (complex elements) of one transform's LDS region: the
-// padded Stockham region rounded up to 4 (mod 32), which spreads the 16
-// transforms of a tile over distinct banks when the tile is staged.
-template <int Li, int Ei>
-constexpr int stage_stride()
-{
-    const int reg = Layout2<Li, Ei>::region();
-    const int r = reg % 32;
-    return reg + ((4 - r + 32) % 32);
-}
 
 template <int S>
 __device__ __forceinline__ cf big_twiddle(const cf* __restrict__ lo, const cf* __restrict__ hi, unsigned j)

@@ -1,0 +1,35 @@
+// Host-side registry of the real-input (FFT_R32) kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace mifft {
+
+// in/out: device buffers (real n values or n/2+1 complex bins per transform,
+// by direction); rows: per-pass twiddle rows of the half-length transform;
+// wn: w_n^k for k < n/2.  we / wi: weights of the edge bins (0, n/2) and of
+// the interior bins (see real.hip).  grid_limit: workgroups of a persistent
+// launch (0 = one per transform group).
+using LaunchReal = hipError_t (*)(const void* in, void* out, const void* rows, const void* wn, int64_t batch,
+                                  float we, float wi, int64_t grid_limit, hipStream_t stream);
+
+struct KernelReal {
+    int log2m;    // log2 of the half length n/2 (0..14)
+    int log2ept;  // complex elements per thread of the half-length transform
+    int wg;
+    int dir;      // 0: real -> bins (R2C), 1: bins -> real (C2R)
+    int kind;     // 0: a whole half-length transform per thread; else as FP32 variants 1..8
+    LaunchReal fn;
+    int (*occupancy)();
+    int rows;       // twiddle-row entries (float2) the kernel reads
+    int lds_bytes;  // LDS per workgroup
+};
+
+void register_real(const KernelReal& k);
+const KernelReal* find_real(int log2m, int log2ept, int wg, int dir, int kind);
+
+hipError_t launch_twiddle_real(const void* tw, void* wn, int log2n, hipStream_t stream);
+
+}  // namespace mifft

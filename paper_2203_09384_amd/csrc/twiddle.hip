@@ -105,3 +105,32 @@ hipError_t launch_twiddle_rows(const void* tw, void* rows, int L, int E, int tot
 }
 
 }  // namespace mifft
+
+namespace mifft {
+
+// Twiddles of the real-input split: wn[k] = w_n^k = exp(-2 pi i k / n) for
+// k < n/2.  Copies of the 2048-entry table for n <= 2048 (twiddles
+// identical to the complex kernels'); FP64 sincospi rounded once above.
+__global__ void k_twiddle_real(const float2* __restrict__ tw, float2* __restrict__ wn, int log2n)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= (1 << (log2n - 1)))
+        return;
+    if (log2n <= 11) {
+        wn[k] = tw[k << (11 - log2n)];
+    } else {
+        double sn, cs;
+        sincospi(2.0 * (double)k / (double)(1 << log2n), &sn, &cs);
+        wn[k] = float2{(float)cs, (float)(-sn)};
+    }
+}
+
+hipError_t launch_twiddle_real(const void* tw, void* wn, int log2n, hipStream_t stream)
+{
+    const int m = 1 << (log2n - 1);
+    hipLaunchKernelGGL(k_twiddle_real, dim3((m + 255) / 256), dim3(256), 0, stream, static_cast<const float2*>(tw),
+                       static_cast<float2*>(wn), log2n);
+    return hipGetLastError();
+}
+
+}  // namespace mifft

@@ -13,7 +13,7 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmifft.so")
 
-FFT_C32, FFT_C16, FFT_CBF16 = 0, 1, 2
+FFT_C32, FFT_C16, FFT_CBF16, FFT_R32 = 0, 1, 2, 3
 STATUS = {
     0: "FFT_OK", 1: "FFT_EINVAL_N", 2: "FFT_EINVAL_BATCH", 3: "FFT_EINVAL_SIGN",
     4: "FFT_EINVAL_DTYPE", 5: "FFT_ENULL", 6: "FFT_EOVERLAP", 7: "FFT_EINVAL_OFFSETS",
@@ -24,7 +24,7 @@ EXPORTS = [
     "fft_plan_create_ragged_config", "fft_execute", "fft_execute_adjoint",
     "fft_execute_scaled", "fft_plan_destroy", "fft_plan_describe", "fft_plan_query",
     "fft_plan_twiddles", "fft_last_error", "fft_last_error_string", "fft_version",
-    "fft_execute_loss_grad",
+    "fft_execute_loss_grad", "fft_plan_create_nd",
 ]
 
 
@@ -35,13 +35,14 @@ class PlanDesc(ctypes.Structure):
         ("wg", ctypes.c_int), ("transforms_per_wg", ctypes.c_int), ("grid", ctypes.c_int64),
         ("npasses", ctypes.c_int), ("radices", ctypes.c_int * 8), ("lds_bytes", ctypes.c_int),
         ("kind", ctypes.c_int), ("tiles", ctypes.c_int64), ("variant", ctypes.c_int),
-        ("ept_by_log2n", ctypes.c_int * 12),
+        ("ept_by_log2n", ctypes.c_int * 12), ("rank", ctypes.c_int), ("dims", ctypes.c_int64 * 3),
     ]
 
     def as_dict(self):
-        d = {k: getattr(self, k) for k, _ in self._fields_ if k not in ("radices", "ept_by_log2n")}
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k not in ("radices", "ept_by_log2n", "dims")}
         d["radices"] = list(self.radices)[: self.npasses]
         d["ept_by_log2n"] = list(self.ept_by_log2n)
+        d["dims"] = list(self.dims)[: self.rank]
         return d
 
 
@@ -72,6 +73,8 @@ def _declare(L):
     L.fft_plan_create.restype = vp
     L.fft_plan_create_config.argtypes = [i64, i64, i32, i32, i32, i32, i32]
     L.fft_plan_create_config.restype = vp
+    L.fft_plan_create_nd.argtypes = [i32, ctypes.POINTER(i64), i64, i32, i32]
+    L.fft_plan_create_nd.restype = vp
     L.fft_plan_create_ragged.argtypes = [i64, ctypes.POINTER(i64), i32, i32]
     L.fft_plan_create_ragged.restype = vp
     L.fft_plan_create_ragged_config.argtypes = [i64, ctypes.POINTER(i64), i32, i32,

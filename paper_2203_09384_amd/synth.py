@@ -18,6 +18,7 @@ SEED_PLAIN = 20220317        # N=256 batch 64 and the per-N sweep
 SEED_AUTOGRAD = 20220318     # x and w of the differentiable-loss workload
 SEED_RAGGED = 20220319       # ragged lengths and values
 SEED_HALF = 20220320         # reduced-precision inputs
+SEED_REAL = 20220321         # real-input transforms
 
 
 def rng(seed: int, *key: int) -> np.random.Generator:
@@ -34,6 +35,12 @@ def uniform_complex(seed: int, shape, key=(), dtype=np.complex64) -> np.ndarray:
     out.real = re
     out.imag = im
     return out
+
+
+def uniform_real(seed: int, shape, key=(), dtype=np.float32) -> np.ndarray:
+    """i.i.d. uniform[-1, 1), drawn in float64 then rounded to dtype."""
+    g = rng(seed, *key)
+    return g.uniform(-1.0, 1.0, size=tuple(np.atleast_1d(shape))).astype(dtype)
 
 
 def log_uniform_polar(seed: int, shape, key=(), lo: float = 1e-3, hi: float = 1e3) -> np.ndarray:

@@ -5,7 +5,9 @@ workgroup size) variant compiled into libmifft.so on a batch of `total`
 elements, and keeps the fastest.  For ragged batches it picks, per length,
 the elements-per-thread of the persistent kernel and the workgroup size of
 the launch, timing one graph-free persistent launch over a seeded ragged
-batch.  The result is a text table ("c32 <log2n> <ept> <wg> <variant>" and
+batch.  Real-input plans (R2C and C2R) are tuned per half length on the
+sum of both directions' times.  The result is a text table ("c32 <log2n>
+<ept> <wg> <variant>", "r32 <log2(n/2)> <ept> <wg> <variant>" and
 "ragged <log2n> <ept>" / "ragged_wg <wg> <ctas_per_cu>" lines) that the library reads
 from the file named by MIFFT_TUNE_TABLE, plus a JSON record of every
 timing.
@@ -70,6 +72,48 @@ def tune_c32(total: int = 1 << 26, steps: int = 30, warmup: int = 5, log2ns=rang
     return best, record
 
 
+REAL_EPTS = (1, 2, 4, 8, 16)
+REAL_VARIANTS = (0, 2, 3, 6, 7)
+
+
+def tune_real(total: int = 1 << 27, steps: int = 30, warmup: int = 5, log2ns=range(2, 16), log=print):
+    """Real-input plans: every compiled (ept, wg, variant) of the half-length
+    transform, timed as R2C plus C2R over `total` float32 reals."""
+    import torch
+    from . import api, synth
+    from .native import MifftError
+    xr = torch.from_numpy(synth.uniform_real(synth.SEED_REAL, (total,), key=(0,))).cuda()
+    back = torch.empty_like(xr)
+    best, record = {}, []
+    for L in log2ns:
+        n = 1 << L
+        b = total // n
+        xs, bs = xr[: b * n].view(b, n), back[: b * n].view(b, n)
+        bins = torch.empty(b, n // 2 + 1, dtype=torch.complex64, device=xr.device)
+        for ept in REAL_EPTS:
+            for wg in WGS:
+                for var in REAL_VARIANTS:
+                    try:
+                        pf = api.Plan(n, b, -1, "r32", ept=ept, wg=wg, variant=var)
+                        pi = api.Plan(n, b, +1, "r32", ept=ept, wg=wg, variant=var)
+                    except MifftError:
+                        continue
+                    ms_f = _time(lambda: pf.execute(xs, bins), steps, warmup, torch)
+                    ms_i = _time(lambda: pi.execute(bins, bs), steps, warmup, torch)
+                    alg = b * (4.0 * n + 8.0 * (n // 2 + 1))
+                    rec = {"n": n, "ept": ept, "wg": wg, "variant": var, "r2c_us": round(ms_f * 1e3, 2),
+                           "c2r_us": round(ms_i * 1e3, 2), "r2c_GBps": round(alg / (ms_f * 1e-3) / 1e9, 1),
+                           "c2r_GBps": round(alg / (ms_i * 1e-3) / 1e9, 1)}
+                    record.append(rec)
+                    log(f"[tune-real] {rec}")
+                    if L - 1 not in best or ms_f + ms_i < best[L - 1][3]:
+                        best[L - 1] = (ept, wg, var, ms_f + ms_i)
+                    pf.close()
+                    pi.close()
+        del bins
+    return best, record
+
+
 def tune_ragged(count: int = 4096, iters: int = 300, log=print):
     """Per-length elements per thread and the workgroup size of the ragged
     persistent kernel, by coordinate descent on one seeded ragged batch
@@ -115,12 +159,15 @@ def tune_ragged(count: int = 4096, iters: int = 300, log=print):
             "us": round(best[2] * 1e3, 2)}, record
 
 
-def write_table(path: str, best_c32: dict, ragged: dict | None = None):
+def write_table(path: str, best_c32: dict, ragged: dict | None = None, best_r32: dict | None = None):
     with open(path, "w") as f:
         f.write("# mifft tuned variants for gfx950 (written by paper_2203_09384_amd.tune)\n")
         for L in sorted(best_c32):
             ept, wg, var, ms = best_c32[L]
             f.write(f"c32 {L} {ept} {wg} {var}  # {ms * 1e3:.2f} us\n")
+        for L in sorted(best_r32 or {}):
+            ept, wg, var, ms = best_r32[L]
+            f.write(f"r32 {L} {ept} {wg} {var}  # r2c + c2r {ms * 1e3:.2f} us\n")
         if ragged:
             for L in sorted(ragged.get("ept", {})):
                 f.write(f"ragged {L} {ragged['ept'][L]}\n")
@@ -136,16 +183,21 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--skip-c32", action="store_true")
     ap.add_argument("--skip-ragged", action="store_true")
+    ap.add_argument("--skip-real", action="store_true")
     args = ap.parse_args(argv)
     log = lambda m: print(m, file=sys.stderr, flush=True)
     best, rec = ({}, []) if args.skip_c32 else tune_c32(1 << args.total_log2, args.steps, log=log)
     rbest, rrec = (None, []) if args.skip_ragged else tune_ragged(log=log)
-    write_table(args.out, best, rbest)
+    real_best, real_rec = ({}, []) if args.skip_real else tune_real(1 << (args.total_log2 + 1), args.steps,
+                                                                      log=log)
+    write_table(args.out, best, rbest, real_best)
     if args.json:
         with open(args.json, "w") as f:
             json.dump({"c32": rec, "best": {L: best[L][:3] for L in best}, "ragged": rrec,
-                       "ragged_best": rbest}, f, indent=1)
-    print(json.dumps({"c32": {L: best[L][:3] for L in best}, "ragged": rbest}))
+                       "ragged_best": rbest, "real": real_rec,
+                       "real_best": {L: real_best[L][:3] for L in real_best}}, f, indent=1)
+    print(json.dumps({"c32": {L: best[L][:3] for L in best}, "ragged": rbest,
+                      "r32": {L: real_best[L][:3] for L in real_best}}))
 
 
 if __name__ == "__main__":

@@ -142,3 +142,48 @@ def test_tune_table_is_read(tmp_path):
     out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=120)
     assert out.returncode == 0, out.stderr
     assert out.stdout.split() == ["4", "64", "2", "8", "256", "4"]
+
+
+# ---------------------------------------------------------------- real input
+@pytest.mark.parametrize("L", range(1, 16))
+def test_real_input_queries(L):
+    """FFT_R32 plans describe the half-length complex transform they run;
+    every built-in choice is a compiled kernel (query checks that)."""
+    n, m = 1 << L, 1 << (L - 1)
+    for sign in (-1, 1):
+        rc, d = q(n, 1000, sign, 3)
+        assert rc == 0, native.lib().fft_last_error_string()
+        assert d.dtype == 3 and d.n == n
+        assert int(np.prod(list(d.radices)[: d.npasses])) == m
+        assert d.ept * (d.wg // d.transforms_per_wg) == m
+        assert d.grid == -(-1000 // d.transforms_per_wg)
+        assert d.scale == (1.0 if sign < 0 else np.float32(1.0 / n))
+
+
+def test_real_input_validation():
+    L = native.lib()
+    assert q(1 << 16, 1, -1, 3)[0] == 1      # real lengths stop at 2^15
+    assert q(24, 1, -1, 3)[0] == 1
+    assert L.fft_plan_create(1 << 16, 1, -1, 3) is None and L.fft_last_error() == 1
+    assert L.fft_plan_create_config(256, 1, -1, 3, 4, 64, 5) is None and L.fft_last_error() == 10
+    assert L.fft_plan_create_config(256, 1, -1, 3, 4, 48, 2) is None and L.fft_last_error() == 10
+
+
+def test_nd_validation():
+    """fft_plan_create_nd checks its arguments before touching a device."""
+    L = native.lib()
+
+    def create(dims, batch=1, sign=-1, dtype=0, rank=None):
+        arr = (ctypes.c_int64 * max(1, len(dims)))(*dims)
+        h = L.fft_plan_create_nd(len(dims) if rank is None else rank, arr, batch, sign, dtype)
+        return h, L.fft_last_error()
+
+    assert create([4, 4], rank=0) == (None, 1)
+    assert create([4, 4, 4, 4]) == (None, 1)
+    assert create([4096, 4]) == (None, 1)       # non-last axes stop at 2048
+    assert create([12, 4]) == (None, 1)
+    assert create([4, 1 << 21]) == (None, 1)
+    assert create([4, 4], batch=0) == (None, 2)
+    assert create([4, 4], sign=0) == (None, 3)
+    assert create([4, 4], dtype=1) == (None, 4)
+    assert L.fft_plan_create_nd(2, None, 1, -1, 0) is None and L.fft_last_error() == 5

@@ -1,0 +1,83 @@
+"""Multidimensional FP32 transforms (2D / 3D) on the GPU against the FP64
+oracle's fftn (pinned in the oracle's own tests).  Bar: max over arrays of
+the relative L2 error <= 1e-5."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2203_09384_amd import api, synth
+from gpu_util import need_gpu, to_cpu, to_gpu
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-5
+SEED_ND = 20220322
+
+SHAPES = [(2, 2), (4, 8), (8, 2), (16, 2048), (2048, 16), (64, 64), (2, 4096), (4, 65536), (8, 4, 2), (2, 2, 2),
+          (32, 64, 8), (16, 16, 16), (4, 2048, 4), (2048, 2, 2)]
+
+
+@pytest.fixture(autouse=True)
+def _gpu():
+    need_gpu()
+
+
+def per_array_relerr(y, ref, ndim):
+    y = np.asarray(y, np.complex128)
+    ref = np.asarray(ref, np.complex128)
+    axes = tuple(range(y.ndim - ndim, y.ndim))
+    num = np.sqrt(np.sum(np.abs(y - ref) ** 2, axis=axes))
+    den = np.sqrt(np.sum(np.abs(ref) ** 2, axis=axes))
+    return float(np.max(num / np.where(den == 0, 1, den)))
+
+
+@pytest.mark.parametrize("shape", SHAPES, ids=lambda s: "x".join(map(str, s)))
+@pytest.mark.parametrize("sign", [-1, 1])
+def test_nd_parity(shape, sign):
+    n = int(np.prod(shape))
+    batch = 3 if n <= 65536 else 1
+    x = synth.uniform_complex(SEED_ND, (batch,) + shape, key=shape + (sign + 1,))
+    p = api.PlanND(shape, batch, sign)
+    print(f"[case] nd shape={shape} batch={batch} sign={sign} {p.describe()}", flush=True)
+    y = to_cpu(p.execute(to_gpu(x)))
+    ref = oracle.fftn(x.astype(np.complex128), len(shape), sign, 1.0 if sign < 0 else 1.0 / n)
+    assert per_array_relerr(y, ref, len(shape)) <= TOL
+    # adjoint: opposite sign, same scale
+    g = synth.uniform_complex(SEED_ND, (batch,) + shape, key=shape + (sign + 5,))
+    a = to_cpu(p.adjoint(to_gpu(g)))
+    ref = oracle.fftn(g.astype(np.complex128), len(shape), -sign, 1.0 if sign < 0 else 1.0 / n)
+    assert per_array_relerr(a, ref, len(shape)) <= TOL
+
+
+def test_nd_full_size_sampled():
+    """2048 x 2048, batch 16 (2^26 elements, 512 MiB each way): two arrays
+    against the oracle, Parseval on every array, and the round trip."""
+    shape, batch = (2048, 2048), 16
+    x = synth.uniform_complex(SEED_ND, (batch,) + shape, key=(99,))
+    xg = to_gpu(x)
+    print(f"[case] nd full size {shape} batch={batch}", flush=True)
+    y = api.PlanND(shape, batch, -1).execute(xg)
+    for b in (0, batch - 1):
+        ys = to_cpu(y[b])
+        assert per_array_relerr(ys[None], oracle.fftn(x[b:b + 1].astype(np.complex128), 2), 2) <= TOL
+    e_in = torch.sum(torch.abs(xg.to(torch.complex128)) ** 2, dim=(1, 2))
+    e_out = torch.sum(torch.abs(y.to(torch.complex128)) ** 2, dim=(1, 2))
+    assert torch.max(torch.abs(e_out / (e_in * (2048 * 2048)) - 1)).item() < 1e-5
+    back = api.PlanND(shape, batch, +1).execute(y)
+    assert per_array_relerr(to_cpu(back), x, 2) <= 2 * TOL
+
+
+def test_functional_and_autograd():
+    x = synth.uniform_complex(SEED_ND, (3, 8, 32), key=(7,))
+    X = to_cpu(api.fft2(to_gpu(x)))
+    assert per_array_relerr(X, oracle.fftn(x.astype(np.complex128), 2), 2) <= TOL
+    back = to_cpu(api.ifft2(to_gpu(X.astype(np.complex64))))
+    assert per_array_relerr(back, x, 2) <= 2 * TOL
+    # gradient of sum w |fftn(x)|^2 = F^H (2 w F x)
+    w = synth.uniform_weights(SEED_ND, (3, 8, 32), key=(8,))
+    xg = to_gpu(x).requires_grad_(True)
+    y = api.fftn_differentiable(xg, 2)
+    (to_gpu(w) * (y.real ** 2 + y.imag ** 2)).sum().backward()
+    x64 = x.astype(np.complex128)
+    ref = oracle.fftn(2.0 * w * oracle.fftn(x64, 2), 2, +1, 1.0)
+    assert per_array_relerr(xg.grad.cpu().numpy(), ref, 2) <= TOL
