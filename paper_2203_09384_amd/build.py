@@ -33,6 +33,7 @@ def _units():
         units.append(("real.hip", f"real_M{L}.o", [f"-DMIFFT_LOG2M={L}"]))
     units.append(("twiddle.hip", "twiddle.o", []))
     units.append(("fourstep.hip", "fourstep.o", []))
+    units.append(("nd.hip", "nd.o", []))
     for wg in (64, 128, 256):
         units.append(("ragged.hip", f"ragged_wg{wg}.o", [f"-DMIFFT_RAGGED_WG={wg}"]))
     units.append(("ragged_plan.cpp", "ragged_plan.o", ["-x", "hip"]))

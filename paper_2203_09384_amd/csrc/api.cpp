@@ -777,7 +777,11 @@ fft_plan create_nd(int rank, const int64_t* dims, int64_t batch, int sign, int d
         return create_batched(dims[0], batch, sign, dtype, nullptr);
     for (int a = 0; a + 1 < rank; a++) {
         const KernelAxis* k = find_axis(ilog2(dims[a]), sign);
-        if (!k || (batch * (n / dims[a]) + k->tile - 1) / k->tile > 0x7fffffffLL - 16) {
+        if (!k) {
+            set_err(FFT_EINVAL_CONFIG, "no axis kernel compiled for length %lld", (long long)dims[a]);
+            return nullptr;
+        }
+        if ((batch * (n / dims[a]) + k->tile - 1) / k->tile > 0x7fffffffLL - 16) {
             set_err(FFT_EINVAL_BATCH, "axis %d: batch=%lld needs more than 2^31-1 workgroups", a,
                     (long long)batch);
             return nullptr;

@@ -187,3 +187,17 @@ def test_nd_validation():
     assert create([4, 4], sign=0) == (None, 3)
     assert create([4, 4], dtype=1) == (None, 4)
     assert L.fft_plan_create_nd(2, None, 1, -1, 0) is None and L.fft_last_error() == 5
+
+
+@pytest.mark.skipif(torch.cuda.is_available(), reason="checks the no-device path")
+def test_nd_axis_kernels_are_compiled():
+    """Valid multidimensional plans get past the kernel lookup for every
+    axis length (they fail only for want of a device here)."""
+    L = native.lib()
+    for d0 in [1 << k for k in range(1, 12)]:
+        arr = (ctypes.c_int64 * 3)(d0, 4, 8)
+        assert L.fft_plan_create_nd(3, arr, 2, -1, 0) is None
+        assert L.fft_last_error() == 8, (d0, L.fft_last_error_string())
+        arr = (ctypes.c_int64 * 2)(d0, 16)
+        assert L.fft_plan_create_nd(2, arr, 2, 1, 0) is None
+        assert L.fft_last_error() == 8, (d0, L.fft_last_error_string())
