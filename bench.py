@@ -142,6 +142,27 @@ def bench_real(api, torch, dev, steps, x_all):
     return res
 
 
+def bench_nd(api, torch, steps, x_all, y_all):
+    """2D 2048 x 2048 (batch 16) and 3D 128^3 (batch 32) forward transforms,
+    2^26 complex64 elements each way; one HBM pass per axis."""
+    res = {"workload": "multidimensional C2C forward FFT, 2^26 complex64 elements (512 MiB in + 512 MiB out); "
+                       "the last axis through the batched kernels, each other axis one in-place tiled pass"}
+    for name, shape, batch in (("2d_2048x2048", (2048, 2048), 16), ("3d_128x128x128", (128, 128, 128), 32)):
+        p = api.PlanND(shape, batch, -1)
+        xs = x_all.view((batch,) + shape)
+        ys = y_all.view((batch,) + shape)
+        m = time_launches(lambda: p.execute(xs, ys), max(20, steps // 2), 5, torch)
+        elems = batch
+        for d in shape:
+            elems *= d
+        res[name] = {"us": round(m * 1e3, 2), "passes_over_hbm": len(shape),
+                     "GBps_algorithmic": round(16.0 * elems / (m * 1e-3) / 1e9, 1),
+                     "GBps_actual_passes": round(16.0 * len(shape) * elems / (m * 1e-3) / 1e9, 1),
+                     "GFLOPs": round(5.0 * elems * math.log2(elems // batch) / (m * 1e-3) / 1e9, 1)}
+        p.close()
+    return res
+
+
 def bench_ragged(api, synth, torch, dev, iters):
     """One persistent launch over 4096 mixed-length transforms (eager and
     graph-replayed) against per-length plain launches (eager and in one
@@ -382,6 +403,10 @@ def main():
         # ------------------------------------------------------------ real input
         out["real"] = bench_real(api, torch, dev, args.steps, x_all)
         log(f"[bench] real {out['real']}")
+
+        # ------------------------------------------------------------ multidimensional
+        out["nd"] = bench_nd(api, torch, args.steps, x_all, y_all)
+        log(f"[bench] nd {out['nd']}")
 
         # ------------------------------------------------------------ ragged
         out["ragged"] = bench_ragged(api, synth, torch, dev, max(200, args.steps * 5))
