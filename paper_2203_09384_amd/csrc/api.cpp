@@ -169,22 +169,23 @@ const Variant kDefaultC32[21] = {
 };
 
 // Real-input transforms (FFT_R32), per log2 of the half length M = n/2
-// (index 0..14): the half-length complex transform's configuration.
+// (index 0..14): the half-length transform's configuration, the
+// autotuner's pick on MI355X (R2C + C2R over 2^27 reals).
 const Variant kDefaultR32[15] = {
     {0, 256, 0},   // n=2     one thread per transform, no passes
     {1, 64, 0},    // n=4     the half-length transform inside one thread
     {2, 128, 0},   // n=8
-    {2, 256, 2},   // n=16
+    {3, 256, 0},   // n=16
     {2, 256, 2},   // n=32
-    {2, 256, 2},   // n=64
-    {2, 64, 6},    // n=128   wavefront-local exchanges
-    {3, 64, 6},    // n=256
-    {4, 256, 6},   // n=512
-    {3, 64, 6},    // n=1024
-    {4, 64, 3},    // n=2048  persistent, next-group prefetch
+    {2, 128, 2},   // n=64
+    {2, 256, 2},   // n=128
+    {3, 256, 6},   // n=256   wavefront-local exchanges
+    {3, 256, 6},   // n=512
+    {3, 256, 7},   // n=1024  wavefront-local, persistent
+    {4, 128, 3},   // n=2048  persistent, next-group prefetch
     {4, 128, 3},   // n=4096
-    {3, 512, 3},   // n=2^13  one transform per workgroup
-    {3, 1024, 3},  // n=2^14
+    {4, 256, 3},   // n=2^13  one transform per workgroup
+    {3, 1024, 2},  // n=2^14
     {4, 1024, 2},  // n=2^15
 };
 
