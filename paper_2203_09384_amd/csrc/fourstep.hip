@@ -11,10 +11,12 @@
 //           X[k1 + N1 k2] (times the plan's scale).
 // Each workgroup owns a tile of 16 transforms (16 columns, or 16 rows k1)
 // so that every global load and store is a run of 16 complex values (one
-// 128-byte line); the tile is staged through LDS, transformed with the same
-// Stockham passes as the batched kernels (each transform inside one
-// wavefront) and staged back for the store.  w_N^j is built from a two-level
-// FP32 table (w_N^{1024 a} and w_N^{b}, both from FP64 sincospi).
+// 128-byte line), and transforms them with the same Stockham passes as the
+// batched kernels.  Long inner transforms are read straight into registers
+// (the tile's transform index is the fastest lane index); short ones are
+// staged through LDS so that their exchanges stay inside one wavefront.
+// w_N^j is built from a two-level FP32 table (w_N^{1024 a} and w_N^{b},
+// both from FP64 sincospi).
 #include "device_fft.hpp"
 #include "fourstep.hpp"
 #include "tile_fft.hpp"
@@ -33,7 +35,12 @@ __device__ __forceinline__ cf big_twiddle(const cf* __restrict__ lo, const cf* _
     return w;
 }
 
-// Pass 1: tile = columns n2 in [16 nb, 16 nb + 16) of transform b.
+// Pass 1: tile = columns n2 in [16 nb, 16 nb + 16) of transform b.  Long
+// columns (axis_direct) are read straight into registers (the column index
+// is the fastest lane index: rows of 16 values per wavefront access);
+// short ones are staged through LDS so their exchanges stay inside one
+// wavefront.  Either way the outputs go out through LDS: the tile's
+// outputs Y[k1 + N1 n2] form one contiguous block.
 template <int L1, int L2, int S>
 __global__ __launch_bounds__(TILE*((1 << L1) >> inner_e(L1))) void k_fourstep1(
     const cf* __restrict__ in, cf* __restrict__ out, const cf* __restrict__ rows, const cf* __restrict__ tlo,
@@ -41,44 +48,52 @@ __global__ __launch_bounds__(TILE*((1 << L1) >> inner_e(L1))) void k_fourstep1(
 {
     constexpr int E = inner_e(L1), N1 = 1 << L1, N2 = 1 << L2, N = N1 * N2;
     constexpr int EPT = 1 << E, TPT = N1 / EPT, WG = TILE * TPT, ST = stage_stride<L1, E>();
+    constexpr bool DIRECT = axis_direct(L1);
     __shared__ cf lds[TILE * ST];
     const int tid = threadIdx.x;
     const int64_t b = blockIdx.x / (N2 / TILE);
     const int nb = blockIdx.x % (N2 / TILE);
     const cf* src = in + b * N + nb * TILE;
-    // stage: 16 consecutive columns per row n1 (one 128-byte line)
-#pragma unroll
-    for (int i = 0; i < TILE * N1 / WG; i++) {
-        const int idx = tid + i * WG;
-        const int c = idx & (TILE - 1), n1 = idx >> 4;
-        lds[c * ST + n1] = src[(int64_t)n1 * N2 + c];
-    }
-    __syncthreads();
-    const int tb = tid / TPT, t = tid % TPT;
+    // thread (tb, t): transform tb of the tile, thread t of that transform
+    const int tb = DIRECT ? (tid & (TILE - 1)) : tid / TPT;
+    const int t = DIRECT ? (tid >> 4) : tid % TPT;
     cf* my = lds + tb * ST;
     cf v[EPT];
+    if constexpr (DIRECT) {
 #pragma unroll
-    for (int m = 0; m < EPT; m++)
-        v[m] = my[t + m * TPT];
+        for (int m = 0; m < EPT; m++)
+            v[m] = src[(int64_t)(t + m * TPT) * N2 + tb];
+    } else {
+        // stage: 16 consecutive columns per row n1 (one 128-byte line)
+#pragma unroll
+        for (int i = 0; i < TILE * N1 / WG; i++) {
+            const int idx = tid + i * WG;
+            const int c = idx & (TILE - 1), n1 = idx >> 4;
+            lds[c * ST + n1] = src[(int64_t)n1 * N2 + c];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < EPT; m++)
+            v[m] = my[t + m * TPT];
+    }
     TwRegs<L1, E> tws;
-#pragma unroll
-    for (int p = 0; p < Sched<L1, E>::NP; p++)
-#pragma unroll
-        for (int r = 0; r < EPT; r++)
-            tws[p][r] = cf{1.f, 0.f};
-    run2<L1, E, S, 1, true>(v, t, rows, tws, my);  // transform tb lives in one wavefront
+    unit_rows<L1, E>(tws);
+    constexpr bool WAVE = DIRECT ? TPT * TILE <= 64 : TPT <= 64;
+    run2<L1, E, S, 1, WAVE>(v, t, rows, tws, my);
     const unsigned n2 = nb * TILE + tb;
 #pragma unroll
     for (int m = 0; m < EPT; m++) {
         const unsigned k1 = t + m * TPT;
         v[m] = cmul(v[m], big_twiddle<S>(tlo, thi, n2 * k1));
     }
-    lds_sync<true>();  // this wavefront's last exchange is read
+    if constexpr (DIRECT)
+        __syncthreads();  // every transform's last exchange is read
+    else
+        lds_sync<true>();  // this wavefront's last exchange is read
 #pragma unroll
     for (int m = 0; m < EPT; m++)
         my[t + m * TPT] = v[m];
     __syncthreads();
-    // the tile's outputs Y[k1 + N1 n2] form one contiguous block
     cf* dst = out + b * N + (int64_t)nb * TILE * N1;
 #pragma unroll
     for (int i = 0; i < TILE * N1 / WG; i++) {
@@ -89,50 +104,20 @@ __global__ __launch_bounds__(TILE*((1 << L1) >> inner_e(L1))) void k_fourstep1(
 }
 
 // Pass 2 (in place): tile = rows k1 in [16 kb, 16 kb + 16) of transform b,
-// elements Y[k1 + N1 n2]; outputs X[k1 + N1 k2] at the same addresses.
+// elements Y[k1 + N1 n2] (stride N1 along n2); outputs X[k1 + N1 k2] at the
+// same addresses: the axis pass of a multidimensional transform with
+// stride N1 over batch * N1 transforms.
 template <int L1, int L2, int S>
-__global__ __launch_bounds__(TILE*((1 << L2) >> inner_e(L2))) void k_fourstep2(cf* __restrict__ io,
-                                                                              const cf* __restrict__ rows,
-                                                                              float scale)
+__global__ __launch_bounds__(axis_wg<L2>()) void k_fourstep2(cf* __restrict__ io, const cf* __restrict__ rows,
+                                                            int64_t count, float scale)
 {
-    constexpr int E = inner_e(L2), N1 = 1 << L1, N2 = 1 << L2, N = N1 * N2;
-    constexpr int EPT = 1 << E, TPT = N2 / EPT, WG = TILE * TPT, ST = stage_stride<L2, E>();
-    __shared__ cf lds[TILE * ST];
-    const int tid = threadIdx.x;
-    const int64_t b = blockIdx.x / (N1 / TILE);
-    const int kb = blockIdx.x % (N1 / TILE);
-    cf* base = io + b * N + kb * TILE;
-#pragma unroll
-    for (int i = 0; i < TILE * N2 / WG; i++) {
-        const int idx = tid + i * WG;
-        const int c = idx & (TILE - 1), n2 = idx >> 4;
-        lds[c * ST + n2] = base[(int64_t)n2 * N1 + c];
-    }
-    __syncthreads();
-    const int tb = tid / TPT, t = tid % TPT;
-    cf* my = lds + tb * ST;
-    cf v[EPT];
-#pragma unroll
-    for (int m = 0; m < EPT; m++)
-        v[m] = my[t + m * TPT];
-    TwRegs<L2, E> tws;
-#pragma unroll
-    for (int p = 0; p < Sched<L2, E>::NP; p++)
-#pragma unroll
-        for (int r = 0; r < EPT; r++)
-            tws[p][r] = cf{1.f, 0.f};
-    run2<L2, E, S, 1, true>(v, t, rows, tws, my);
-    lds_sync<true>();
-#pragma unroll
-    for (int m = 0; m < EPT; m++)
-        my[t + m * TPT] = cscale(v[m], scale);
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < TILE * N2 / WG; i++) {
-        const int idx = tid + i * WG;
-        const int c = idx & (TILE - 1), k2 = idx >> 4;
-        base[(int64_t)k2 * N1 + c] = lds[c * ST + k2];
-    }
+    static_assert(axis_tile(L2) == TILE, "row tiles of 16");
+    __shared__ cf lds[TILE * stage_stride<L2, axis_e(L2)>()];
+    const int64_t q0 = (int64_t)blockIdx.x * TILE;
+    if constexpr (axis_direct(L2))
+        axis_tile_direct<L2, S>(io, rows, lds, q0, count, L1, scale);
+    else
+        axis_tile_staged<L2, S>(io, rows, lds, q0, count, L1, scale);
 }
 
 template <int L1, int L2, int S>
@@ -149,7 +134,7 @@ hipError_t launch_fourstep(const void* in, void* out, const void* rows1, const v
     if (e != hipSuccess)
         return e;
     hipLaunchKernelGGL((k_fourstep2<L1, L2, S>), dim3((unsigned)g2), dim3(WG2), 0, stream, static_cast<cf*>(out),
-                       static_cast<const cf*>(rows2), scale);
+                       static_cast<const cf*>(rows2), batch << L1, scale);
     return hipGetLastError();
 }
 

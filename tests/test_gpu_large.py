@@ -67,3 +67,20 @@ def test_large_full_size_sampled():
         idx = np.unique(np.array([0, batch // 3, batch - 1]))
         ys = y[torch.from_numpy(idx).cuda()].cpu().numpy()
         assert per_transform_relerr(ys, oracle.forward(x_np[idx].astype(np.complex128))) <= TOL
+
+
+@pytest.mark.parametrize("L", [12, 13, 14])
+@pytest.mark.parametrize("sign", [-1, 1])
+def test_forced_four_step(L, sign):
+    """The four-step split (variant 9) at the lengths that default to the
+    single-pass kernels."""
+    n = 1 << L
+    batch = 5
+    x = synth.uniform_complex(67, (batch, n), key=(L, sign + 1))
+    p = api.Plan(n, batch, sign, ept=2, wg=64, variant=9)
+    assert p.describe()["variant"] == 9
+    print(f"[case] forced four-step n={n} sign={sign}", flush=True)
+    y = to_cpu(p.execute(to_gpu(x)))
+    x64 = x.astype(np.complex128)
+    ref = oracle.forward(x64) if sign < 0 else oracle.inverse(x64)
+    assert per_transform_relerr(y, ref) <= TOL
