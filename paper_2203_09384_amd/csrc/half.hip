@@ -9,19 +9,24 @@
 //   pass C  radix-16 (NS = 128) } F16 the 16-point DFT matrix,
 // where each complex product is two real MFMAs over K = 32:
 //   Re Y = [Re F | -Im F] [Re X; Im X],   Im Y = [Im F | Re F] [Re X; Im X]
-// on v_mfma_f32_16x16x32_{f16,bf16} with FP32 accumulation.  The
+// on v_mfma_f32_16x16x32_f16 with FP32 accumulation.  The
 // inter-pass twiddles (FP32, from the plan's table) are applied when a pass
 // writes its outputs to LDS, so every MFMA operand is a plain gather.
 //
 // Block floating point: logical value = stored * 2^exp[b] per transform.
 // On load the transform is scaled by a power of two so its largest
 // component lies in [8, 16); with the at most 8 * 16 * 16 = 2^11 growth of
-// the three passes no FP16 operand can exceed 2^15 < 65504, and the output
-// is stored at that scale with exponent in_exp + e_max - 4 (- 11 for the
+// the three passes no operand can exceed 2^15 < 65504, and the output is
+// stored at that scale with exponent in_exp + e_max - 4 (- 11 for the
 // inverse's 1/N, exact).  Scaling is by powers of two only, so it adds no
-// rounding.  BF16 operands are split hi + lo (x = hi + lo, both BF16) and
-// each real product is Fhi Xhi + Fhi Xlo + Flo Xhi, giving ~16 significant
-// bits per operand; FP16 operands are used as is.
+// rounding.
+//
+// MFMA operands are FP16 for both storage types.  After the block scaling
+// every operand lies in FP16's range, FP16 carries three more significand
+// bits than BF16 (a BF16 value converts to FP16 exactly), and the error of
+// BF16 storage is set by the rounding of its output to BF16 (7 bits): FP16
+// operands give the same error as BF16 operands split hi + lo (modelled
+// 1.75e-3 against 1.72e-3) at one MFMA per product instead of three.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -34,7 +39,6 @@ namespace mifft {
 namespace {
 
 typedef _Float16 v8h __attribute__((ext_vector_type(8)));
-typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef uint32_t v4u __attribute__((ext_vector_type(4)));
 
@@ -73,34 +77,15 @@ __device__ __forceinline__ uint16_t from_f32(float f)
         return __builtin_bit_cast(uint16_t, (_Float16)f);
 }
 
-// MFMA operand of 8 values (hi part, and for BF16 the lo remainder).
-template <bool BF>
-struct Op8;
-template <>
-struct Op8<false> {
+// MFMA operand: 8 FP16 values.
+struct Op8 {
     v8h hi;
     __device__ __forceinline__ void set(int i, float x) { hi[i] = (_Float16)x; }
 };
-template <>
-struct Op8<true> {
-    v8bf hi, lo;
-    __device__ __forceinline__ void set(int i, float x)
-    {
-        const __bf16 h = (__bf16)x;
-        hi[i] = h;
-        lo[i] = (__bf16)(x - (float)h);
-    }
-};
 
-__device__ __forceinline__ v4f mfma(const Op8<false>& a, const Op8<false>& b, v4f c)
+__device__ __forceinline__ v4f mfma(const Op8& a, const Op8& b, v4f c)
 {
     return __builtin_amdgcn_mfma_f32_16x16x32_f16(a.hi, b.hi, c, 0, 0, 0);
-}
-__device__ __forceinline__ v4f mfma(const Op8<true>& a, const Op8<true>& b, v4f c)
-{
-    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.hi, b.hi, c, 0, 0, 0);
-    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.hi, b.lo, c, 0, 0, 0);
-    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.lo, b.hi, c, 0, 0, 0);
 }
 
 // This lane's rows of the A operands of the 16-point DFT with the twiddles
@@ -108,11 +93,9 @@ __device__ __forceinline__ v4f mfma(const Op8<true>& a, const Op8<true>& b, v4f 
 // i.e. F[m][r] w_128^{g r} (g = 0: the plain DFT).  Real form over K = 32:
 // A_re[m] = [Re A[m][.] | -Im A[m][.]], A_im[m] = [Im A[m][.] | Re A[m][.]];
 // lane l holds row m = l % 16, columns k = 8 (l / 16) + i.  Entries are
-// single lookups of the FP32 table w_2048^{16 e}, rounded once to the
-// operand type.
-template <int S, bool BF>
-__device__ __forceinline__ void dft16_operands(Op8<BF>& are, Op8<BF>& aim, int lane, int g,
-                                               const cf* __restrict__ tw)
+// single lookups of the FP32 table w_2048^{16 e}, rounded once to FP16.
+template <int S>
+__device__ __forceinline__ void dft16_operands(Op8& are, Op8& aim, int lane, int g, const cf* __restrict__ tw)
 {
     const int m = lane & 15, kq = lane >> 4;
 #pragma unroll
@@ -149,10 +132,9 @@ __device__ __forceinline__ void unpack8(const uint32_t (&u)[8], cf (&v)[8])
 }
 
 // Per-thread constants of the kernel: MFMA operands, twiddles, LDS bases.
-template <bool BF>
 struct HalfCtx {
-    Op8<BF> a_re[2], a_im[2];  // pass B, group g = 2 wave + gg, twiddles folded
-    Op8<BF> f_re, f_im;        // pass C, plain DFT
+    Op8 a_re[2], a_im[2];  // pass B, group g = 2 wave + gg, twiddles folded
+    Op8 f_re, f_im;        // pass C, plain DFT
     cf twB[2][4];              // pass C twiddle of pass B output (gg, i)
     int oWA, oRB[2], oWB[2], oRC[2], oWC[2], oRS0, oRS1;
     int tid, lane, wave;
@@ -162,7 +144,7 @@ struct HalfCtx {
 // output and exponent.  X holds the A->B and C->store exchanges, Y the B->C
 // exchange; `red` the per-wave maxima.
 template <int S, bool BF>
-__device__ __forceinline__ void half_transform(const HalfCtx<BF>& c, const uint32_t (&cur)[8], float* X, float* Y,
+__device__ __forceinline__ void half_transform(const HalfCtx& c, const uint32_t (&cur)[8], float* X, float* Y,
                                                float* red, const int32_t* __restrict__ in_exp,
                                                uint32_t* __restrict__ out, int32_t* __restrict__ out_exp,
                                                int64_t b, int scale_log2)
@@ -206,7 +188,7 @@ __device__ __forceinline__ void half_transform(const HalfCtx<BF>& c, const uint3
 #pragma unroll
     for (int gg = 0; gg < 2; gg++) {
         const float* rb = X + c.oRB[gg];
-        Op8<BF> bo;
+        Op8 bo;
 #pragma unroll
         for (int i = 0; i < 8; i++)
             bo.set(i, rb[144 * i] * sc);
@@ -232,7 +214,7 @@ __device__ __forceinline__ void half_transform(const HalfCtx<BF>& c, const uint3
 #pragma unroll
     for (int gg = 0; gg < 2; gg++) {
         const float* rc = Y + c.oRC[gg];
-        Op8<BF> bo;
+        Op8 bo;
 #pragma unroll
         for (int i = 0; i < 8; i++)
             bo.set(i, rc[130 * i]);
@@ -280,7 +262,7 @@ __device__ __forceinline__ void load_raw(uint32_t (&u)[8], const uint32_t* __res
 // Two LDS buffers alternate between consecutive transforms (loop unrolled
 // twice so each body's buffer roles are fixed), so three barriers suffice.
 template <int S, bool BF>
-__global__ __launch_bounds__(HWG, BF ? 3 : 4) void k_fft_half_2048(const uint32_t* __restrict__ in,
+__global__ __launch_bounds__(HWG, 4) void k_fft_half_2048(const uint32_t* __restrict__ in,
                                                        const int32_t* __restrict__ in_exp,
                                                        uint32_t* __restrict__ out, int32_t* __restrict__ out_exp,
                                                        const cf* __restrict__ tw, int64_t batch, int scale_log2)
@@ -290,16 +272,16 @@ __global__ __launch_bounds__(HWG, BF ? 3 : 4) void k_fft_half_2048(const uint32_
     int64_t b = blockIdx.x;
     if (b >= batch)
         return;
-    HalfCtx<BF> c;
+    HalfCtx c;
     c.tid = threadIdx.x;
     c.lane = c.tid & 63;
     c.wave = c.tid >> 6;
     const int n = c.lane & 15, kq = c.lane >> 4, r0 = (kq & 1) * 8;
-    dft16_operands<S, BF>(c.f_re, c.f_im, c.lane, 0, tw);
+    dft16_operands<S>(c.f_re, c.f_im, c.lane, 0, tw);
 #pragma unroll
     for (int gg = 0; gg < 2; gg++) {
         const int g = 2 * c.wave + gg;
-        dft16_operands<S, BF>(c.a_re[gg], c.a_im[gg], c.lane, g, tw);
+        dft16_operands<S>(c.a_re[gg], c.a_im[gg], c.lane, g, tw);
 #pragma unroll
         for (int i = 0; i < 4; i++)  // w_2048^{n (g + 8 m)}, m = 4 kq + i
             c.twB[gg][i] = tw_at<S>(tw, n * (g + 8 * (4 * kq + i)));
