@@ -140,19 +140,31 @@ struct HalfCtx {
     int tid, lane, wave;
 };
 
+__device__ __forceinline__ void load_raw(uint32_t (&u)[8], const uint32_t* __restrict__ in, int64_t b, int tid)
+{
+    const uint32_t* src = in + b * HN;
+#pragma unroll
+    for (int m = 0; m < 8; m++)
+        u[m] = __builtin_nontemporal_load(src + tid + 256 * m);
+}
+
 // One transform: raw input `cur` (thread t holds x[t + 256 m]) -> stored
-// output and exponent.  X holds the A->B and C->store exchanges, Y the B->C
-// exchange; `red` the per-wave maxima.
+// output and exponent.  Once unpacked, `cur` is refilled with transform
+// `refill` (if < batch), so two transforms' loads stay in flight.  X holds
+// the A->B and C->store exchanges, Y the B->C exchange; `red` the per-wave
+// maxima.
 template <int S, bool BF>
-__device__ __forceinline__ void half_transform(const HalfCtx& c, const uint32_t (&cur)[8], float* X, float* Y,
-                                               float* red, const int32_t* __restrict__ in_exp,
+__device__ __forceinline__ void half_transform(const HalfCtx& c, uint32_t (&cur)[8], float* X, float* Y, float* red,
+                                               const uint32_t* __restrict__ in, const int32_t* __restrict__ in_exp,
                                                uint32_t* __restrict__ out, int32_t* __restrict__ out_exp,
-                                               int64_t b, int scale_log2)
+                                               int64_t b, int64_t refill, int64_t batch, int scale_log2)
 {
     constexpr int dWC[4] = {0, 130, 264, 394};  // fC(d0 + 128 i) - fC(d0)
     // ---- pass A: radix 8 on the VALU in FP32 over x[tid + 256 m]
     cf v[8];
     unpack8<BF>(cur, v);
+    if (refill < batch)
+        load_raw(cur, in, refill, c.tid);
     float mx = 0.f;
 #pragma unroll
     for (int m = 0; m < 8; m++)
@@ -249,18 +261,11 @@ __device__ __forceinline__ void half_transform(const HalfCtx& c, const uint32_t 
         out_exp[b] = e_out;
 }
 
-__device__ __forceinline__ void load_raw(uint32_t (&u)[8], const uint32_t* __restrict__ in, int64_t b, int tid)
-{
-    const uint32_t* src = in + b * HN;
-#pragma unroll
-    for (int m = 0; m < 8; m++)
-        u[m] = __builtin_nontemporal_load(src + tid + 256 * m);
-}
-
 // Persistent: a workgroup walks transforms blockIdx.x, + gridDim.x, ...,
-// loading the next transform's input while the current one is computed.
-// Two LDS buffers alternate between consecutive transforms (loop unrolled
-// twice so each body's buffer roles are fixed), so three barriers suffice.
+// with the inputs of the next two transforms in flight while one is
+// computed.  Two LDS buffers (and two raw register buffers) alternate
+// between consecutive transforms (loop unrolled twice so each body's
+// buffer roles are fixed), so three barriers suffice.
 template <int S, bool BF>
 __global__ __launch_bounds__(HWG, 4) void k_fft_half_2048(const uint32_t* __restrict__ in,
                                                        const int32_t* __restrict__ in_exp,
@@ -298,23 +303,21 @@ __global__ __launch_bounds__(HWG, 4) void k_fft_half_2048(const uint32_t* __rest
     float* const buf0 = lds;
     float* const buf1 = lds + BUF;
     uint32_t ua[8], ub[8];
-    load_raw(ua, in, b, c.tid);
     const int64_t stride = gridDim.x;
+    load_raw(ua, in, b, c.tid);
+    if (b + stride < batch)
+        load_raw(ub, in, b + stride, c.tid);
     while (true) {
-        int64_t b1 = b + stride;
-        if (b1 < batch)
-            load_raw(ub, in, b1, c.tid);
-        half_transform<S, BF>(c, ua, buf0, buf1, s_red[0], in_exp, out, out_exp, b, scale_log2);
-        if (b1 >= batch)
+        half_transform<S, BF>(c, ua, buf0, buf1, s_red[0], in, in_exp, out, out_exp, b, b + 2 * stride, batch,
+                              scale_log2);
+        b += stride;
+        if (b >= batch)
             break;
-        b = b1;
-        b1 = b + stride;
-        if (b1 < batch)
-            load_raw(ua, in, b1, c.tid);
-        half_transform<S, BF>(c, ub, buf1, buf0, s_red[1], in_exp, out, out_exp, b, scale_log2);
-        if (b1 >= batch)
+        half_transform<S, BF>(c, ub, buf1, buf0, s_red[1], in, in_exp, out, out_exp, b, b + 2 * stride, batch,
+                              scale_log2);
+        b += stride;
+        if (b >= batch)
             break;
-        b = b1;
     }
 }
 
