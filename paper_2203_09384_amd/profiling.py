@@ -45,9 +45,12 @@ def _one(pattern):
     return sorted(hits)[0]
 
 
-def kernel_stats(run_dir: str, out: str, command: str, top: int = 8):
+def kernel_stats(run_dir: str, out: str, command: str, top: int = 8, name_filter: str = ""):
+    """Summary of a rocprofv3 --stats run: the `top` kernels by total time
+    (0: all) whose names contain `name_filter`."""
     path = _one(os.path.join(run_dir, "**", "*kernel_stats.csv"))
-    rows = list(csv.DictReader(open(path)))
+    rows = [r for r in csv.DictReader(open(path)) if name_filter in r["Name"]]
+    top = top or len(rows)
     lines = [f"# rocprofv3 kernel statistics", f"# command: {command}", "",
              f"{'calls':>7} {'avg_us':>10} {'min_us':>10} {'max_us':>10} {'total_ms':>10}  kernel"]
     for r in rows[:top]:
@@ -100,6 +103,8 @@ def main(argv=None):
     a.add_argument("run_dir")
     a.add_argument("out")
     a.add_argument("--command", required=True)
+    a.add_argument("--top", type=int, default=8, help="kernels to list by total time (0: all)")
+    a.add_argument("--filter", default="", help="only kernels whose names contain this")
     b = sub.add_parser("traffic")
     b.add_argument("fetch_dir")
     b.add_argument("write_dir")
@@ -111,7 +116,7 @@ def main(argv=None):
     b.add_argument("--command", required=True)
     args = ap.parse_args(argv)
     if args.cmd == "kernel-stats":
-        kernel_stats(args.run_dir, args.out, args.command)
+        kernel_stats(args.run_dir, args.out, args.command, args.top, args.filter)
     else:
         print(json.dumps(traffic(args.fetch_dir, args.write_dir, args.out, args.kernel, args.copy_kernel,
                                  args.copy_bytes, args.algorithmic_bytes, args.command), indent=1))
