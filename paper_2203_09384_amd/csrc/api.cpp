@@ -341,9 +341,9 @@ int fill_desc_fourstep(int64_t n, int64_t batch, int sign, int dtype, fft_plan_d
     if (!f)
         return FFT_OK;
     d->ept = 1 << f->log2e1;
-    d->wg = 16 * (int)((1 << f->log2n1) >> f->log2e1);
-    d->transforms_per_wg = 16;
-    d->grid = batch * ((int64_t(1) << f->log2n2) / 16);
+    d->wg = f->tile1 * (int)((1 << f->log2n1) >> f->log2e1);
+    d->transforms_per_wg = f->tile1;
+    d->grid = batch * ((int64_t(1) << f->log2n2) / f->tile1);
     int r1[8], r2[8];
     const int n1 = schedule(f->log2n1, f->log2e1, r1), n2 = schedule(f->log2n2, f->log2e2, r2);
     d->npasses = std::min(8, n1 + n2);
@@ -652,7 +652,7 @@ fft_plan create_batched(int64_t n, int64_t batch, int sign, int dtype, const Var
             set_err(FFT_EINVAL_N, "no four-step kernels for n=%lld", (long long)n);
             return nullptr;
         }
-        if (batch > 0x7fffffffLL / ((int64_t(1) << f->log2n2) / 16)) {
+        if (batch > (0x7fffffffLL - 16) / ((int64_t(1) << f->log2n2) / 8)) {
             set_err(FFT_EINVAL_BATCH, "batch=%lld needs more than 2^31-1 workgroups", (long long)batch);
             return nullptr;
         }

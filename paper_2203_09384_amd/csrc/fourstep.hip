@@ -35,28 +35,43 @@ __device__ __forceinline__ cf big_twiddle(const cf* __restrict__ lo, const cf* _
     return w;
 }
 
-// Pass 1: tile = columns n2 in [16 nb, 16 nb + 16) of transform b.  Long
-// columns (axis_direct) are read straight into registers (the column index
-// is the fastest lane index: rows of 16 values per wavefront access);
-// short ones are staged through LDS so their exchanges stay inside one
-// wavefront.  Either way the outputs go out through LDS: the tile's
-// outputs Y[k1 + N1 n2] form one contiguous block.
+// Columns per pass-1 tile: 16 (whole 128-byte lines), or 8 for 1024-point
+// columns so that two workgroups fit one CU's LDS (MI355X, 2^26 elements:
+// 2^20 616 -> 578 us, 2^19 583 -> 547 us).
+constexpr int col_tile(int L1) { return L1 >= 10 ? 8 : 16; }
+
+// Pass 1: tile = columns n2 in [T nb, T nb + T) of transform b (T =
+// col_tile).  Long columns (axis_direct) are read straight into registers
+// (the column index is the fastest lane index: rows of T values per
+// wavefront access); short ones are staged through LDS so their exchanges
+// stay inside one wavefront.  Either way the outputs go out through LDS:
+// the tile's outputs Y[k1 + N1 n2] form one contiguous block.
 template <int L1, int L2, int S>
-__global__ __launch_bounds__(TILE*((1 << L1) >> inner_e(L1))) void k_fourstep1(
+__global__ __launch_bounds__(col_tile(L1)*((1 << L1) >> inner_e(L1))) void k_fourstep1(
     const cf* __restrict__ in, cf* __restrict__ out, const cf* __restrict__ rows, const cf* __restrict__ tlo,
-    const cf* __restrict__ thi)
+    const cf* __restrict__ thi, int64_t ntiles)
 {
+    constexpr int T = col_tile(L1), LT = T == 16 ? 4 : 3;
     constexpr int E = inner_e(L1), N1 = 1 << L1, N2 = 1 << L2, N = N1 * N2;
-    constexpr int EPT = 1 << E, TPT = N1 / EPT, WG = TILE * TPT, ST = stage_stride<L1, E>();
+    constexpr int EPT = 1 << E, TPT = N1 / EPT, WG = T * TPT, ST = stage_stride<L1, E>();
     constexpr bool DIRECT = axis_direct(L1);
-    __shared__ cf lds[TILE * ST];
+    static_assert(T == 16 || DIRECT, "8-column tiles load directly");
+    __shared__ cf lds[T * ST];
     const int tid = threadIdx.x;
-    const int64_t b = blockIdx.x / (N2 / TILE);
-    const int nb = blockIdx.x % (N2 / TILE);
-    const cf* src = in + b * N + nb * TILE;
+    int64_t tile = blockIdx.x;
+    if constexpr (T < 16) {
+        // tiles 2i and 2i+1 share 128-byte lines: same XCD (blocks b, b + 8)
+        const int64_t g = blockIdx.x;
+        tile = (g & ~int64_t(15)) + 2 * (g & 7) + ((g >> 3) & 1);
+    }
+    if (tile >= ntiles)
+        return;
+    const int64_t b = tile / (N2 / T);
+    const int nb = (int)(tile % (N2 / T));
+    const cf* src = in + b * N + nb * T;
     // thread (tb, t): transform tb of the tile, thread t of that transform
-    const int tb = DIRECT ? (tid & (TILE - 1)) : tid / TPT;
-    const int t = DIRECT ? (tid >> 4) : tid % TPT;
+    const int tb = DIRECT ? (tid & (T - 1)) : tid / TPT;
+    const int t = DIRECT ? (tid >> LT) : tid % TPT;
     cf* my = lds + tb * ST;
     cf v[EPT];
     if constexpr (DIRECT) {
@@ -66,9 +81,9 @@ __global__ __launch_bounds__(TILE*((1 << L1) >> inner_e(L1))) void k_fourstep1(
     } else {
         // stage: 16 consecutive columns per row n1 (one 128-byte line)
 #pragma unroll
-        for (int i = 0; i < TILE * N1 / WG; i++) {
+        for (int i = 0; i < T * N1 / WG; i++) {
             const int idx = tid + i * WG;
-            const int c = idx & (TILE - 1), n1 = idx >> 4;
+            const int c = idx & (T - 1), n1 = idx >> LT;
             lds[c * ST + n1] = src[(int64_t)n1 * N2 + c];
         }
         __syncthreads();
@@ -78,9 +93,9 @@ __global__ __launch_bounds__(TILE*((1 << L1) >> inner_e(L1))) void k_fourstep1(
     }
     TwRegs<L1, E> tws;
     unit_rows<L1, E>(tws);
-    constexpr bool WAVE = DIRECT ? TPT * TILE <= 64 : TPT <= 64;
+    constexpr bool WAVE = DIRECT ? TPT * T <= 64 : TPT <= 64;
     run2<L1, E, S, 1, WAVE>(v, t, rows, tws, my);
-    const unsigned n2 = nb * TILE + tb;
+    const unsigned n2 = nb * T + tb;
 #pragma unroll
     for (int m = 0; m < EPT; m++) {
         const unsigned k1 = t + m * TPT;
@@ -94,9 +109,9 @@ __global__ __launch_bounds__(TILE*((1 << L1) >> inner_e(L1))) void k_fourstep1(
     for (int m = 0; m < EPT; m++)
         my[t + m * TPT] = v[m];
     __syncthreads();
-    cf* dst = out + b * N + (int64_t)nb * TILE * N1;
+    cf* dst = out + b * N + (int64_t)nb * T * N1;
 #pragma unroll
-    for (int i = 0; i < TILE * N1 / WG; i++) {
+    for (int i = 0; i < T * N1 / WG; i++) {
         const int idx = tid + i * WG;
         const int c = idx / N1, k1 = idx % N1;
         dst[idx] = lds[c * ST + k1];
@@ -124,12 +139,14 @@ template <int L1, int L2, int S>
 hipError_t launch_fourstep(const void* in, void* out, const void* rows1, const void* rows2, const void* tlo,
                            const void* thi, int64_t batch, float scale, hipStream_t stream)
 {
-    constexpr int WG1 = TILE * ((1 << L1) >> inner_e(L1));
+    constexpr int T1 = col_tile(L1);
+    constexpr int WG1 = T1 * ((1 << L1) >> inner_e(L1));
     constexpr int WG2 = TILE * ((1 << L2) >> inner_e(L2));
-    const int64_t g1 = batch * ((1 << L2) / TILE), g2 = batch * ((1 << L1) / TILE);
+    const int64_t t1 = batch * ((1 << L2) / T1), g2 = batch * ((1 << L1) / TILE);
+    const int64_t g1 = T1 < 16 ? (t1 + 15) & ~int64_t(15) : t1;  // whole chunks for the XCD pairing
     hipLaunchKernelGGL((k_fourstep1<L1, L2, S>), dim3((unsigned)g1), dim3(WG1), 0, stream,
                        static_cast<const cf*>(in), static_cast<cf*>(out), static_cast<const cf*>(rows1),
-                       static_cast<const cf*>(tlo), static_cast<const cf*>(thi));
+                       static_cast<const cf*>(tlo), static_cast<const cf*>(thi), t1);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return e;
@@ -145,8 +162,8 @@ void add_len()
     const FourStep fs{L, L1, L2, inner_e(L1), inner_e(L2), Layout2<L1, inner_e(L1)>::rows_total(),
                       Layout2<L2, inner_e(L2)>::rows_total(), &launch_fourstep<L1, L2, -1>,
                       &launch_fourstep<L1, L2, +1>,
-                      (int)(TILE * stage_stride<L1, inner_e(L1)>() * sizeof(cf)),
-                      (int)(TILE * stage_stride<L2, inner_e(L2)>() * sizeof(cf))};
+                      (int)(col_tile(L1) * stage_stride<L1, inner_e(L1)>() * sizeof(cf)),
+                      (int)(TILE * stage_stride<L2, inner_e(L2)>() * sizeof(cf)), col_tile(L1)};
     register_fourstep(fs);
 }
 

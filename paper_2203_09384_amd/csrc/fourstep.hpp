@@ -16,6 +16,7 @@ struct FourStep {
     int rows1, rows2;           // twiddle-row entries of the inner transforms
     LaunchFourStep fwd, bwd;    // sign -1 / +1
     int lds1, lds2;             // LDS per workgroup of each pass
+    int tile1;                  // columns per pass-1 workgroup
 };
 
 void register_fourstep(const FourStep& f);
