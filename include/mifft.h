@@ -105,7 +105,9 @@ typedef struct {
                            group per workgroup, twiddles kept / re-read;
                            3, 4: persistent with next-group prefetch);
                            5..8 as 1..4 with wavefront-local exchanges
-                           (transforms of at most 64 threads)               */
+                           (transforms of at most 64 threads); 9 the
+                           four-step split (n > 2048); 10 the single-pass
+                           2D kernel (multidimensional plans)             */
     int ept_by_log2n[12]; /* ragged: elements per thread used for length 2^L */
     int rank;           /* multidimensional plans: number of axes (else 0)   */
     int64_t dims[3];    /* multidimensional plans: axis lengths, first to last */
@@ -180,7 +182,11 @@ fft_plan fft_plan_create_ragged_config(int64_t count, const int64_t *offsets, in
  * s = 1 (sign -1) or 1/prod(dims) (sign +1).  The kernel factors over the
  * axes, so the plan runs the 1D batched kernels over the last axis
  * (in -> out) and then one in-place pass per remaining axis over `out`,
- * each staging tiles of transforms adjacent in memory through LDS.
+ * each over tiles of transforms adjacent in memory.  A 2D array that fits
+ * one workgroup's LDS (at most 16384 points, both axes >= 16 points per
+ * thread group, e.g. 128 x 128) instead runs one kernel: rows, a
+ * transpose through LDS and columns, one pass over HBM
+ * (fft_plan_desc.variant 10).
  *   rank   1, 2 or 3 (rank 1 is fft_plan_create).
  *   dims   host array of `rank` powers of two: the last in [2, 2^20], the
  *          others in [2, 2048].  Copied into the plan.

@@ -20,6 +20,7 @@
 #include "fused_loss.hpp"
 #include "half.hpp"
 #include "nd.hpp"
+#include "nd2.hpp"
 #include "ragged.hpp"
 #include "real.hpp"
 #include "registry.hpp"
@@ -134,6 +135,19 @@ const KernelAxis* find_axis(int log2n, int sign)
 {
     for (const auto& k : axis_reg())
         if (k.log2n == log2n && k.sign == sign)
+            return &k;
+    return nullptr;
+}
+static std::vector<KernelNd2>& nd2_reg()
+{
+    static std::vector<KernelNd2> r;
+    return r;
+}
+void register_nd2(const KernelNd2& k) { nd2_reg().push_back(k); }
+const KernelNd2* find_nd2(int log2n0, int log2n1, int sign)
+{
+    for (const auto& k : nd2_reg())
+        if (k.log2n0 == log2n0 && k.log2n1 == log2n1 && k.sign == sign)
             return &k;
     return nullptr;
 }
@@ -300,6 +314,10 @@ struct mifft_plan_s {
     int ax_log2s[2] = {0, 0};
     int64_t ax_count[2] = {0, 0};
     float ax_scale[2] = {1.f, 1.f};
+    // single-pass 2D (the array fits one workgroup's LDS): no sub-plan
+    const KernelNd2* nd2_same = nullptr;
+    const KernelNd2* nd2_opp = nullptr;
+    void* nd2_rows[2] = {nullptr, nullptr};  // column, row transforms
 };
 
 namespace {
@@ -573,7 +591,7 @@ void free_plan(mifft_plan_s* p)
         return;
     if (p->last)
         free_plan(p->last);
-    for (void* q : {p->ax_rows[0], p->ax_rows[1]})
+    for (void* q : {p->ax_rows[0], p->ax_rows[1], p->nd2_rows[0], p->nd2_rows[1]})
         if (q)
             (void)hipFree(q);
     if (p->ragged)
@@ -733,6 +751,66 @@ fft_plan create_batched(int64_t n, int64_t batch, int sign, int dtype, const Var
 
 constexpr int64_t kMaxAxisN = 2048;
 
+// A 2D plan whose arrays fit one workgroup's LDS: one kernel, one HBM pass.
+fft_plan create_nd2(const int64_t* dims, int64_t batch, int sign)
+{
+    const int L0 = ilog2(dims[0]), L1 = ilog2(dims[1]);
+    const KernelNd2* k = find_nd2(L0, L1, sign);
+    if ((batch + k->arrays_per_wg - 1) / k->arrays_per_wg > 0x7fffffffLL) {
+        set_err(FFT_EINVAL_BATCH, "batch=%lld needs more than 2^31-1 workgroups", (long long)batch);
+        return nullptr;
+    }
+    int dev = -1;
+    if (current_gfx950(&dev) != FFT_OK)
+        return nullptr;
+    auto* p = new (std::nothrow) mifft_plan_s();
+    if (!p) {
+        set_err(FFT_ENOMEM, "out of host memory");
+        return nullptr;
+    }
+    p->kind = 2;
+    p->n = dims[0] * dims[1];
+    p->batch = batch;
+    p->sign = sign;
+    p->dtype = FFT_C32;
+    p->scale = sign > 0 ? 1.0f / (float)p->n : 1.0f;
+    p->device = dev;
+    p->log2n = L0 + L1;
+    p->total = p->n * batch;
+    p->rank = 2;
+    p->dims[0] = dims[0];
+    p->dims[1] = dims[1];
+    p->nd2_same = k;
+    p->nd2_opp = find_nd2(L0, L1, -sign);
+    if (make_twiddles(p) != FFT_OK) {
+        free_plan(p);
+        return nullptr;
+    }
+    const int Ls[2] = {L0, L1}, counts[2] = {k->rows0, k->rows1};
+    for (int i = 0; i < 2; i++) {
+        if (counts[i] <= 0)
+            continue;
+        hipError_t e = hipMalloc(&p->nd2_rows[i], (size_t)counts[i] * sizeof(float2));
+        if (e != hipSuccess) {
+            p->nd2_rows[i] = nullptr;
+            e == hipErrorOutOfMemory ? set_err(FFT_ENOMEM, "hipMalloc(2D twiddle rows) failed")
+                                     : hip_err(e, "hipMalloc(2D twiddle rows)");
+            free_plan(p);
+            return nullptr;
+        }
+        e = launch_twiddle_rows(p->tw, p->nd2_rows[i], Ls[i], k->log2ept, counts[i], nullptr);
+        if (e == hipSuccess)
+            e = hipStreamSynchronize(nullptr);
+        if (e != hipSuccess) {
+            hip_err(e, "2D twiddle rows");
+            free_plan(p);
+            return nullptr;
+        }
+    }
+    ok();
+    return p;
+}
+
 fft_plan create_nd(int rank, const int64_t* dims, int64_t batch, int sign, int dtype)
 {
     if (!dims) {
@@ -788,6 +866,9 @@ fft_plan create_nd(int rank, const int64_t* dims, int64_t batch, int sign, int d
             return nullptr;
         }
     }
+    if (rank == 2 && find_nd2(ilog2(dims[0]), ilog2(dims[1]), sign) &&
+        find_nd2(ilog2(dims[0]), ilog2(dims[1]), -sign))
+        return create_nd2(dims, batch, sign);
     mifft_plan_s* last = create_batched(dims[rank - 1], batch * (n / dims[rank - 1]), sign, dtype, nullptr);
     if (!last)
         return nullptr;
@@ -893,6 +974,13 @@ int exec_real(fft_plan p, const void* in, void* out, bool to_bins, float we, flo
 // direction: the sign of the exponent actually applied; scale as given.
 int exec_c32(fft_plan p, const void* in, void* out, int sign, float scale, hipStream_t st)
 {
+    if (p->kind == 2 && p->nd2_same) {
+        const KernelNd2* k = sign == p->sign ? p->nd2_same : p->nd2_opp;
+        hipError_t e = k->fn(in, out, p->nd2_rows[0], p->nd2_rows[1], p->batch, p->scale, st);
+        if (e != hipSuccess)
+            return hip_err(e, "2D kernel launch");
+        return ok();
+    }
     if (p->kind == 2) {
         // last axis (batched 1D), then the other axes in place in `out`
         int rc = exec_c32(p->last, in, out, sign, p->last->scale, st);
@@ -1131,6 +1219,31 @@ int fft_plan_describe(fft_plan p, fft_plan_desc* d)
 {
     if (!p || !d)
         return set_err(FFT_ENULL, "plan or desc is NULL");
+    if (p->kind == 2 && p->nd2_same) {
+        const KernelNd2* k = p->nd2_same;
+        memset(d, 0, sizeof *d);
+        d->n = p->n;
+        d->batch = p->batch;
+        d->sign = p->sign;
+        d->dtype = FFT_C32;
+        d->scale = p->scale;
+        d->ept = 1 << k->log2ept;
+        d->wg = k->wg;
+        d->transforms_per_wg = k->arrays_per_wg;
+        d->grid = (p->batch + k->arrays_per_wg - 1) / k->arrays_per_wg;
+        int r0[8], r1[8];
+        const int n0 = schedule(k->log2n0, k->log2ept, r0), n1 = schedule(k->log2n1, k->log2ept, r1);
+        d->npasses = std::min(8, n0 + n1);
+        for (int i = 0; i < d->npasses; i++)
+            d->radices[i] = i < n1 ? r1[i] : r0[i - n1];
+        d->lds_bytes = k->lds_bytes;
+        d->kind = 2;
+        d->variant = 10;
+        d->rank = 2;
+        d->dims[0] = p->dims[0];
+        d->dims[1] = p->dims[1];
+        return ok();
+    }
     if (p->kind == 2) {
         // the last axis's kernel shape, with the whole plan's sizes
         fft_plan_describe(p->last, d);

@@ -14,7 +14,9 @@ TOL = 1e-5
 SEED_ND = 20220322
 
 SHAPES = [(2, 2), (4, 8), (8, 2), (16, 2048), (2048, 16), (64, 64), (2, 4096), (4, 65536), (8, 4, 2), (2, 2, 2),
-          (32, 64, 8), (16, 16, 16), (4, 2048, 4), (2048, 2, 2)]
+          (32, 64, 8), (16, 16, 16), (4, 2048, 4), (2048, 2, 2),
+          # single-pass 2D (the array fits one workgroup's LDS)
+          (128, 128), (64, 256), (256, 64), (16, 1024), (1024, 16), (2, 1024), (32, 32), (8, 512), (4, 4)]
 
 
 @pytest.fixture(autouse=True)
@@ -81,3 +83,27 @@ def test_functional_and_autograd():
     x64 = x.astype(np.complex128)
     ref = oracle.fftn(2.0 * w * oracle.fftn(x64, 2), 2, +1, 1.0)
     assert per_array_relerr(xg.grad.cpu().numpy(), ref, 2) <= TOL
+
+
+@pytest.mark.parametrize("shape,single", [((128, 128), True), ((64, 64), True), ((2, 2), True), ((16, 2048), False),
+                                          ((2, 4096), False), ((256, 128), False)])
+def test_single_pass_choice(shape, single):
+    """Arrays that fit one workgroup's LDS run the single-pass 2D kernel."""
+    d = api.PlanND(shape, 2, -1).describe()
+    assert (d["variant"] == 10) == single, d
+    assert d["dims"] == list(shape)
+
+
+def test_single_pass_full_size():
+    """128 x 128, batch 4096 (2^26 elements): sampled arrays against the
+    oracle and the round trip over the whole batch."""
+    shape, batch = (128, 128), 4096
+    x = synth.uniform_complex(SEED_ND, (batch,) + shape, key=(98,))
+    xg = to_gpu(x)
+    print(f"[case] nd2 full size {shape} batch={batch}", flush=True)
+    y = api.PlanND(shape, batch, -1).execute(xg)
+    idx = [0, 1, batch // 2, batch - 1]
+    ys = to_cpu(y[idx])
+    assert per_array_relerr(ys, oracle.fftn(x[idx].astype(np.complex128), 2), 2) <= TOL
+    back = api.PlanND(shape, batch, +1).execute(y)
+    assert per_array_relerr(to_cpu(back), x, 2) <= 2 * TOL
