@@ -157,7 +157,7 @@ def bench_nd(api, torch, steps, x_all, y_all):
         elems = batch
         for d in shape:
             elems *= d
-        passes = 1 if p.describe()["variant"] == 10 else len(shape)
+        passes = len(shape) - 1 if p.describe()["variant"] == 10 else len(shape)
         res[name] = {"us": round(m * 1e3, 2), "passes_over_hbm": passes,
                      "GBps_algorithmic": round(16.0 * elems / (m * 1e-3) / 1e9, 1),
                      "GBps_actual_passes": round(16.0 * passes * elems / (m * 1e-3) / 1e9, 1),

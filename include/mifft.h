@@ -186,7 +186,8 @@ fft_plan fft_plan_create_ragged_config(int64_t count, const int64_t *offsets, in
  * one workgroup's LDS (at most 16384 points, both axes >= 16 points per
  * thread group, e.g. 128 x 128) instead runs one kernel: rows, a
  * transpose through LDS and columns, one pass over HBM
- * (fft_plan_desc.variant 10).
+ * (fft_plan_desc.variant 10); a 3D plan whose last two axes form such an
+ * array runs that kernel over them, then one pass for its first axis.
  *   rank   1, 2 or 3 (rank 1 is fft_plan_create).
  *   dims   host array of `rank` powers of two: the last in [2, 2^20], the
  *          others in [2, 2048].  Copied into the plan.

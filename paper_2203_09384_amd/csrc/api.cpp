@@ -314,6 +314,7 @@ struct mifft_plan_s {
     int ax_log2s[2] = {0, 0};
     int64_t ax_count[2] = {0, 0};
     float ax_scale[2] = {1.f, 1.f};
+    int ax_first = -1;  // the axis passes run for axes ax_first .. 0
     // single-pass 2D (the array fits one workgroup's LDS): no sub-plan
     const KernelNd2* nd2_same = nullptr;
     const KernelNd2* nd2_opp = nullptr;
@@ -869,7 +870,12 @@ fft_plan create_nd(int rank, const int64_t* dims, int64_t batch, int sign, int d
     if (rank == 2 && find_nd2(ilog2(dims[0]), ilog2(dims[1]), sign) &&
         find_nd2(ilog2(dims[0]), ilog2(dims[1]), -sign))
         return create_nd2(dims, batch, sign);
-    mifft_plan_s* last = create_batched(dims[rank - 1], batch * (n / dims[rank - 1]), sign, dtype, nullptr);
+    // The trailing axes handled by the sub-plan: the last one (batched 1D),
+    // or for 3D the last two when they fit the single-pass 2D kernel.
+    const bool tail2 = rank == 3 && find_nd2(ilog2(dims[1]), ilog2(dims[2]), sign) &&
+                       find_nd2(ilog2(dims[1]), ilog2(dims[2]), -sign);
+    mifft_plan_s* last = tail2 ? create_nd2(dims + 1, batch * dims[0], sign)
+                               : create_batched(dims[rank - 1], batch * (n / dims[rank - 1]), sign, dtype, nullptr);
     if (!last)
         return nullptr;
     auto* p = new (std::nothrow) mifft_plan_s();
@@ -895,8 +901,9 @@ fft_plan create_nd(int rank, const int64_t* dims, int64_t batch, int sign, int d
         free_plan(p);
         return nullptr;
     }
-    int log2s = ilog2(dims[rank - 1]);
-    for (int a = rank - 2; a >= 0; a--) {
+    int log2s = ilog2(dims[rank - 1]) + (tail2 ? ilog2(dims[1]) : 0);
+    p->ax_first = tail2 ? 0 : rank - 2;
+    for (int a = p->ax_first; a >= 0; a--) {
         const int L = ilog2(dims[a]);
         p->ax_same[a] = find_axis(L, sign);
         p->ax_opp[a] = find_axis(L, -sign);
@@ -986,7 +993,7 @@ int exec_c32(fft_plan p, const void* in, void* out, int sign, float scale, hipSt
         int rc = exec_c32(p->last, in, out, sign, p->last->scale, st);
         if (rc != FFT_OK)
             return rc;
-        for (int a = p->rank - 2; a >= 0; a--) {
+        for (int a = p->ax_first; a >= 0; a--) {
             const KernelAxis* k = sign == p->sign ? p->ax_same[a] : p->ax_opp[a];
             hipError_t e = k->fn(out, p->ax_rows[a], p->ax_count[a], p->ax_log2s[a], p->ax_scale[a], st);
             if (e != hipSuccess)
@@ -1245,7 +1252,8 @@ int fft_plan_describe(fft_plan p, fft_plan_desc* d)
         return ok();
     }
     if (p->kind == 2) {
-        // the last axis's kernel shape, with the whole plan's sizes
+        // the sub-plan's kernel shape (the last axis; for 3D with variant 10
+        // the last two axes in one pass), with the whole plan's sizes
         fft_plan_describe(p->last, d);
         d->n = p->n;
         d->batch = p->batch;

@@ -16,7 +16,9 @@ SEED_ND = 20220322
 SHAPES = [(2, 2), (4, 8), (8, 2), (16, 2048), (2048, 16), (64, 64), (2, 4096), (4, 65536), (8, 4, 2), (2, 2, 2),
           (32, 64, 8), (16, 16, 16), (4, 2048, 4), (2048, 2, 2),
           # single-pass 2D (the array fits one workgroup's LDS)
-          (128, 128), (64, 256), (256, 64), (16, 1024), (1024, 16), (2, 1024), (32, 32), (8, 512), (4, 4)]
+          (128, 128), (64, 256), (256, 64), (16, 1024), (1024, 16), (2, 1024), (32, 32), (8, 512), (4, 4),
+          # 3D: last two axes in one pass, or not
+          (2, 128, 128), (4, 64, 64), (2, 256, 256), (8, 2, 1024)]
 
 
 @pytest.fixture(autouse=True)
@@ -86,9 +88,11 @@ def test_functional_and_autograd():
 
 
 @pytest.mark.parametrize("shape,single", [((128, 128), True), ((64, 64), True), ((2, 2), True), ((16, 2048), False),
-                                          ((2, 4096), False), ((256, 128), False)])
+                                          ((2, 4096), False), ((256, 128), False), ((4, 128, 128), True),
+                                          ((2, 256, 256), False)])
 def test_single_pass_choice(shape, single):
-    """Arrays that fit one workgroup's LDS run the single-pass 2D kernel."""
+    """Arrays that fit one workgroup's LDS run the single-pass 2D kernel (for
+    3D: over the last two axes)."""
     d = api.PlanND(shape, 2, -1).describe()
     assert (d["variant"] == 10) == single, d
     assert d["dims"] == list(shape)
