@@ -76,3 +76,45 @@ def test_half_in_graph(dtype, tdt):
     ry, re = ry.clone(), re.clone()
     y, e = torch.empty_like(ry), torch.empty_like(re)
     replay_and_check(capture(lambda: p.execute_scaled(xh, out=y, out_exp=e)), [y, e], [ry, re], xh.float())
+
+
+@pytest.mark.parametrize("n", [2, 64, 2048, 1 << 15])
+def test_real_input_in_graph(n):
+    batch = max(1, (1 << 19) // n) + 1
+    x = to_gpu(synth.uniform_real(57, (batch, n), key=(n,)))
+    pf, pi = api.Plan(n, batch, -1, "r32"), api.Plan(n, batch, +1, "r32")
+    ref_X, ref_a = pf.execute(x), pf.adjoint(pf.execute(x))
+    ref_x = pi.execute(ref_X)
+    X, a, xb = torch.empty_like(ref_X), torch.empty_like(ref_a), torch.empty_like(ref_x)
+
+    def fn():
+        pf.execute(x, X)
+        pf.adjoint(X, a)
+        pi.execute(X, xb)
+    replay_and_check(capture(fn), [X, a, xb], [ref_X, ref_a, ref_x], x)
+
+
+@pytest.mark.parametrize("shape", [(128, 128), (2048, 64), (4, 64, 64), (8, 16, 512)],
+                         ids=lambda s: "x".join(map(str, s)))
+def test_nd_in_graph(shape):
+    """Single-pass and multi-kernel multidimensional plans."""
+    n = int(np.prod(shape))
+    batch = max(1, (1 << 20) // n)
+    x = to_gpu(synth.uniform_complex(59, (batch,) + shape, key=shape))
+    p = api.PlanND(shape, batch, -1)
+    ref_y, ref_a = p.execute(x), p.adjoint(x)
+    y, a = torch.empty_like(x), torch.empty_like(x)
+
+    def fn():
+        p.execute(x, y)
+        p.adjoint(x, a)
+    replay_and_check(capture(fn), [y, a], [ref_y, ref_a], x)
+
+
+def test_four_step_in_graph():
+    n, batch = 1 << 16, 8
+    x = to_gpu(synth.uniform_complex(61, (batch, n)))
+    p = api.Plan(n, batch, +1)
+    ref = p.execute(x)
+    y = torch.empty_like(x)
+    replay_and_check(capture(lambda: p.execute(x, y)), [y], [ref], x)
