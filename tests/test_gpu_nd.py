@@ -111,3 +111,20 @@ def test_single_pass_full_size():
     assert per_array_relerr(ys, oracle.fftn(x[idx].astype(np.complex128), 2), 2) <= TOL
     back = api.PlanND(shape, batch, +1).execute(y)
     assert per_array_relerr(to_cpu(back), x, 2) <= 2 * TOL
+
+
+@pytest.mark.parametrize("shape", [(128, 128), (2048, 64), (4, 64, 64)], ids=lambda s: "x".join(map(str, s)))
+def test_nd_run_to_run_bitwise_and_scaled_adjoint(shape):
+    """Repeated executes give identical bits, and the inverse equals the
+    forward plan's adjoint times 1/prod(dims) bit for bit (the same kernels,
+    a power-of-two scale)."""
+    n = int(np.prod(shape))
+    batch = 3
+    x = to_gpu(synth.uniform_complex(SEED_ND, (batch,) + shape, key=shape + (30,)))
+    pf, pi = api.PlanND(shape, batch, -1), api.PlanND(shape, batch, +1)
+    y0 = pf.execute(x)
+    for _ in range(3):
+        assert torch.equal(pf.execute(x), y0)
+    inv = to_cpu(pi.execute(x))
+    adj = to_cpu(pf.adjoint(x))
+    assert np.array_equal(inv, (adj / np.float32(n)).astype(np.complex64))

@@ -238,3 +238,16 @@ def test_overlap_and_size_checks():
     with pytest.raises(ValueError):
         p.execute(torch.empty(batch, n, dtype=torch.complex64, device="cuda"))
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("n", [16, 2048, 1 << 15])
+def test_run_to_run_bitwise(n):
+    """No atomics on data: repeated executes give identical bits."""
+    batch = 37
+    x = to_gpu(synth.uniform_real(synth.SEED_REAL, (batch, n), key=(n, 20)))
+    pf, pi = api.Plan(n, batch, -1, "r32"), api.Plan(n, batch, +1, "r32")
+    X0 = pf.execute(x)
+    x0 = pi.execute(X0)
+    for _ in range(3):
+        assert torch.equal(pf.execute(x), X0)
+        assert torch.equal(pi.execute(X0), x0)
