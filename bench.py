@@ -139,6 +139,17 @@ def bench_real(api, torch, dev, steps, x_all):
         p.close()
     res["algorithmic_bytes_per_launch"] = alg
     del bins, back
+    # above 2^15: four-step half-length transform + split pass (workspace)
+    nl, bl = 1 << 20, 64
+    xl = torch.view_as_real(x_all).view(-1)[: nl * bl].view(bl, nl)
+    binl = torch.empty(bl, nl // 2 + 1, dtype=torch.complex64, device=dev)
+    p = api.Plan(nl, bl, -1, dtype="r32")
+    m = time_launches(lambda: p.execute(xl, binl), max(20, steps // 4), 5, torch)
+    alg_l = bl * (4.0 * nl + 8.0 * (nl // 2 + 1))
+    res["r2c_n2^20_batch64"] = {"us": round(m * 1e3, 2), "GBps_algorithmic": round(alg_l / (m * 1e-3) / 1e9, 1),
+                                "passes_over_hbm": 3}
+    p.close()
+    del binl
     return res
 
 

@@ -123,7 +123,11 @@ typedef struct {
  *          "Conclusions") use the four-step split N = N1 N2: a column pass
  *          with the w_N^{n2 k1} twiddles, then an in-place row pass in
  *          `out` (two kernels on the stream).  FFT_C16 / FFT_CBF16: 2048.
- *          FFT_R32: [2, 2^15].
+ *          FFT_R32: [2, 2^21]; up to 2^15 one fused kernel per
+ *          execute, above it the half-length four-step transform plus a
+ *          split pass through a plan-owned workspace of n/2 complex values
+ *          per transform (allocated here; executes of one such plan must
+ *          not overlap in time).
  *   batch  >= 1.
  *   sign   -1: forward transform Eq. (dft), scale 1.
  *          +1: inverse transform Eq. (idft), scale 1/n.

@@ -303,6 +303,11 @@ struct mifft_plan_s {
     const KernelReal* r2c = nullptr;  // FFT_R32: real -> bins kernel
     const KernelReal* c2r = nullptr;  // FFT_R32: bins -> real kernel
     void* wn = nullptr;               // FFT_R32: w_n^k, k < n/2
+    // FFT_R32 above 2^15: four-step half-length sub-plan, its workspace
+    // (n/2 complex per transform) and the two-level w_n table of the split
+    mifft_plan_s* real_sub = nullptr;
+    void* real_ws = nullptr;
+    void* real_tw = nullptr;
     // multidimensional plans (kind 2): the last axis as a batched sub-plan,
     // then in-place axis passes from the second-to-last axis to the first
     int rank = 1;
@@ -323,17 +328,18 @@ struct mifft_plan_s {
 
 namespace {
 constexpr int64_t kMaxN = int64_t(1) << 20;
-constexpr int64_t kMaxRealN = int64_t(1) << 15;
+constexpr int64_t kMaxRealN = int64_t(1) << 21;
+constexpr int64_t kMaxFusedRealN = int64_t(1) << 15;  // above: four-step half length + split pass
 
 int check_common(int64_t n, int64_t batch, int sign, int dtype)
 {
     if (dtype != FFT_C32 && dtype != FFT_C16 && dtype != FFT_CBF16 && dtype != FFT_R32)
         return set_err(FFT_EINVAL_DTYPE, "dtype %d is not FFT_C32, FFT_C16, FFT_CBF16 or FFT_R32", dtype);
-    if (!is_pow2(n) || n < 2 || n > kMaxN)
-        return set_err(FFT_EINVAL_N, "n=%lld is not a power of two in [2, 2^20]", (long long)n);
-    if (dtype == FFT_R32 && n > kMaxRealN)
-        return set_err(FFT_EINVAL_N, "n=%lld: real-input (FFT_R32) lengths are powers of two in [2, 2^15]",
+    if (dtype == FFT_R32 && (!is_pow2(n) || n < 2 || n > kMaxRealN))
+        return set_err(FFT_EINVAL_N, "n=%lld: real-input (FFT_R32) lengths are powers of two in [2, 2^21]",
                        (long long)n);
+    if (dtype != FFT_R32 && (!is_pow2(n) || n < 2 || n > kMaxN))
+        return set_err(FFT_EINVAL_N, "n=%lld is not a power of two in [2, 2^20]", (long long)n);
     if (n > 2048 && dtype != FFT_C32 && dtype != FFT_R32)
         return set_err(FFT_EINVAL_N, "n=%lld: lengths above 2048 are FFT_C32 / FFT_R32 only", (long long)n);
     if (batch < 1)
@@ -402,6 +408,14 @@ int fill_desc_c32(int64_t n, int64_t batch, int sign, int dtype, Variant v, int6
 // and lds describe it.
 int fill_desc_r32(int64_t n, int64_t batch, int sign, Variant v, int64_t grid_limit, fft_plan_desc* d)
 {
+    if (n > kMaxFusedRealN) {
+        // the half-length four-step transform (plus the split pass)
+        fill_desc_fourstep(n / 2, batch, sign, FFT_C32, d);
+        d->n = n;
+        d->dtype = FFT_R32;
+        d->scale = sign > 0 ? 1.0f / (float)n : 1.0f;
+        return FFT_OK;
+    }
     memset(d, 0, sizeof *d);
     const int log2m = ilog2(n) - 1;
     d->n = n;
@@ -592,6 +606,11 @@ void free_plan(mifft_plan_s* p)
         return;
     if (p->last)
         free_plan(p->last);
+    if (p->real_sub)
+        free_plan(p->real_sub);
+    for (void* q : {p->real_ws, p->real_tw})
+        if (q)
+            (void)hipFree(q);
     for (void* q : {p->ax_rows[0], p->ax_rows[1], p->nd2_rows[0], p->nd2_rows[1]})
         if (q)
             (void)hipFree(q);
@@ -611,8 +630,73 @@ void free_plan(mifft_plan_s* p)
     delete p;
 }
 
+fft_plan create_batched(int64_t n, int64_t batch, int sign, int dtype, const Variant* force);
+
+// Real input above 2^15: the half-length complex transform as a four-step
+// sub-plan into a workspace, and the even/odd split as a pass of its own.
+fft_plan create_real_large(int64_t n, int64_t batch, int sign)
+{
+    const int64_t m = n / 2;
+    const int64_t kblocks = ((m / 2 + 1) + 255) / 256;
+    if (batch > 0x7fffffffLL / kblocks) {
+        set_err(FFT_EINVAL_BATCH, "batch=%lld needs more than 2^31-1 workgroups", (long long)batch);
+        return nullptr;
+    }
+    mifft_plan_s* sub = create_batched(m, batch, sign, FFT_C32, nullptr);
+    if (!sub)
+        return nullptr;
+    auto* p = new (std::nothrow) mifft_plan_s();
+    if (!p) {
+        free_plan(sub);
+        set_err(FFT_ENOMEM, "out of host memory");
+        return nullptr;
+    }
+    p->kind = 0;
+    p->n = n;
+    p->batch = batch;
+    p->sign = sign;
+    p->dtype = FFT_R32;
+    p->scale = sign > 0 ? 1.0f / (float)n : 1.0f;
+    p->device = sub->device;
+    p->log2n = ilog2(n);
+    p->total = n * batch;
+    p->real_sub = sub;
+    p->var = Variant{0, 0, 9};
+    hipError_t e = hipMalloc(&p->real_ws, (size_t)m * (size_t)batch * sizeof(float2));
+    if (e != hipSuccess) {
+        p->real_ws = nullptr;
+    } else {
+        e = hipMalloc(&p->real_tw, (size_t)(1024 + n / 1024) * sizeof(float2));
+        if (e != hipSuccess)
+            p->real_tw = nullptr;
+    }
+    if (e != hipSuccess) {
+        e == hipErrorOutOfMemory ? set_err(FFT_ENOMEM, "hipMalloc(real-input workspace) failed")
+                                 : hip_err(e, "hipMalloc(real-input workspace)");
+        free_plan(p);
+        return nullptr;
+    }
+    e = launch_twiddle_big(p->real_tw, static_cast<float2*>(p->real_tw) + 1024, p->log2n, nullptr);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(nullptr);
+    if (e != hipSuccess) {
+        hip_err(e, "real-input split table");
+        free_plan(p);
+        return nullptr;
+    }
+    ok();
+    return p;
+}
+
 fft_plan create_real(int64_t n, int64_t batch, int sign, const Variant* force)
 {
+    if (n > kMaxFusedRealN) {
+        if (force && force->kind != 9) {
+            set_err(FFT_EINVAL_CONFIG, "real-input lengths above 2^15 use the four-step split (variant 9)");
+            return nullptr;
+        }
+        return create_real_large(n, batch, sign);
+    }
     const int log2m = ilog2(n) - 1;
     const Variant v = force ? *force : choose_r32(log2m);
     const KernelReal* r2c = find_real(log2m, v.log2ept, v.wg, 0, v.kind);
@@ -967,10 +1051,29 @@ int check_exec(fft_plan p, const void* in, const void* out, bool to_bins = false
     return FFT_OK;
 }
 
+int exec_c32(fft_plan p, const void* in, void* out, int sign, float scale, hipStream_t st);
+
 // FFT_R32: to_bins selects the real -> bins kernel; we / wi weight the
 // edge and interior bins (see real.hip).
 int exec_real(fft_plan p, const void* in, void* out, bool to_bins, float we, float wi, hipStream_t st)
 {
+    if (p->real_sub) {
+        // Z = DFT_{n/2}(z) into the workspace, then the split (or the
+        // reverse); the complex transform runs unscaled, the weights carry
+        // the plan's scale
+        const float2* tw = static_cast<const float2*>(p->real_tw);
+        if (to_bins) {
+            int rc = exec_c32(p->real_sub, in, p->real_ws, -1, 1.0f, st);
+            if (rc != FFT_OK)
+                return rc;
+            hipError_t e = launch_real_split(0, p->real_ws, out, tw, tw + 1024, p->log2n, p->batch, we, wi, st);
+            return e == hipSuccess ? ok() : hip_err(e, "real-input split launch");
+        }
+        hipError_t e = launch_real_split(1, in, p->real_ws, tw, tw + 1024, p->log2n, p->batch, we, wi, st);
+        if (e != hipSuccess)
+            return hip_err(e, "real-input split launch");
+        return exec_c32(p->real_sub, p->real_ws, out, +1, 1.0f, st);
+    }
     const KernelReal* k = to_bins ? p->r2c : p->c2r;
     hipError_t e = k->fn(in, out, p->rows, p->wn, p->batch, we, wi, p->grid_limit, st);
     if (e != hipSuccess)
@@ -1298,6 +1401,12 @@ int fft_plan_query(int64_t n, int64_t batch, int sign, int dtype, fft_plan_desc*
     int rc = check_common(n, batch, sign, dtype);
     if (rc != FFT_OK)
         return rc;
+    if (dtype == FFT_R32 && n > kMaxFusedRealN) {
+        if (!find_fourstep(ilog2(n) - 1))
+            return set_err(FFT_EINVAL_CONFIG, "no four-step kernels for the half length of n=%lld", (long long)n);
+        fill_desc_r32(n, batch, sign, Variant{0, 0, 9}, 0, d);
+        return ok();
+    }
     if (dtype == FFT_R32) {
         const Variant v = choose_r32(ilog2(n) - 1);
         if (!find_real(ilog2(n) - 1, v.log2ept, v.wg, sign < 0 ? 0 : 1, v.kind))

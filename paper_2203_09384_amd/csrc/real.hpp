@@ -33,3 +33,15 @@ const KernelReal* find_real(int log2m, int log2ept, int wg, int dir, int kind);
 hipError_t launch_twiddle_real(const void* tw, void* wn, int log2n, hipStream_t stream);
 
 }  // namespace mifft
+
+namespace mifft {
+
+// Real-input lengths above 2^15: the even/odd split as a pass of its own
+// around a four-step complex transform of the half length M = n/2.
+//   dir 0: src = Z (M complex per transform), dst = bins X_0..X_M
+//   dir 1: src = bins X_0..X_M, dst = Z' (M complex per transform)
+// tlo / thi: the two-level table w_n^j = thi[j >> 10] * tlo[j & 1023].
+hipError_t launch_real_split(int dir, const void* src, void* dst, const void* tlo, const void* thi, int log2n,
+                             int64_t batch, float we, float wi, hipStream_t stream);
+
+}  // namespace mifft

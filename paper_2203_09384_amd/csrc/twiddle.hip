@@ -134,3 +134,93 @@ hipError_t launch_twiddle_real(const void* tw, void* wn, int log2n, hipStream_t 
 }
 
 }  // namespace mifft
+
+namespace mifft {
+
+// The even/odd split of the real-input transforms above 2^15 (see
+// real.hip for the formulas), one thread per bin pair (k, M - k),
+// k = 0..M/2, so both halves of a transform are read and written in
+// ascending / descending runs.
+struct cf2 {
+    float x, y;
+};
+
+__device__ __forceinline__ cf2 cmul2(cf2 a, cf2 b) { return cf2{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
+
+// X_k from a = Z_k, b = Z_{M-k}, w = w_n^k.
+__device__ __forceinline__ cf2 split_bin(cf2 a, cf2 b, cf2 w)
+{
+    const float sx = 0.5f * (a.x + b.x), sy = 0.5f * (a.y - b.y);
+    const float dx = 0.5f * (a.y + b.y), dy = -0.5f * (a.x - b.x);
+    return cf2{sx + w.x * dx - w.y * dy, sy + w.x * dy + w.y * dx};
+}
+
+// Z'_k from a = X_k, b = X_{M-k}, w = w_n^k.
+__device__ __forceinline__ cf2 unsplit_bin(cf2 a, cf2 b, cf2 w)
+{
+    const float dx = a.x - b.x, dy = a.y + b.y;
+    return cf2{a.x + b.x - w.x * dy + w.y * dx, a.y - b.y + w.x * dx + w.y * dy};
+}
+
+template <int DIR>
+__global__ __launch_bounds__(256) void k_real_split(const cf2* __restrict__ src, cf2* __restrict__ dst,
+                                                    const cf2* __restrict__ tlo, const cf2* __restrict__ thi,
+                                                    int log2m, int64_t kblocks, float we, float wi)
+{
+    const int64_t M = int64_t(1) << log2m;
+    const int64_t b = blockIdx.x / kblocks;
+    const int64_t k = (blockIdx.x % kblocks) * 256 + threadIdx.x;
+    if (k > M / 2)
+        return;
+    const int64_t kp = (M - k) & (M - 1);  // partner bin (k = 0 pairs with itself in Z)
+    const cf2 w = cmul2(thi[k >> 10], tlo[k & 1023]);        // w_n^k
+    const cf2 wp = cmul2(thi[(M - k) >> 10], tlo[(M - k) & 1023]);  // w_n^{M-k}
+    if (DIR == 0) {
+        const cf2* z = src + b * M;
+        cf2* x = dst + b * (M + 1);
+        const cf2 a = z[k], c = z[kp];
+        const float s = k == 0 ? we : wi;
+        const cf2 xk = split_bin(a, c, w);
+        x[k] = cf2{xk.x * s, xk.y * s};
+        if (k == 0) {
+            x[M] = cf2{(a.x - a.y) * we, 0.f};  // X_M = E_0 - O_0
+        } else if (k != M / 2) {
+            const cf2 xm = split_bin(c, a, wp);
+            x[M - k] = cf2{xm.x * wi, xm.y * wi};
+        }
+    } else {
+        const cf2* x = src + b * (M + 1);
+        cf2* z = dst + b * M;
+        cf2 a = x[k], c = x[M - k];
+        if (k == 0) {
+            a.y = 0.f;
+            c.y = 0.f;
+        }
+        const float s = k == 0 ? we : wi;
+        const cf2 zk = unsplit_bin(a, c, w);
+        z[k] = cf2{zk.x * s, zk.y * s};
+        if (k != 0 && k != M / 2) {
+            const cf2 zm = unsplit_bin(c, a, wp);
+            z[M - k] = cf2{zm.x * wi, zm.y * wi};
+        }
+    }
+}
+
+hipError_t launch_real_split(int dir, const void* src, void* dst, const void* tlo, const void* thi, int log2n,
+                             int64_t batch, float we, float wi, hipStream_t stream)
+{
+    const int log2m = log2n - 1;
+    const int64_t kblocks = (((int64_t(1) << log2m) / 2 + 1) + 255) / 256;
+    const dim3 grid((unsigned)(kblocks * batch));
+    if (dir == 0)
+        hipLaunchKernelGGL(k_real_split<0>, grid, dim3(256), 0, stream, static_cast<const cf2*>(src),
+                           static_cast<cf2*>(dst), static_cast<const cf2*>(tlo), static_cast<const cf2*>(thi), log2m,
+                           kblocks, we, wi);
+    else
+        hipLaunchKernelGGL(k_real_split<1>, grid, dim3(256), 0, stream, static_cast<const cf2*>(src),
+                           static_cast<cf2*>(dst), static_cast<const cf2*>(tlo), static_cast<const cf2*>(thi), log2m,
+                           kblocks, we, wi);
+    return hipGetLastError();
+}
+
+}  // namespace mifft

@@ -160,11 +160,23 @@ def test_real_input_queries(L):
         assert d.scale == (1.0 if sign < 0 else np.float32(1.0 / n))
 
 
+@pytest.mark.parametrize("L", range(16, 22))
+def test_large_real_input_queries(L):
+    """Above 2^15 a real-input plan runs the half-length four-step split."""
+    n, m = 1 << L, 1 << (L - 1)
+    for sign in (-1, 1):
+        rc, d = q(n, 7, sign, 3)
+        assert rc == 0, native.lib().fft_last_error_string()
+        assert d.dtype == 3 and d.n == n and d.variant == 9
+        assert int(np.prod(list(d.radices)[: d.npasses])) == m
+        assert d.scale == (1.0 if sign < 0 else np.float32(1.0 / n))
+
+
 def test_real_input_validation():
     L = native.lib()
-    assert q(1 << 16, 1, -1, 3)[0] == 1      # real lengths stop at 2^15
+    assert q(1 << 22, 1, -1, 3)[0] == 1      # real lengths stop at 2^21
     assert q(24, 1, -1, 3)[0] == 1
-    assert L.fft_plan_create(1 << 16, 1, -1, 3) is None and L.fft_last_error() == 1
+    assert L.fft_plan_create(1 << 22, 1, -1, 3) is None and L.fft_last_error() == 1
     assert L.fft_plan_create_config(256, 1, -1, 3, 4, 64, 5) is None and L.fft_last_error() == 10
     assert L.fft_plan_create_config(256, 1, -1, 3, 4, 48, 2) is None and L.fft_last_error() == 10
 

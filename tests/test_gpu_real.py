@@ -3,9 +3,10 @@
 The oracle's rfft / irfft are Eq. (dft) of x + 0i restricted to bins
 0..n/2 and Eq. (idft) of the Hermitian extension (pinned in the oracle's own
 tests).  Bar: max over transforms of the relative L2 error <= 1e-5, as for
-the complex FP32 path.  Every length 2..2^15 runs with its built-in
-configuration at a batch that leaves a partial last workgroup; every
-compiled configuration of a few lengths runs too.
+the complex FP32 path.  Every length 2..2^21 runs with its built-in
+configuration at a batch that leaves a partial last workgroup (above 2^15:
+the four-step half-length transform plus the split pass); every compiled
+configuration of a few lengths runs too.
 """
 import numpy as np
 import pytest
@@ -18,7 +19,7 @@ from gpu_util import need_gpu, per_transform_relerr, to_cpu, to_gpu
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-5
-LS = list(range(1, 16))
+LS = list(range(1, 22))
 
 
 @pytest.fixture(autouse=True)
@@ -131,7 +132,7 @@ def test_every_config(L):
 
 def test_paper_ramp_closed_form():
     """The paper's f(x) = x is real: X_0 = N(N-1)/2, X_k = -N/2 + i (N/2) cot(pi k/N)."""
-    for n in (8, 256, 2048, 1 << 15):
+    for n in (8, 256, 2048, 1 << 15, 1 << 18):
         k = np.arange(1, n // 2 + 1)
         want = np.empty(n // 2 + 1, np.complex128)
         want[0] = n * (n - 1) / 2
