@@ -295,10 +295,15 @@ def fft_differentiable(x, sign: int = -1):
     return FFTFn.apply(x, sign)
 
 
+FUSED_LOSS_MAX_N = 2048  # the fused loss-gradient kernel's lengths
+
+
 class WeightedPowerLossFn(torch.autograd.Function):
     """L = sum_b sum_k w |(A x_b)_k|^2 in one fused kernel that also produces
     dL/dx = A^H (2 w A x) (PyTorch's complex convention); backward scales the
-    saved gradient by the incoming scalar.  w is treated as a constant."""
+    saved gradient by the incoming scalar.  w is treated as a constant.
+    Longer transforms take the plan's transform, the weighting in torch and
+    the plan's adjoint (three launches, the same result)."""
 
     @staticmethod
     def forward(ctx, x, w, sign: int = -1):
@@ -306,7 +311,12 @@ class WeightedPowerLossFn(torch.autograd.Function):
         w = w.contiguous()
         n = x.shape[-1]
         plan = get_plan(n, x.numel() // n, sign, "c32", x.device.index)
-        loss, grad = plan.loss_grad(x, w)
+        if n <= FUSED_LOSS_MAX_N:
+            loss, grad = plan.loss_grad(x, w)
+        else:
+            y = plan.execute(x)
+            loss = (w * (y.real ** 2 + y.imag ** 2)).sum(dim=-1)
+            grad = plan.adjoint((2.0 * w) * y)
         ctx.save_for_backward(grad)
         return loss.sum()
 

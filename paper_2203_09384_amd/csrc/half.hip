@@ -48,16 +48,17 @@ constexpr int HWG = 256;
 // LDS layouts, one per exchange, each conflict-free for both its writer and
 // its reader (modelled on the 64 banks) and affine in the per-instruction
 // indices, so every access is a per-thread base plus an immediate offset.
-// Real and imaginary parts are separate planes; IM_* is the imaginary
-// plane's offset.
+// Element d is one 32-bit word holding its (re, im) as two 16-bit halves:
+// FP16 for the A -> B and B -> C exchanges (the MFMA operand type, so
+// rounding there is the operands' own rounding), the storage format for
+// C -> store (output scale applied first, so the value is rounded once).
 //   A -> B      : d + (d >> 3) + 16 (d >> 10)
 //   B -> C      : d + (d >> 6)
 //   C -> store  : d + (d >> 6) + 4 (d >> 8)
 __device__ __forceinline__ int fA(int d) { return d + (d >> 3) + 16 * (d >> 10); }
 __device__ __forceinline__ int fB(int d) { return d + (d >> 6); }
 __device__ __forceinline__ int fC(int d) { return d + (d >> 6) + 4 * (d >> 8); }
-constexpr int IM_A = 2336, IM_B = 2080, IM_C = 2112;
-constexpr int BUF = 2 * IM_A;  // floats per buffer (largest layout)
+constexpr int BUF = 2336;  // words per buffer (largest layout: fA)
 
 // ---- conversions (round to nearest even)
 template <bool BF>
@@ -135,10 +136,35 @@ __device__ __forceinline__ void unpack8(const uint32_t (&u)[8], cf (&v)[8])
 struct HalfCtx {
     Op8 a_re[2], a_im[2];  // pass B, group g = 2 wave + gg, twiddles folded
     Op8 f_re, f_im;        // pass C, plain DFT
-    cf twB[2][4];              // pass C twiddle of pass B output (gg, i)
+    cf twB[2][4];          // pass C twiddle of pass B output (gg, i)
     int oWA, oRB[2], oWB[2], oRC[2], oWC[2], oRS0, oRS1;
+    uint32_t sel;          // byte selector of this lane's halves (re: low, im: high)
     int tid, lane, wave;
 };
+
+__device__ __forceinline__ uint32_t pack_f16(float a, float b)
+{
+    return (uint32_t)__builtin_bit_cast(uint16_t, (_Float16)a) |
+           ((uint32_t)__builtin_bit_cast(uint16_t, (_Float16)b) << 16);
+}
+
+template <bool BF>
+__device__ __forceinline__ uint32_t pack_store(float a, float b)
+{
+    return (uint32_t)from_f32<BF>(a) | ((uint32_t)from_f32<BF>(b) << 16);
+}
+
+// An MFMA operand from 8 packed words: this lane's half (re or im) of each.
+__device__ __forceinline__ Op8 gather_op(const uint32_t (&w)[8], uint32_t sel)
+{
+    v4u q;
+#pragma unroll
+    for (int j = 0; j < 4; j++)
+        q[j] = __builtin_amdgcn_perm(w[2 * j + 1], w[2 * j], sel);
+    Op8 o;
+    o.hi = __builtin_bit_cast(v8h, q);
+    return o;
+}
 
 __device__ __forceinline__ void load_raw(uint32_t (&u)[8], const uint32_t* __restrict__ in, int64_t b, int tid)
 {
@@ -152,12 +178,14 @@ __device__ __forceinline__ void load_raw(uint32_t (&u)[8], const uint32_t* __res
 // output and exponent.  Once unpacked, `cur` is refilled with transform
 // `refill` (if < batch), so two transforms' loads stay in flight.  X holds
 // the A->B and C->store exchanges, Y the B->C exchange; `red` the per-wave
-// maxima.
+// maxima.  Four barriers: the block maximum (needed before pass A's
+// outputs are scaled to FP16), then one per exchange.
 template <int S, bool BF>
-__device__ __forceinline__ void half_transform(const HalfCtx& c, uint32_t (&cur)[8], float* X, float* Y, float* red,
-                                               const uint32_t* __restrict__ in, const int32_t* __restrict__ in_exp,
-                                               uint32_t* __restrict__ out, int32_t* __restrict__ out_exp,
-                                               int64_t b, int64_t refill, int64_t batch, int scale_log2)
+__device__ __forceinline__ void half_transform(const HalfCtx& c, uint32_t (&cur)[8], uint32_t* X, uint32_t* Y,
+                                               float* red, const uint32_t* __restrict__ in,
+                                               const int32_t* __restrict__ in_exp, uint32_t* __restrict__ out,
+                                               int32_t* __restrict__ out_exp, int64_t b, int64_t refill,
+                                               int64_t batch, int scale_log2)
 {
     constexpr int dWC[4] = {0, 130, 264, 394};  // fC(d0 + 128 i) - fC(d0)
     // ---- pass A: radix 8 on the VALU in FP32 over x[tid + 256 m]
@@ -175,13 +203,6 @@ __device__ __forceinline__ void half_transform(const HalfCtx& c, uint32_t (&cur)
     if (c.lane == 0)
         red[c.wave] = mx;
     dft8<S>(v);
-    // outputs to the Stockham position d = 8 tid + r (pass B's twiddles are in its operands)
-    float* wa = X + c.oWA;
-#pragma unroll
-    for (int r = 0; r < 8; r++) {
-        wa[r] = v[r].x;
-        wa[IM_A + r] = v[r].y;
-    }
     __syncthreads();
 
     // ---- block maximum -> power-of-two scale (largest input component in [8, 16))
@@ -192,6 +213,13 @@ __device__ __forceinline__ void half_transform(const HalfCtx& c, uint32_t (&cur)
     const float sc = ldexpf(1.0f, 4 - e_max);
     const int e_in = in_exp ? in_exp[b] : 0;
     const int e_out = e_in + e_max - 4 + scale_log2;
+    // outputs to the Stockham position d = 8 tid + r, scaled, as FP16 pairs
+    // (pass B's twiddles are in its operands)
+    uint32_t* wa = X + c.oWA;
+#pragma unroll
+    for (int r = 0; r < 8; r++)
+        wa[r] = pack_f16(v[r].x * sc, v[r].y * sc);
+    __syncthreads();
 
     // ---- pass B: radix 16 (NS = 8) on MFMA.  Group g holds the 16 butterflies
     // j = g + 8 n (all with j mod 8 = g, so one twiddled DFT matrix serves them);
@@ -199,11 +227,12 @@ __device__ __forceinline__ void half_transform(const HalfCtx& c, uint32_t (&cur)
     v4f yre[2], yim[2];
 #pragma unroll
     for (int gg = 0; gg < 2; gg++) {
-        const float* rb = X + c.oRB[gg];
-        Op8 bo;
+        const uint32_t* rb = X + c.oRB[gg];
+        uint32_t w[8];
 #pragma unroll
         for (int i = 0; i < 8; i++)
-            bo.set(i, rb[144 * i] * sc);
+            w[i] = rb[144 * i];
+        const Op8 bo = gather_op(w, c.sel);
         const v4f z = {0.f, 0.f, 0.f, 0.f};
         yre[gg] = mfma(c.a_re[gg], bo, z);
         yim[gg] = mfma(c.a_im[gg], bo, z);
@@ -211,50 +240,48 @@ __device__ __forceinline__ void half_transform(const HalfCtx& c, uint32_t (&cur)
     // outputs Y[m] of butterfly j = g + 8 n to d = 128 n + g + 8 m, times pass C's twiddle
 #pragma unroll
     for (int gg = 0; gg < 2; gg++) {
-        float* wb = Y + c.oWB[gg];
+        uint32_t* wb = Y + c.oWB[gg];
 #pragma unroll
         for (int i = 0; i < 4; i++) {
             const cf y = cmul(cf{yre[gg][i], yim[gg][i]}, c.twB[gg][i]);
-            wb[8 * i] = y.x;
-            wb[IM_B + 8 * i] = y.y;
+            wb[8 * i] = pack_f16(y.x, y.y);
         }
     }
     __syncthreads();
 
     // ---- pass C: radix 16 (NS = 128) on MFMA over butterflies j = 16 g + n;
-    // natural-order outputs d = j + 128 m
+    // natural-order outputs d = j + 128 m, stored in the output format
 #pragma unroll
     for (int gg = 0; gg < 2; gg++) {
-        const float* rc = Y + c.oRC[gg];
-        Op8 bo;
+        const uint32_t* rc = Y + c.oRC[gg];
+        uint32_t w[8];
 #pragma unroll
         for (int i = 0; i < 8; i++)
-            bo.set(i, rc[130 * i]);
+            w[i] = rc[130 * i];
+        const Op8 bo = gather_op(w, c.sel);
         const v4f z = {0.f, 0.f, 0.f, 0.f};
         yre[gg] = mfma(c.f_re, bo, z);
         yim[gg] = mfma(c.f_im, bo, z);
     }
+    const float osc = out_exp ? 1.0f : ldexpf(1.0f, e_out);
 #pragma unroll
     for (int gg = 0; gg < 2; gg++) {
-        float* wc = X + c.oWC[gg];
+        uint32_t* wc = X + c.oWC[gg];
 #pragma unroll
-        for (int i = 0; i < 4; i++) {
-            wc[dWC[i]] = yre[gg][i];
-            wc[IM_C + dWC[i]] = yim[gg][i];
-        }
+        for (int i = 0; i < 4; i++)
+            wc[dWC[i]] = pack_store<BF>(yre[gg][i] * osc, yim[gg][i] * osc);
     }
     __syncthreads();
 
     // ---- store: 4 consecutive elements (16 bytes) per lane and instruction
-    const float osc = out_exp ? 1.0f : ldexpf(1.0f, e_out);
     v4u* dst = reinterpret_cast<v4u*>(out + b * HN);
 #pragma unroll
     for (int h = 0; h < 2; h++) {
-        const float* rs = X + (h ? c.oRS1 : c.oRS0);
+        const uint32_t* rs = X + (h ? c.oRS1 : c.oRS0);
         v4u o;
 #pragma unroll
         for (int i = 0; i < 4; i++)
-            o[i] = (uint32_t)from_f32<BF>(rs[i] * osc) | ((uint32_t)from_f32<BF>(rs[IM_C + i] * osc) << 16);
+            o[i] = rs[i];
         __builtin_nontemporal_store(o, dst + c.tid + HWG * h);
     }
     if (out_exp && c.tid == 0)
@@ -272,7 +299,7 @@ __global__ __launch_bounds__(HWG, 4) void k_fft_half_2048(const uint32_t* __rest
                                                        uint32_t* __restrict__ out, int32_t* __restrict__ out_exp,
                                                        const cf* __restrict__ tw, int64_t batch, int scale_log2)
 {
-    __shared__ float lds[2 * BUF];
+    __shared__ uint32_t lds[2 * BUF];
     __shared__ float s_red[2][HWG / 64];
     int64_t b = blockIdx.x;
     if (b >= batch)
@@ -290,18 +317,19 @@ __global__ __launch_bounds__(HWG, 4) void k_fft_half_2048(const uint32_t* __rest
 #pragma unroll
         for (int i = 0; i < 4; i++)  // w_2048^{n (g + 8 m)}, m = 4 kq + i
             c.twB[gg][i] = tw_at<S>(tw, n * (g + 8 * (4 * kq + i)));
-        c.oRB[gg] = ((kq >> 1) ? IM_A : 0) + fA(g + 8 * n + 128 * r0);
+        c.oRB[gg] = fA(g + 8 * n + 128 * r0);
         c.oWB[gg] = fB(128 * n + g + 32 * kq);
         const int j = 16 * g + n;
-        c.oRC[gg] = ((kq >> 1) ? IM_B : 0) + fB(j + 128 * r0);
+        c.oRC[gg] = fB(j + 128 * r0);
         c.oWC[gg] = fC(j + 512 * kq);
     }
+    c.sel = (kq >> 1) ? 0x07060302u : 0x05040100u;  // rows k >= 16 take the imaginary halves
     c.oWA = fA(8 * c.tid);
     c.oRS0 = fC(4 * c.tid);
     c.oRS1 = fC(4 * (c.tid + HWG));
 
-    float* const buf0 = lds;
-    float* const buf1 = lds + BUF;
+    uint32_t* const buf0 = lds;
+    uint32_t* const buf1 = lds + BUF;
     uint32_t ua[8], ub[8];
     const int64_t stride = gridDim.x;
     load_raw(ua, in, b, c.tid);
@@ -418,7 +446,7 @@ void half_query(int64_t n, int64_t batch, fft_plan_desc* d)
     d->radices[0] = 8;
     d->radices[1] = 16;
     d->radices[2] = 16;
-    d->lds_bytes = (int)((2 * BUF + 2 * HWG / 64) * sizeof(float));
+    d->lds_bytes = (int)(2 * BUF * sizeof(uint32_t) + 2 * HWG / 64 * sizeof(float));
     d->kind = 0;
     d->variant = 0;
 }

@@ -174,3 +174,16 @@ def test_fused_loss_gradient_vs_finite_differences():
                 e[b, i] = unit * h
                 fd[b, i] += unit * (loss(x64 + e) - loss(x64 - e)) / (2 * h)
     assert per_transform_relerr(g, fd) <= TOL
+
+
+def test_weighted_power_loss_beyond_fused_lengths():
+    """n = 8192: the loss falls back to transform + torch weighting + adjoint."""
+    n, batch = 8192, 6
+    x = synth.uniform_complex(45, (batch, n))
+    w = synth.uniform_weights(45, (batch, n), key=(1,))
+    xg = to_gpu(x).requires_grad_(True)
+    L = api.weighted_power_loss(xg, to_gpu(w))
+    L.backward()
+    loss_ref, g_ref = oracle.loss_grad(x.astype(np.complex128), w.astype(np.float64))
+    assert abs(float(L) - loss_ref) / loss_ref < 1e-5
+    assert per_transform_relerr(xg.grad.cpu().numpy(), g_ref) <= TOL
