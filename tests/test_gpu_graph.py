@@ -118,3 +118,24 @@ def test_four_step_in_graph():
     ref = p.execute(x)
     y = torch.empty_like(x)
     replay_and_check(capture(lambda: p.execute(x, y)), [y], [ref], x)
+
+
+def test_one_plan_on_two_streams():
+    """A batched plan is immutable after creation: executes of it on two
+    streams at once give the eager results."""
+    n, batch = 2048, 4096
+    p = api.Plan(n, batch, -1)
+    xs = [to_gpu(synth.uniform_complex(63, (batch, n), key=(i,))) for i in range(2)]
+    refs = [p.execute(x).clone() for x in xs]
+    torch.cuda.synchronize()
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    outs = [torch.empty_like(x) for x in xs]
+    for s in streams:
+        s.wait_stream(torch.cuda.current_stream())
+    for _ in range(20):
+        for s, x, o in zip(streams, xs, outs):
+            with torch.cuda.stream(s):
+                p.execute(x, o, stream=s)
+    torch.cuda.synchronize()
+    for o, r in zip(outs, refs):
+        assert torch.equal(o, r)
