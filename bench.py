@@ -114,6 +114,15 @@ def bench_half(api, synth, torch, dev, steps, ms_fp32, x_all):
         res[dt] = {"us": round(m * 1e3, 2), "GBps": round(alg / (m * 1e-3) / 1e9, 1),
                    "GFLOPs": round(5.0 * n * 11 * batch / (m * 1e-3) / 1e9, 1),
                    "speedup_vs_fp32": round(ms_fp32 / m, 3)}
+        # a short length (FP32 passes with 16-bit storage), same bytes
+        ns, bs = 256, batch * 8
+        ps = api.Plan(ns, bs, -1, dtype=dt)
+        xs, ys = xh.view(bs, ns, 2), yh.view(bs, ns, 2)
+        exs = torch.empty(bs, dtype=torch.int32, device=dev)
+        ms_s = time_launches(lambda: ps.execute_scaled(xs, out=ys, out_exp=exs), steps, 20, torch)
+        res[dt]["n256_batch262144"] = {"us": round(ms_s * 1e3, 2),
+                                       "GBps": round((8.0 * ns * bs + 4.0 * bs) / (ms_s * 1e-3) / 1e9, 1)}
+        ps.close()
         del xh, yh
     return res
 

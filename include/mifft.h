@@ -122,7 +122,9 @@ typedef struct {
  *          LDS); 2^15 .. 2^20 (the paper's future work, section
  *          "Conclusions") use the four-step split N = N1 N2: a column pass
  *          with the w_N^{n2 k1} twiddles, then an in-place row pass in
- *          `out` (two kernels on the stream).  FFT_C16 / FFT_CBF16: 2048.
+ *          `out` (two kernels on the stream).  FFT_C16 / FFT_CBF16: [2, 2048]
+ *          (2048: radix-16 passes on MFMA; below: the FP32 passes with
+ *          16-bit storage).
  *          FFT_R32: [2, 2^21]; up to 2^15 one fused kernel per
  *          execute, above it the half-length four-step transform plus a
  *          split pass through a plan-owned workspace of n/2 complex values

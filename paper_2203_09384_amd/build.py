@@ -39,6 +39,8 @@ def _units():
         units.append(("ragged.hip", f"ragged_wg{wg}.o", [f"-DMIFFT_RAGGED_WG={wg}"]))
     units.append(("ragged_plan.cpp", "ragged_plan.o", ["-x", "hip"]))
     units.append(("half.hip", "half.o", []))
+    for L in range(1, 11):
+        units.append(("half_small.hip", f"half_small_L{L}.o", [f"-DMIFFT_LOG2N={L}"]))
     units.append(("api.cpp", "api.o", ["-x", "hip"]))
     return units
 

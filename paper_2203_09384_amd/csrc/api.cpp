@@ -823,7 +823,7 @@ fft_plan create_batched(int64_t n, int64_t batch, int sign, int dtype, const Var
         return nullptr;
     }
     if (dtype != FFT_C32) {
-        int rc = half_create(&p->half, n, batch, dtype);
+        int rc = half_create(&p->half, n, batch, dtype, p->tw);
         if (rc != FFT_OK) {
             set_err(rc, "%s", half_last_message());
             free_plan(p);

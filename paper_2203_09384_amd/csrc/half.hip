@@ -31,6 +31,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <vector>
 
 #include "device_fft.hpp"
 #include "half.hpp"
@@ -371,19 +372,47 @@ int occupancy_half()
 
 thread_local char g_hmsg[256] = "";
 
+std::vector<KernelHalfSmall>& small_reg()
+{
+    static std::vector<KernelHalfSmall> r;
+    return r;
+}
+
+const KernelHalfSmall* find_small(int log2n, int sign, bool bf16)
+{
+    for (const auto& k : small_reg())
+        if (k.log2n == log2n && k.sign == sign && k.bf16 == bf16)
+            return &k;
+    return nullptr;
+}
+
+int ilog2h(int64_t v)
+{
+    int l = 0;
+    while ((int64_t(1) << l) < v)
+        l++;
+    return l;
+}
+
 }  // namespace
+
+hipError_t launch_twiddle_rows(const void* tw, void* rows, int L, int E, int total, hipStream_t stream);
+
+void register_half_small(const KernelHalfSmall& k) { small_reg().push_back(k); }
 
 struct HalfPlan {
     int64_t n = 0, batch = 0;
     int dtype = FFT_C16;
     int64_t grid_limit[2] = {0, 0};  // CUs x resident workgroups, forward / inverse kernel
+    const KernelHalfSmall* small[2] = {nullptr, nullptr};  // n < 2048: forward / inverse kernel
+    void* rows = nullptr;                                  // their twiddle rows
 };
 
-bool half_supported(int64_t n) { return n == HN; }
-const char* half_supported_lengths() { return "2048"; }
+bool half_supported(int64_t n) { return n >= 2 && n <= HN && (n & (n - 1)) == 0; }
+const char* half_supported_lengths() { return "2, 4, ..., 2048"; }
 const char* half_last_message() { return g_hmsg; }
 
-int half_create(HalfPlan** out, int64_t n, int64_t batch, int dtype)
+int half_create(HalfPlan** out, int64_t n, int64_t batch, int dtype, const void* tw)
 {
     *out = nullptr;
     if (batch > 0x7fffffffLL) {
@@ -398,6 +427,32 @@ int half_create(HalfPlan** out, int64_t n, int64_t batch, int dtype)
     hp->n = n;
     hp->batch = batch;
     hp->dtype = dtype;
+    if (n < HN) {
+        const int L = ilog2h(n);
+        const bool bf = dtype == FFT_CBF16;
+        hp->small[0] = find_small(L, -1, bf);
+        hp->small[1] = find_small(L, +1, bf);
+        if (!hp->small[0] || !hp->small[1]) {
+            snprintf(g_hmsg, sizeof g_hmsg, "no half-precision kernel for n=%lld", (long long)n);
+            delete hp;
+            return FFT_EINVAL_CONFIG;
+        }
+        const KernelHalfSmall* k = hp->small[0];
+        if (k->rows > 0) {
+            hipError_t e = hipMalloc(&hp->rows, (size_t)k->rows * sizeof(float2));
+            if (e == hipSuccess)
+                e = launch_twiddle_rows(tw, hp->rows, L, k->log2ept, k->rows, nullptr);
+            if (e == hipSuccess)
+                e = hipStreamSynchronize(nullptr);
+            if (e != hipSuccess) {
+                snprintf(g_hmsg, sizeof g_hmsg, "half-precision twiddle rows: %s", hipGetErrorString(e));
+                half_destroy(hp);
+                return e == hipErrorOutOfMemory ? FFT_ENOMEM : FFT_EHIP;
+            }
+        }
+        *out = hp;
+        return FFT_OK;
+    }
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
@@ -416,8 +471,17 @@ int half_create(HalfPlan** out, int64_t n, int64_t batch, int dtype)
 int half_execute(HalfPlan* hp, const void* in, const int32_t* in_exp, void* out, int32_t* out_exp, const void* tw,
                  int sign, hipStream_t stream)
 {
-    const int sl = sign > 0 ? -11 : 0;  // inverse: the 1/N of Eq. (idft), exact in the exponent
     hipError_t e;
+    if (hp->small[0]) {
+        const int sl = sign > 0 ? -ilog2h(hp->n) : 0;  // the inverse's 1/N, exact in the exponent
+        e = hp->small[sign > 0 ? 1 : 0]->fn(in, in_exp, out, out_exp, hp->rows, hp->batch, sl, stream);
+        if (e != hipSuccess) {
+            snprintf(g_hmsg, sizeof g_hmsg, "half-precision kernel launch: %s", hipGetErrorString(e));
+            return FFT_EHIP;
+        }
+        return FFT_OK;
+    }
+    const int sl = sign > 0 ? -11 : 0;  // inverse: the 1/N of Eq. (idft), exact in the exponent
     const bool bf = hp->dtype == FFT_CBF16;
     if (sign < 0)
         e = bf ? launch_half<-1, true>(in, in_exp, out, out_exp, tw, hp->batch, sl, hp->grid_limit[0], stream)
@@ -432,10 +496,37 @@ int half_execute(HalfPlan* hp, const void* in, const int32_t* in_exp, void* out,
     return FFT_OK;
 }
 
-void half_destroy(HalfPlan* hp) { delete hp; }
+void half_destroy(HalfPlan* hp)
+{
+    if (hp && hp->rows)
+        (void)hipFree(hp->rows);
+    delete hp;
+}
 
 void half_query(int64_t n, int64_t batch, fft_plan_desc* d)
 {
+    if (n < HN) {
+        const KernelHalfSmall* k = find_small(ilog2h(n), -1, false);
+        d->n = n;
+        d->batch = batch;
+        if (!k)
+            return;
+        const int L = ilog2h(n), tpt = (int)(n >> k->log2ept);
+        d->ept = 1 << k->log2ept;
+        d->wg = k->wg;
+        d->transforms_per_wg = k->wg / tpt;
+        d->grid = (batch + d->transforms_per_wg - 1) / d->transforms_per_wg;
+        const int rem = L % k->log2ept;
+        int np = 0;
+        if (rem)
+            d->radices[np++] = 1 << rem;
+        for (int i = 0; i < L / k->log2ept; i++)
+            d->radices[np++] = 1 << k->log2ept;
+        d->npasses = np;
+        d->kind = 0;
+        d->variant = 0;
+        return;
+    }
     d->n = n;
     d->batch = batch;
     d->ept = 8;
@@ -454,6 +545,8 @@ void half_query(int64_t n, int64_t batch, fft_plan_desc* d)
 void half_describe(const HalfPlan* hp, fft_plan_desc* d)
 {
     half_query(hp->n, hp->batch, d);
+    if (hp->small[0])
+        return;
     const int64_t lim = hp->grid_limit[d->sign > 0 ? 1 : 0];
     if (lim > 0 && d->grid > lim)
         d->grid = lim;

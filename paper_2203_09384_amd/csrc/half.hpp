@@ -1,4 +1,5 @@
-// FP16 / BF16 storage path: block floating point, radix-16 stages on MFMA.
+// FP16 / BF16 storage path: block floating point; N = 2048 with radix-16
+// stages on MFMA, N = 2 .. 1024 around the FP32 Stockham passes.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -9,9 +10,21 @@ namespace mifft {
 
 struct HalfPlan;
 
+// Lengths 2 .. 1024 (half_small.hip): rows are the per-pass twiddle rows of
+// (log2n, log2ept); scale_log2 is added to every output exponent.
+using LaunchHalfSmall = hipError_t (*)(const void* in, const int32_t* in_exp, void* out, int32_t* out_exp,
+                                       const void* rows, int64_t batch, int scale_log2, hipStream_t stream);
+struct KernelHalfSmall {
+    int log2n, log2ept, wg, sign;
+    bool bf16;
+    LaunchHalfSmall fn;
+    int rows;  // twiddle-row entries (float2)
+};
+void register_half_small(const KernelHalfSmall& k);
+
 bool half_supported(int64_t n);
 const char* half_supported_lengths();
-int half_create(HalfPlan** out, int64_t n, int64_t batch, int dtype);
+int half_create(HalfPlan** out, int64_t n, int64_t batch, int dtype, const void* tw);
 int half_execute(HalfPlan* hp, const void* in, const int32_t* in_exp, void* out, int32_t* out_exp,
                  const void* tw, int sign, hipStream_t stream);
 void half_destroy(HalfPlan* hp);

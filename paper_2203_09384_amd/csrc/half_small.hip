@@ -1,0 +1,160 @@
+// FP16 / BF16 storage for lengths 2 .. 1024 (compiled once per log2 N with
+// -DMIFFT_LOG2N=<1..10>): block floating point around the FP32 Stockham
+// passes of the batched kernels.
+//
+// Storage is (re, im) pairs of 16-bit values with one int32 exponent per
+// transform (logical value = stored * 2^exp).  Each transform is
+//   loaded and widened to FP32, scaled by the power of two that brings its
+//   largest component into [1/2, 1) (exact), transformed with the FP32
+//   passes (growth at most N <= 2^10), scaled again so its largest output
+//   component lies in [2^14, 2^15) (exact), and narrowed to the storage
+//   type once.
+// out_exp = in_exp + e_in + e_out - 15 (- log2 N for the inverse's 1/N).
+// The radix-16 MFMA passes of the 2048-point kernel need at least 256
+// points and pay off at that size; here the transform's threads share one
+// wavefront, so both maxima are wavefront shuffles.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "device_fft.hpp"
+#include "half.hpp"
+
+#ifndef MIFFT_LOG2N
+#error "compile with -DMIFFT_LOG2N=<1..10>"
+#endif
+
+namespace mifft {
+namespace {
+
+template <bool BF>
+__device__ __forceinline__ float h_to_f32(uint32_t h)
+{
+    if constexpr (BF)
+        return __builtin_bit_cast(float, h << 16);
+    else
+        return (float)__builtin_bit_cast(_Float16, (uint16_t)h);
+}
+
+template <bool BF>
+__device__ __forceinline__ uint32_t f32_to_h(float f)
+{
+    if constexpr (BF)
+        return (uint32_t)__builtin_bit_cast(uint16_t, (__bf16)f);
+    else
+        return (uint32_t)__builtin_bit_cast(uint16_t, (_Float16)f);
+}
+
+// Largest |component| over the TPT threads of a transform (contiguous
+// lanes of one wavefront), in every one of them.
+template <int TPT>
+__device__ __forceinline__ float group_max(float m)
+{
+#pragma unroll
+    for (int off = TPT / 2; off > 0; off >>= 1)
+        m = fmaxf(m, __shfl_xor(m, off));
+    return m;
+}
+
+template <int E>
+__device__ __forceinline__ float abs_max(const cf (&v)[1 << E])
+{
+    float m = 0.f;
+#pragma unroll
+    for (int i = 0; i < (1 << E); i++)
+        m = fmaxf(m, fmaxf(fabsf(v[i].x), fabsf(v[i].y)));
+    return m;
+}
+
+// the exponent e with m < 2^e (0 for zero or non-finite m)
+__device__ __forceinline__ int exp_above(float m)
+{
+    int e = 0;
+    if (m > 0.f && m <= 3.4e38f)
+        (void)frexpf(m, &e);
+    return e;
+}
+
+template <int L, int E, int WG, int S, bool BF>
+__global__ __launch_bounds__(WG) void k_half_small(const uint32_t* __restrict__ in, const int32_t* __restrict__ in_exp,
+                                                   uint32_t* __restrict__ out, int32_t* __restrict__ out_exp,
+                                                   const cf* __restrict__ rows, int64_t batch, int scale_log2)
+{
+    using SC = Sched<L, E>;
+    constexpr int N = SC::N, EPT = SC::EPT, TPT = SC::TPT, TPB = WG / TPT;
+    static_assert(TPT <= 64, "a transform's threads share one wavefront");
+    constexpr int REG = TPT > 1 ? Layout2<L, E>::region() : 1;
+    __shared__ cf lds[TPT > 1 ? TPB * REG : 1];
+    const int tid = threadIdx.x, tb = tid / TPT, t = tid % TPT;
+    const int64_t b = (int64_t)blockIdx.x * TPB + tb;
+    const bool live = b < batch;
+    cf v[EPT];
+#pragma unroll
+    for (int m = 0; m < EPT; m++) {
+        const uint32_t u = live ? in[b * N + t + m * TPT] : 0u;
+        v[m] = cf{h_to_f32<BF>(u & 0xffffu), h_to_f32<BF>(u >> 16)};
+    }
+    // normalise: largest component into [1/2, 1)
+    const int e_in = exp_above(group_max<TPT>(abs_max<E>(v)));
+    const float s_in = ldexpf(1.0f, -e_in);
+#pragma unroll
+    for (int m = 0; m < EPT; m++)
+        v[m] = cscale(v[m], s_in);
+    TwRegs<L, E> tws;
+#pragma unroll
+    for (int p = 0; p < SC::NP; p++)
+#pragma unroll
+        for (int r = 0; r < EPT; r++)
+            tws[p][r] = cf{1.f, 0.f};
+    if constexpr (TPT == 1)
+        pass_compute2<L, E, S, 0>(v, tws[0]);
+    else
+        run2<L, E, S, 1, true>(v, t, rows, tws, lds + tb * REG);
+    // output: largest component into [2^14, 2^15), or the logical value
+    const int e_o = exp_above(group_max<TPT>(abs_max<E>(v)));
+    const int ein = (live && in_exp) ? in_exp[b] : 0;
+    const int e_total = ein + e_in + e_o - 15 + scale_log2;  // logical = stored * 2^e_total
+#pragma unroll
+    for (int m = 0; m < EPT; m++) {
+        const cf y = out_exp ? cscale(v[m], ldexpf(1.0f, 15 - e_o))
+                             : cf{ldexpf(v[m].x, ein + e_in + scale_log2), ldexpf(v[m].y, ein + e_in + scale_log2)};
+        if (live)
+            out[b * N + t + m * TPT] = f32_to_h<BF>(y.x) | (f32_to_h<BF>(y.y) << 16);
+    }
+    if (out_exp && live && t == 0)
+        out_exp[b] = e_total;
+}
+
+template <int L, int E, int WG, int S, bool BF>
+hipError_t launch_half_small(const void* in, const int32_t* in_exp, void* out, int32_t* out_exp, const void* rows,
+                             int64_t batch, int scale_log2, hipStream_t stream)
+{
+    constexpr int TPB = WG / ((1 << L) >> E);
+    const int64_t grid = (batch + TPB - 1) / TPB;
+    hipLaunchKernelGGL((k_half_small<L, E, WG, S, BF>), dim3((unsigned)grid), dim3(WG), 0, stream,
+                       static_cast<const uint32_t*>(in), in_exp, static_cast<uint32_t*>(out), out_exp,
+                       static_cast<const cf*>(rows), batch, scale_log2);
+    return hipGetLastError();
+}
+
+// One configuration per length: elements per thread and workgroup size.
+constexpr int small_e(int L) { return L <= 2 ? L : (L <= 6 ? 2 : (L == 7 || L == 9 ? 3 : 4)); }
+constexpr int small_wg(int L) { return L <= 2 ? 64 : (L <= 5 || L == 8 ? 256 : 64); }
+
+template <int L>
+void add_small()
+{
+    constexpr int E = small_e(L), WG = small_wg(L), TPT = (1 << L) >> E;
+    const int rows = TPT > 1 ? Layout2<L, E>::rows_total() : 0;
+    register_half_small(KernelHalfSmall{L, E, WG, -1, false, &launch_half_small<L, E, WG, -1, false>, rows});
+    register_half_small(KernelHalfSmall{L, E, WG, +1, false, &launch_half_small<L, E, WG, +1, false>, rows});
+    register_half_small(KernelHalfSmall{L, E, WG, -1, true, &launch_half_small<L, E, WG, -1, true>, rows});
+    register_half_small(KernelHalfSmall{L, E, WG, +1, true, &launch_half_small<L, E, WG, +1, true>, rows});
+}
+
+struct HalfSmallRegistrar {
+    HalfSmallRegistrar() { add_small<MIFFT_LOG2N>(); }
+};
+HalfSmallRegistrar half_small_registrar;
+
+}  // namespace
+}  // namespace mifft

@@ -115,7 +115,11 @@ def test_half_precision_queries():
     assert rc == 0 and d.radices[:3] == [8, 16, 16] and d.wg == 256
     rc, d = q(2048, 4, 1, 2)
     assert rc == 0 and d.scale == np.float32(1.0 / 2048)
-    assert q(1024, 4, -1, 1)[0] == 4   # FP16/BF16 plans are N=2048 only
+    for L in range(1, 11):               # FP16/BF16 below 2048: FP32 passes, 16-bit storage
+        rc, d = q(1 << L, 100, 1, 1)
+        assert rc == 0 and int(np.prod(list(d.radices)[: d.npasses])) == 1 << L
+        assert d.scale == np.float32(1.0 / (1 << L))
+    assert q(4096, 4, -1, 1)[0] == 1     # half precision stops at 2048
     L = native.lib()
     assert L.fft_execute_scaled(None, None, None, None, None, None) == 5
 

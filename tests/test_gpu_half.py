@@ -124,3 +124,65 @@ def test_unit_scale_execute_and_determinism(dtype):
     assert torch.equal(y, y2)
     ref = oracle.forward(from_half(xh))
     assert rel(from_half(out), ref) <= TOL
+
+
+# ---------------------------------------------------------------- n = 2 .. 1024
+# FP32 Stockham passes with 16-bit storage and block exponents.
+SMALL = [1 << L for L in range(1, 11)]
+
+
+def draw_n(cls, batch, n, key):
+    if cls == "uniform":
+        return synth.uniform_complex(synth.SEED_HALF, (batch, n), key=(n, key, 0), dtype=np.complex128)
+    return synth.log_uniform_polar(synth.SEED_HALF, (batch, n), key=(n, key, 1))
+
+
+# The error of these lengths is the rounding of the stored output: one
+# value rounds with relative error at most 2^-11 (FP16) or 2^-8 (BF16, 8
+# significant bits), and with few outputs per transform the per-transform
+# L2 error need not average below that.  Bars: those bounds plus the FP32
+# passes' ~1e-6.  (At N = 2048 the BF16 error averages to ~1.7e-3, under
+# the 3e-3 bar of that workload.)
+SMALL_TOL = {"c16": 2.0 ** -11 + 1e-5, "cbf16": 2.0 ** -8 + 1e-5}
+
+
+@pytest.mark.parametrize("n", SMALL)
+@pytest.mark.parametrize("dtype", ["c16", "cbf16"])
+@pytest.mark.parametrize("sign", [-1, 1])
+def test_small_lengths_parity(n, dtype, sign):
+    """Both input classes against the oracle on the stored input."""
+    batch = 3 * max(1, 4096 // n) + 1
+    p = api.Plan(n, batch, sign, dtype=dtype)
+    print(f"[case] half small n={n} {dtype} sign={sign} {p.describe()}", flush=True)
+    for cls in ("uniform", "loguniform"):
+        xh = to_half(draw_n(cls, batch, n, 4), dtype)
+        yh, ex = p.execute_scaled(xh)
+        torch.cuda.synchronize()
+        y = from_half(yh, ex)
+        xs = from_half(xh)
+        ref = oracle.forward(xs) if sign < 0 else oracle.inverse(xs)
+        e = rel(y, ref)
+        assert np.all(np.isfinite(y))
+        assert e <= SMALL_TOL[dtype], (cls, e)
+        # stored outputs use the format's range: largest component in
+        # [2^14, 2^15] (scaled below 2^15, which rounding may reach)
+        mx = yh.float().abs().amax(dim=(1, 2))
+        assert float(mx.max()) <= 2.0 ** 15 and float(mx.min()) >= 2.0 ** 14
+
+
+@pytest.mark.parametrize("n", [2, 64, 1024])
+@pytest.mark.parametrize("dtype", ["c16", "cbf16"])
+def test_small_lengths_exponents_and_unit_scale(n, dtype):
+    """An input exponent shifts only the output exponent; unit-scale output
+    (no exponent array) is the logical value."""
+    batch = 33
+    xh = to_half(1e-2 * draw_n("uniform", batch, n, 5), dtype)
+    p = api.Plan(n, batch, -1, dtype=dtype)
+    y0, e0 = p.execute_scaled(xh)
+    k = torch.from_numpy(np.random.default_rng(1).integers(-20, 20, batch).astype(np.int32)).cuda()
+    y1, e1 = p.execute_scaled(xh, in_exp=k)
+    out = p.execute(xh)
+    torch.cuda.synchronize()
+    assert torch.equal(y0, y1)
+    assert torch.equal(e1, e0 + k)
+    assert rel(from_half(out), oracle.forward(from_half(xh))) <= SMALL_TOL[dtype]
