@@ -218,6 +218,8 @@ int fft_execute(fft_plan p, const void *in, void *out, void *stream);
  * opposite sign at the SAME scale.  For a forward plan that is the
  * unnormalised inverse sum (no 1/n); for an inverse plan it is the forward
  * sum times 1/n.  Used as the backward pass of the differentiable FFT.
+ * FFT_C16 / FFT_CBF16 plans write the adjoint at unit scale (no exponent
+ * array), as fft_execute does for them.
  * FFT_R32 plans map the other way round (spectrum side -> real side for a
  * sign -1 plan) and apply the adjoint under the real inner product
  * Re<a, b>, which is the gradient PyTorch takes through the transform:

@@ -1276,8 +1276,15 @@ int fft_execute_adjoint(fft_plan p, const void* in, void* out, void* stream)
         const float s = p->scale;
         return exec_real(p, in, out, true, s, 2.0f * s, static_cast<hipStream_t>(stream));
     }
-    if (p->dtype != FFT_C32)
-        return set_err(FFT_EINVAL_DTYPE, "the adjoint is provided for FFT_C32 plans");
+    if (p->dtype != FFT_C32) {
+        // FP16/BF16: the opposite sign at the plan's scale, unit-scale output
+        // (as fft_execute on these plans)
+        rc = half_execute(p->half, in, nullptr, out, nullptr, p->tw, -p->sign, p->sign > 0,
+                          static_cast<hipStream_t>(stream));
+        if (rc != FFT_OK)
+            return set_err(rc, "%s", half_last_message());
+        return ok();
+    }
     return exec_c32(p, in, out, -p->sign, p->scale, static_cast<hipStream_t>(stream));
 }
 
@@ -1291,7 +1298,7 @@ int fft_execute_scaled(fft_plan p, const void* in, const int32_t* in_exp, void* 
         return set_err(FFT_EINVAL_DTYPE, "fft_execute_scaled needs an FFT_C16 or FFT_CBF16 plan");
     if ((reinterpret_cast<uintptr_t>(in_exp) | reinterpret_cast<uintptr_t>(out_exp)) & 3)
         return set_err(FFT_EALIGN, "exponent arrays must be 4-byte aligned");
-    rc = half_execute(p->half, in, in_exp, out, out_exp, p->tw, p->sign, static_cast<hipStream_t>(stream));
+    rc = half_execute(p->half, in, in_exp, out, out_exp, p->tw, p->sign, p->sign > 0, static_cast<hipStream_t>(stream));
     if (rc != FFT_OK)
         return set_err(rc, "%s", half_last_message());
     return ok();

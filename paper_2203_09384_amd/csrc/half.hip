@@ -469,11 +469,12 @@ int half_create(HalfPlan** out, int64_t n, int64_t batch, int dtype, const void*
 }
 
 int half_execute(HalfPlan* hp, const void* in, const int32_t* in_exp, void* out, int32_t* out_exp, const void* tw,
-                 int sign, hipStream_t stream)
+                 int sign, bool inv_scale, hipStream_t stream)
 {
     hipError_t e;
+    // the 1/N of an inverse-scaled transform, exact in the exponent
+    const int sl = inv_scale ? -ilog2h(hp->n) : 0;
     if (hp->small[0]) {
-        const int sl = sign > 0 ? -ilog2h(hp->n) : 0;  // the inverse's 1/N, exact in the exponent
         e = hp->small[sign > 0 ? 1 : 0]->fn(in, in_exp, out, out_exp, hp->rows, hp->batch, sl, stream);
         if (e != hipSuccess) {
             snprintf(g_hmsg, sizeof g_hmsg, "half-precision kernel launch: %s", hipGetErrorString(e));
@@ -481,7 +482,6 @@ int half_execute(HalfPlan* hp, const void* in, const int32_t* in_exp, void* out,
         }
         return FFT_OK;
     }
-    const int sl = sign > 0 ? -11 : 0;  // inverse: the 1/N of Eq. (idft), exact in the exponent
     const bool bf = hp->dtype == FFT_CBF16;
     if (sign < 0)
         e = bf ? launch_half<-1, true>(in, in_exp, out, out_exp, tw, hp->batch, sl, hp->grid_limit[0], stream)

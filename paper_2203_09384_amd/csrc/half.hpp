@@ -25,8 +25,10 @@ void register_half_small(const KernelHalfSmall& k);
 bool half_supported(int64_t n);
 const char* half_supported_lengths();
 int half_create(HalfPlan** out, int64_t n, int64_t batch, int dtype, const void* tw);
+// sign: the exponent sign applied; inv_scale: whether the 1/N is applied
+// (the plan's scale, also for its adjoint, which has the opposite sign).
 int half_execute(HalfPlan* hp, const void* in, const int32_t* in_exp, void* out, int32_t* out_exp,
-                 const void* tw, int sign, hipStream_t stream);
+                 const void* tw, int sign, bool inv_scale, hipStream_t stream);
 void half_destroy(HalfPlan* hp);
 void half_describe(const HalfPlan* hp, fft_plan_desc* d);
 void half_query(int64_t n, int64_t batch, fft_plan_desc* d);

@@ -186,3 +186,19 @@ def test_small_lengths_exponents_and_unit_scale(n, dtype):
     assert torch.equal(y0, y1)
     assert torch.equal(e1, e0 + k)
     assert rel(from_half(out), oracle.forward(from_half(xh))) <= SMALL_TOL[dtype]
+
+
+@pytest.mark.parametrize("n", [64, 2048])
+@pytest.mark.parametrize("dtype", ["c16", "cbf16"])
+@pytest.mark.parametrize("sign", [-1, 1])
+def test_half_adjoint(n, dtype, sign):
+    """The adjoint of a half-precision plan: opposite sign, the plan's scale,
+    unit-scale output."""
+    batch = 19
+    xh = to_half(1e-2 * draw_n("uniform", batch, n, 6), dtype)
+    p = api.Plan(n, batch, sign, dtype=dtype)
+    out = p.adjoint(xh)
+    torch.cuda.synchronize()
+    ref = oracle.adjoint(from_half(xh), sign, 1.0 if sign < 0 else 1.0 / n)
+    bar = SMALL_TOL[dtype] if n < 2048 else TOL
+    assert rel(from_half(out), ref) <= bar
