@@ -39,9 +39,13 @@ __device__ __forceinline__ cf big_twiddle(const cf* __restrict__ lo, const cf* _
 // columns so that two workgroups fit one CU's LDS (MI355X, 2^26 elements:
 // 2^20 616 -> 578 us, 2^19 583 -> 547 us).
 constexpr int col_tile(int L1) { return L1 >= 10 ? 8 : 16; }
+// Columns of 128+ points load straight into registers (MI355X: 2^15
+// 485 -> 468 us, 2^16 494 -> 479 us against staging 128- and 256-point
+// columns through LDS); the row pass keeps the axis-pass threshold.
+constexpr bool col_direct(int L1) { return L1 >= 7; }
 
 // Pass 1: tile = columns n2 in [T nb, T nb + T) of transform b (T =
-// col_tile).  Long columns (axis_direct) are read straight into registers
+// col_tile).  Long columns (col_direct) are read straight into registers
 // (the column index is the fastest lane index: rows of T values per
 // wavefront access); short ones are staged through LDS so their exchanges
 // stay inside one wavefront.  Either way the outputs go out through LDS:
@@ -54,7 +58,7 @@ __global__ __launch_bounds__(col_tile(L1)*((1 << L1) >> inner_e(L1))) void k_fou
     constexpr int T = col_tile(L1), LT = T == 16 ? 4 : 3;
     constexpr int E = inner_e(L1), N1 = 1 << L1, N2 = 1 << L2, N = N1 * N2;
     constexpr int EPT = 1 << E, TPT = N1 / EPT, WG = T * TPT, ST = stage_stride<L1, E>();
-    constexpr bool DIRECT = axis_direct(L1);
+    constexpr bool DIRECT = col_direct(L1);
     static_assert(T == 16 || DIRECT, "8-column tiles load directly");
     __shared__ cf lds[T * ST];
     const int tid = threadIdx.x;
