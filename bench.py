@@ -7,7 +7,7 @@ One step = one fft_execute of that batch.  Also measured in the same run:
 the forward + adjoint pair of the differentiable FFT (N = 2048, batch
 16384), the per-N sweep (every N = 2..2048 at 2^26 elements, forward and
 inverse), a plain 512 MiB copy kernel as the practical bandwidth ceiling,
-the ragged batch (4096 mixed lengths, one persistent launch vs per-length
+the ragged batch (4096 mixed lengths, one launch vs per-length
 launches), and the FP64 CPU oracle on a bounded sample (cpu_baseline).
 
 Prints ONE JSON line.  Times come from HIP events recorded on the stream
@@ -187,7 +187,7 @@ def bench_nd(api, torch, steps, x_all, y_all):
 
 
 def bench_ragged(api, synth, torch, dev, iters):
-    """One persistent launch over 4096 mixed-length transforms (eager and
+    """One launch over 4096 mixed-length transforms (eager and
     graph-replayed) against per-length plain launches (eager and in one
     graph), the transforms pre-grouped by length outside the timed region."""
     import numpy as np

@@ -41,9 +41,8 @@
  *     asynchronous and surface at the caller's next synchronisation.
  *   - A plan is bound to the HIP device that was current when it was
  *     created and is immutable afterwards, so executes of one plan on
- *     several streams may run concurrently -- except ragged plans, whose
- *     work counter is shared: executes of ONE ragged plan must not overlap
- *     in time (use one plan per stream).
+ *     several streams may run concurrently (plan-owned workspaces are the
+ *     exception; see the plans that have one).
  */
 #ifndef MIFFT_H
 #define MIFFT_H
@@ -161,9 +160,10 @@ fft_plan fft_plan_create_config(int64_t n, int64_t batch, int sign, int dtype, i
  * into the plan: offsets[0] = 0, and each length offsets[b+1]-offsets[b]
  * is a power of two in [2, 2048]; transform b occupies elements
  * [offsets[b], offsets[b+1]) of both input and output.  Every execute is
- * one persistent kernel launch that pulls length-grouped work tiles from a
- * plan-owned counter (largest transforms first) and resets the counter
- * itself when done, so the launch can be captured into a hipGraph.
+ * one kernel launch over length-grouped work tiles (largest transforms
+ * first), dealt to its workgroups in a fixed order; the launch keeps no
+ * device state between executes, so it can be captured into a hipGraph
+ * and executes of one plan on several streams may overlap.
  * Only FFT_C32.  sign as for fft_plan_create; the inverse scales each
  * transform by 1/its length.
  */
@@ -172,10 +172,11 @@ fft_plan fft_plan_create_ragged(int64_t count, const int64_t *offsets, int sign,
 /*
  * As fft_plan_create_ragged with the per-length kernel variant forced:
  * ept_by_log2n[L] (L = 1..11; entries 0 ignored) gives the elements per
- * thread used for length 2^L, `wg` the workgroup size of the persistent
- * launch (64..512) and `ctas_per_cu` how many workgroups per compute unit
- * the launch holds (0: as many as fit).  wg must be 64, 128 or 256 (0: the
- * built-in choice).  Used by the autotuner.
+ * thread used for length 2^L, `wg` the workgroup size of the launch and
+ * `ctas_per_cu` how many workgroups per compute unit the launch holds
+ * (0: as many as fit; the grid is never larger than the tile count, and
+ * workgroups loop over the tiles when it is smaller).  wg must be 64, 128
+ * or 256 (0: the built-in choice).  Used by the autotuner.
  */
 fft_plan fft_plan_create_ragged_config(int64_t count, const int64_t *offsets, int sign, int dtype,
                                        const int *ept_by_log2n, int wg, int ctas_per_cu);

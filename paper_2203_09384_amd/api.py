@@ -178,7 +178,7 @@ class _DeviceArray:
 
 class RaggedPlan:
     """fft_plan_create_ragged(count, offsets, sign, dtype): mixed lengths,
-    packed back to back, one persistent launch per execute."""
+    packed back to back, one launch per execute."""
 
     def __init__(self, offsets, sign: int = -1, dtype: str = "c32",
                  ept_by_log2n=None, wg: int = 0, ctas_per_cu: int = 0):

@@ -4,12 +4,18 @@
 // The paper finds that for transforms running O(10) us, kernel dispatch --
 // not the transform -- dominates (section "Results", launch-latency table).
 // A mixed batch would otherwise need one launch per length.  Here one
-// launch of CUs x occupancy workgroups pulls tiles from a counter (largest
-// lengths first) and dispatches, per tile, to the transform instantiated
-// for that (length, elements per thread); every such instantiation is the
-// same Stockham pass machinery as the batched kernels.  The last workgroup
-// to finish resets the counters, so the launch can be replayed from a
-// hipGraph without any memset node.
+// launch covers every tile of the plan (tiles sorted largest length first)
+// and each workgroup dispatches, per tile, to the transform instantiated for
+// that (length, elements per thread); every such instantiation is the same
+// Stockham pass machinery as the batched kernels.
+//
+// Tiles are dealt to workgroups statically, in rounds of gridDim.x, the
+// order reversed every other round (workgroup b takes tile r G + b in even
+// rounds r, r G + G - 1 - b in odd ones), so that each workgroup's share of
+// the longest-first list is balanced.  A shared atomic counter would balance
+// dynamically, but its atomics serialise on one address (about 10 ns each on
+// MI355X, which made them most of the launch); the static deal needs no
+// device state, so a launch replays from a hipGraph as it is.
 #include "device_fft.hpp"
 #include "ragged_kernel.hpp"
 
@@ -48,11 +54,11 @@ constexpr int ragged_lds_elems()
 }
 
 template <int L, int E, int WG, int S>
-__device__ __forceinline__ void ragged_tile(const RaggedArgs& a, const RaggedTile& tile, cf* lds)
+__device__ __forceinline__ void ragged_tile(const RaggedArgs& a, const RaggedTile& tile, cf* lds, int tid)
 {
     using SC = Sched<L, E>;
     constexpr int N = SC::N, EPT = SC::EPT, TPT = SC::TPT;
-    const int tid = threadIdx.x, tb = tid / TPT, t = tid % TPT;
+    const int tb = tid / TPT, t = tid % TPT;
     const bool live = tb < tile.count;
     const int64_t off = live ? a.toff[tile.first + tb] : 0;
     const cf* __restrict__ src = static_cast<const cf*>(a.in) + off;
@@ -85,23 +91,27 @@ __device__ __forceinline__ void ragged_tile(const RaggedArgs& a, const RaggedTil
 #define MIFFT_RCASE(L, E)                                      \
     case (L) * 8 + (E):                                        \
         if constexpr (ragged_pair_ok(L, E, WG, MAXE))          \
-            ragged_tile<L, E, WG, S>(a, tile, lds);            \
+            ragged_tile<L, E, WG, S>(a, tile, lds, tid);       \
         break;
 
 template <int WG, int MAXE, int S>
 __global__ __launch_bounds__(WG) void k_fft_ragged(RaggedArgs a)
 {
     __shared__ cf lds[ragged_lds_elems<WG, MAXE>()];
-    __shared__ int s_tile;
-    while (true) {
-        if (threadIdx.x == 0)
-            s_tile = atomicAdd(a.counter, 1);
-        __syncthreads();
-        const int ti = s_tile;
-        __syncthreads();  // s_tile read by all; the previous tile's LDS use is over
+    const int G = gridDim.x, b = blockIdx.x;
+    for (int base = 0, round = 0; base < a.ntiles; base += G, round++) {
+        const int ti = base + ((round & 1) ? G - 1 - b : b);
         if (ti >= a.ntiles)
-            break;
+            break;  // only in the last round
+        if (round > 0)
+            __syncthreads();  // the previous tile's LDS use is over
         const RaggedTile tile = a.tiles[ti];
+        // The thread index is made opaque per tile: otherwise the address
+        // arithmetic of every case is hoisted out of the loop and stays
+        // live across all of them (294 VGPRs, one wavefront per SIMD,
+        // instead of the largest single case's 83).
+        int tid = threadIdx.x;
+        asm volatile("" : "+v"(tid));
         switch (tile.log2n * 8 + tile.log2e) {
             MIFFT_RCASE(1, 1)
             MIFFT_RCASE(2, 1) MIFFT_RCASE(2, 2)
@@ -116,13 +126,6 @@ __global__ __launch_bounds__(WG) void k_fft_ragged(RaggedArgs a)
             MIFFT_RCASE(11, 2) MIFFT_RCASE(11, 3) MIFFT_RCASE(11, 4)
             default:
                 break;
-        }
-    }
-    // The last workgroup out resets both counters for the next launch.
-    if (threadIdx.x == 0) {
-        if (atomicAdd(a.done, 1) == (int)gridDim.x - 1) {
-            atomicExch(a.counter, 0);
-            atomicExch(a.done, 0);
         }
     }
 }

@@ -19,8 +19,6 @@ struct RaggedArgs {
     const void* rows;           // concatenated per-length twiddle rows
     const int64_t* toff;        // element offset of each transform, tile order
     const RaggedTile* tiles;    // largest lengths first
-    int* counter;               // next tile to hand out; reset to 0 by the last workgroup
-    int* done;                  // workgroups finished; reset to 0 by the last workgroup
     int ntiles;
     int inv;                    // nonzero: scale each transform by 1/its length
     int rows_off[12];           // start of length 2^L's rows in `rows`

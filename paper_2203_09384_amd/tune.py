@@ -3,9 +3,8 @@
 For the batched FP32 path it times, per length N, each (elements per thread,
 workgroup size) variant compiled into libmifft.so on a batch of `total`
 elements, and keeps the fastest.  For ragged batches it picks, per length,
-the elements-per-thread of the persistent kernel and the workgroup size of
-the launch, timing one graph-free persistent launch over a seeded ragged
-batch.  Real-input plans (R2C and C2R) are tuned per half length on the
+the elements-per-thread of the ragged kernel and the workgroup size of
+the launch, timing one graph-free launch over a seeded ragged batch.  Real-input plans (R2C and C2R) are tuned per half length on the
 sum of both directions' times.  The result is a text table ("c32 <log2n>
 <ept> <wg> <variant>", "r32 <log2(n/2)> <ept> <wg> <variant>" and
 "ragged <log2n> <ept>" / "ragged_wg <wg> <ctas_per_cu>" lines) that the library reads
@@ -116,7 +115,7 @@ def tune_real(total: int = 1 << 27, steps: int = 30, warmup: int = 5, log2ns=ran
 
 def tune_ragged(count: int = 4096, iters: int = 300, log=print):
     """Per-length elements per thread and the workgroup size of the ragged
-    persistent kernel, by coordinate descent on one seeded ragged batch
+    kernel, by coordinate descent on one seeded ragged batch
     (lengths 2^3..2^11), timing one launch per call."""
     import numpy as np
     import torch
@@ -138,7 +137,7 @@ def tune_ragged(count: int = 4096, iters: int = 300, log=print):
 
     record, best = [], None
     for wg in (64, 128, 256):
-        table = [0, 2, 4, 8, 4, 4, 4, 8, 8, 8, 16, 16]
+        table = [0, 2, 4, 8, 4, 4, 4, 8, 8, 8, 8, 8]
         cur = cost(table, wg)
         for _ in range(2):
             for L in range(3, 12):

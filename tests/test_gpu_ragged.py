@@ -1,4 +1,4 @@
-"""Ragged batches (mixed lengths, one persistent launch) against the FP64 oracle.
+"""Ragged batches (mixed lengths, one launch) against the FP64 oracle.
 
 Workload of record: 4096 transforms, lengths 2^L with L uniform on 3..11,
 packed back to back; bar: every transform within relative L2 1e-5.
@@ -55,7 +55,7 @@ def test_every_length_including_2_and_4():
     assert max_seg_err(y, ref, off) <= TOL
 
 
-def test_repeated_launches_reset_the_counter():
+def test_repeated_launches_agree():
     off, x = workload(1000, 3, 11, seed=11)
     p = api.RaggedPlan(off, -1)
     xg = to_gpu(x)
@@ -77,7 +77,7 @@ def test_adjoint():
 
 
 def test_graph_replay_matches_eager():
-    """One persistent launch captured in a graph; replays interleaved with
+    """One launch captured in a graph; replays interleaved with
     other eager work all equal the eager result bit for bit."""
     off, x = workload(4096, 3, 11, seed=17)
     p = api.RaggedPlan(off, -1)
