@@ -126,3 +126,43 @@ def test_single_transform_and_ctas_limit():
     p = api.RaggedPlan(off, -1, ctas_per_cu=1)
     y = to_cpu(p.execute(to_gpu(x)))
     assert max_seg_err(y, oracle.forward(x.astype(np.complex128)), off) <= TOL
+
+
+@pytest.mark.parametrize("ctas", [1, 2, 3])
+def test_several_rounds_per_workgroup(ctas):
+    """A grid smaller than the tile list: each workgroup takes tiles in
+    rounds, every other round reversed.  The result is bitwise that of the
+    one-round launch (same per-tile kernels) and within tolerance of the
+    oracle."""
+    off, x = workload(4096, 3, 11, seed=29)
+    xg = to_gpu(x)
+    full = api.RaggedPlan(off, -1, wg=128)
+    p = api.RaggedPlan(off, -1, wg=128, ctas_per_cu=ctas)
+    d, dfull = p.describe(), full.describe()
+    print(f"[case] ragged rounds ctas={ctas} grid={d['grid']} tiles={d['tiles']}", flush=True)
+    assert d["grid"] < d["tiles"] and d["tiles"] == dfull["tiles"]
+    y = p.execute(xg)
+    assert torch.equal(y, full.execute(xg))
+    ref = oracle.fft_ragged(x.astype(np.complex128), off, -1)
+    assert max_seg_err(to_cpu(y), ref, off) <= TOL
+
+
+def test_one_plan_on_two_streams():
+    """A ragged launch keeps no device state, so executes of one plan may
+    overlap on two streams."""
+    off, _ = workload(2000, 3, 11, seed=31)
+    p = api.RaggedPlan(off, -1)
+    xs = [to_gpu(synth.uniform_complex(31, (int(off[-1]),), key=(i,))) for i in range(2)]
+    refs = [p.execute(x).clone() for x in xs]
+    torch.cuda.synchronize()
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    outs = [torch.empty_like(x) for x in xs]
+    for s in streams:
+        s.wait_stream(torch.cuda.current_stream())
+    for _ in range(20):
+        for s, x, o in zip(streams, xs, outs):
+            with torch.cuda.stream(s):
+                p.execute(x, o, stream=s)
+    torch.cuda.synchronize()
+    for o, r in zip(outs, refs):
+        assert torch.equal(o, r)
