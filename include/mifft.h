@@ -267,6 +267,14 @@ int fft_plan_describe(fft_plan p, fft_plan_desc *d);
  * launch, without touching any device.  Same argument checks and codes. */
 int fft_plan_query(int64_t n, int64_t batch, int sign, int dtype, fft_plan_desc *d);
 
+/* Host-only: the FP32 kernel variants compiled in for length n (a power of
+ * two in [2, 2048]) that fft_plan_create_config accepts for both signs.
+ * Writes up to `cap` triples (ept, wg, variant) to out[3*i .. 3*i+2] and
+ * returns how many variants exist (which may exceed cap; out may be NULL
+ * when cap is 0).  Returns -1 with FFT_EINVAL_N / FFT_ENULL set on error.
+ * Touches no device.  Used by the autotuner and the tests. */
+int fft_c32_variants(int64_t n, int *out, int cap);
+
 /* Device address of the plan's FP32 twiddle table tw[m] = exp(-2 pi i m/2048),
  * m < 2048 (16 KiB), or NULL.  Read-only; owned by the plan. */
 const void *fft_plan_twiddles(fft_plan p);

@@ -32,6 +32,17 @@ def query(n: int, batch: int = 1, sign: int = -1, dtype: str = "c32") -> dict:
     return d.as_dict()
 
 
+def c32_variants(n: int) -> list:
+    """Host-only: the compiled FP32 variants (ept, wg, variant) for length n."""
+    L = lib()
+    count = L.fft_c32_variants(n, None, 0)
+    if count < 0:
+        check(L.fft_last_error())
+    buf = (ctypes.c_int * (3 * count))()
+    L.fft_c32_variants(n, buf, count)
+    return [tuple(buf[3 * i: 3 * i + 3]) for i in range(count)]
+
+
 class Plan:
     """fft_plan_create(n, batch, sign, dtype) and its execute calls.
 

@@ -1440,6 +1440,29 @@ int fft_plan_query(int64_t n, int64_t batch, int sign, int dtype, fft_plan_desc*
     return ok();
 }
 
+int fft_c32_variants(int64_t n, int* out, int cap)
+{
+    if (!is_pow2(n) || n < 2 || n > 2048)
+        return set_err(FFT_EINVAL_N, "n=%lld: variants are listed for powers of two in [2, 2048]", (long long)n), -1;
+    if (cap > 0 && !out)
+        return set_err(FFT_ENULL, "out is NULL"), -1;
+    const int log2n = ilog2(n);
+    int count = 0;
+    for (int i = 0; i < mifft::count_c32(); i++) {
+        const mifft::KernelC32* k = mifft::c32_at(i);
+        if (k->log2n != log2n || k->sign != -1 || !mifft::find_c32(log2n, k->log2ept, k->wg, +1, k->kind))
+            continue;
+        if (count < cap) {
+            out[3 * count + 0] = 1 << k->log2ept;
+            out[3 * count + 1] = k->wg;
+            out[3 * count + 2] = k->kind;
+        }
+        count++;
+    }
+    ok();
+    return count;
+}
+
 const void* fft_plan_twiddles(fft_plan p) { return p ? p->tw : nullptr; }
 
 int fft_last_error(void) { return g_err; }

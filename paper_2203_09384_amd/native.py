@@ -24,7 +24,7 @@ EXPORTS = [
     "fft_plan_create_ragged_config", "fft_execute", "fft_execute_adjoint",
     "fft_execute_scaled", "fft_plan_destroy", "fft_plan_describe", "fft_plan_query",
     "fft_plan_twiddles", "fft_last_error", "fft_last_error_string", "fft_version",
-    "fft_execute_loss_grad", "fft_plan_create_nd",
+    "fft_execute_loss_grad", "fft_plan_create_nd", "fft_c32_variants",
 ]
 
 
@@ -100,6 +100,8 @@ def _declare(L):
     L.fft_last_error.restype = i32
     L.fft_last_error_string.argtypes = []
     L.fft_last_error_string.restype = ctypes.c_char_p
+    L.fft_c32_variants.argtypes = [i64, ctypes.POINTER(i32), i32]
+    L.fft_c32_variants.restype = i32
     L.fft_version.argtypes = []
     L.fft_version.restype = ctypes.c_char_p
     return L

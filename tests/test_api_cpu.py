@@ -217,3 +217,24 @@ def test_nd_axis_kernels_are_compiled():
         arr = (ctypes.c_int64 * 2)(d0, 16)
         assert L.fft_plan_create_nd(2, arr, 2, 1, 0) is None
         assert L.fft_last_error() == 8, (d0, L.fft_last_error_string())
+
+
+@pytest.mark.parametrize("L", range(1, 12))
+def test_compiled_variant_listing(L):
+    """fft_c32_variants lists distinct configurations, each consistent with
+    n, and includes the tuned default that fft_plan_query picks."""
+    from paper_2203_09384_amd import api
+    n = 1 << L
+    vs = api.c32_variants(n)
+    assert len(vs) == len(set(vs)) >= 1
+    for ept, wg, var in vs:
+        assert ept in (2, 4, 8, 16) and 64 <= wg <= 1024 and 0 <= var <= 8
+        assert ept <= n
+    rc, d = q(n, 1000, -1)
+    assert rc == 0 and (d.ept, d.wg, d.variant) in vs
+    Lib = native.lib()
+    assert Lib.fft_c32_variants(n, None, 0) == len(vs)
+    assert Lib.fft_c32_variants(3, None, 0) == -1 and Lib.fft_last_error() == 1
+    assert Lib.fft_c32_variants(4096, None, 0) == -1
+    assert Lib.fft_c32_variants(n, None, 1) == -1 and Lib.fft_last_error() == 5
+

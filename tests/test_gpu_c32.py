@@ -10,7 +10,6 @@ import torch
 
 import oracle
 from paper_2203_09384_amd import api, synth
-from paper_2203_09384_amd.native import MifftError
 from gpu_util import need_gpu, per_transform_relerr, to_cpu, to_gpu
 
 pytestmark = pytest.mark.gpu
@@ -79,13 +78,8 @@ def test_default_variant_parity(n, sign):
 
 
 def variants():
-    out = []
-    for n in NS:
-        for ept in (2, 4, 8, 16):
-            for wg in (64, 128, 256, 512):
-                for var in range(9):
-                    out.append((n, ept, wg, var))
-    return out
+    """Every (n, ept, wg, variant) compiled into the library (host-only query)."""
+    return [(n, *v) for n in NS for v in api.c32_variants(n)]
 
 
 @pytest.mark.parametrize("n,ept,wg,var", variants())
@@ -93,12 +87,7 @@ def test_every_compiled_variant(n, ept, wg, var):
     """Every compiled kernel variant, both signs, several workgroups and a
     partly filled last group; persistent variants (3, 4, 7, 8) additionally with
     more groups than workgroups, so each workgroup loops and prefetches."""
-    try:
-        p = api.Plan(n, 1 << 24, -1, ept=ept, wg=wg, variant=var)
-    except MifftError as e:
-        assert e.status == "FFT_EINVAL_CONFIG"
-        pytest.skip("variant not compiled in")
-    d = p.describe()
+    d = api.Plan(n, 1 << 24, -1, ept=ept, wg=wg, variant=var).describe()
     tpw = d["transforms_per_wg"]
     batches = [2 * tpw + 3 if tpw > 3 else 2 * tpw + 1]
     if var in (3, 4, 7, 8):
