@@ -166,17 +166,17 @@ const Variant kDefaultC32[21] = {
     {0, 0, 0},     // unused
     {1, 64, 0},    // N=2     one thread per transform
     {2, 128, 0},   // N=4
-    {2, 256, 2},   // N=8
+    {3, 256, 0},   // N=8     one thread per transform
     {2, 256, 2},   // N=16
-    {2, 256, 2},   // N=32
-    {2, 64, 6},    // N=64    wavefront-local exchanges
+    {2, 128, 6},   // N=32
+    {2, 128, 5},   // N=64    wavefront-local exchanges
     {3, 64, 6},    // N=128
-    {4, 256, 6},   // N=256
+    {3, 64, 5},    // N=256
     {3, 64, 6},    // N=512
-    {4, 64, 3},    // N=1024  persistent, next-group prefetch
-    {4, 128, 3},   // N=2048  persistent, next-group prefetch
+    {3, 128, 2},   // N=1024
+    {4, 256, 3},   // N=2048  persistent, next-group prefetch
     {3, 512, 3},   // N=2^12  one transform per workgroup
-    {3, 1024, 3},  // N=2^13
+    {4, 512, 3},   // N=2^13
     {4, 1024, 2},  // N=2^14  135 KiB LDS
     {0, 0, 9},     // N=2^15 .. 2^20: four-step (column + row pass)
     {0, 0, 9}, {0, 0, 9}, {0, 0, 9}, {0, 0, 9}, {0, 0, 9},
@@ -188,18 +188,18 @@ const Variant kDefaultC32[21] = {
 const Variant kDefaultR32[15] = {
     {0, 256, 0},   // n=2     one thread per transform, no passes
     {1, 64, 0},    // n=4     the half-length transform inside one thread
-    {2, 128, 0},   // n=8
-    {3, 256, 0},   // n=16
+    {2, 256, 0},   // n=8
+    {2, 256, 2},   // n=16
     {2, 256, 2},   // n=32
-    {2, 128, 2},   // n=64
+    {3, 256, 3},   // n=64    persistent, next-group prefetch
     {2, 256, 2},   // n=128
     {3, 256, 6},   // n=256   wavefront-local exchanges
-    {3, 256, 6},   // n=512
-    {3, 256, 7},   // n=1024  wavefront-local, persistent
-    {4, 128, 3},   // n=2048  persistent, next-group prefetch
+    {4, 256, 3},   // n=512   persistent, next-group prefetch
+    {4, 256, 3},   // n=1024
+    {4, 64, 3},    // n=2048
     {4, 128, 3},   // n=4096
     {4, 256, 3},   // n=2^13  one transform per workgroup
-    {3, 1024, 2},  // n=2^14
+    {4, 512, 3},   // n=2^14
     {4, 1024, 2},  // n=2^15
 };
 

@@ -523,16 +523,18 @@ __device__ __forceinline__ void load_group(cf (&v)[1 << E], const cf* __restrict
     constexpr bool NT = stream_nt<N, TPT>();
     const int64_t first = g * TPB;
     const char* gb = reinterpret_cast<const char*>(in + first * N);
-    if (first + TPB <= batch) {
-#pragma unroll
-        for (int m = 0; m < EPT; m++)
-            v[m] = ld_data<NT>(gb + (toff8 + (unsigned)(m * TPT * 8)));
-    } else {
-        const bool live = first + tb < batch;
-#pragma unroll
-        for (int m = 0; m < EPT; m++)
-            v[m] = live ? ld_data<NT>(gb + (toff8 + (unsigned)(m * TPT * 8))) : cf{0.f, 0.f};
+    unsigned off = toff8;
+    if constexpr (TPB > 1) {
+        // Threads of a transform past the end of the batch (last group
+        // only) read the batch's last transform instead: every thread
+        // issues the same loads, with no branch around them, and those
+        // results are never stored.
+        const int64_t last = batch - 1 - first;
+        off = first + tb < batch ? toff8 : (unsigned)(last * N + (toff8 / 8u) % (unsigned)TPT) * 8u;
     }
+#pragma unroll
+    for (int m = 0; m < EPT; m++)
+        v[m] = ld_data<NT>(gb + (off + (unsigned)(m * TPT * 8)));
 }
 
 template <int L, int E, int TPB>

@@ -143,30 +143,38 @@ __global__ __launch_bounds__(WG) void k_fft_c32_v2(const cf* __restrict__ in, cf
         store_group<L, E, TPB>(a, out, g, batch, tb, toff8, scale);
         return;
     }
+    // Groups g, g + stride, ... ; `left` more after the current one.  The
+    // loop body issues the next group's loads unconditionally (two groups
+    // per trip, one per register set), and the last one or two groups run
+    // after it.  A prefetch under a condition would let the path without
+    // it meet the path with it before the current group is used, and the
+    // wait placed there would then cover most of the prefetched loads.
     const int64_t stride = gridDim.x;
-    while (true) {
-        int64_t g1 = g + stride;
-        if (PF && g1 < ngroups)
-            load_group<L, E, TPB>(b, in, g1, batch, tb, toff8);
+    int64_t left = (ngroups - 1 - g) / stride;
+    while (left >= 2) {
+        load_group<L, E, TPB>(b, in, g + stride, batch, tb, toff8);
         run2<L, E, S, TW, WAVE>(a, t, rows, tws, my);
         store_group<L, E, TPB>(a, out, g, batch, tb, toff8, scale);
-        if (g1 >= ngroups)
-            break;
-        if (!PF)
-            load_group<L, E, TPB>(b, in, g1, batch, tb, toff8);
+        g += stride;
         lds_sync<WAVE>();  // LDS is reused by the next group
-        g = g1;
-        g1 = g + stride;
-        if (PF && g1 < ngroups)
-            load_group<L, E, TPB>(a, in, g1, batch, tb, toff8);
+        load_group<L, E, TPB>(a, in, g + stride, batch, tb, toff8);
         run2<L, E, S, TW, WAVE>(b, t, rows, tws, my);
         store_group<L, E, TPB>(b, out, g, batch, tb, toff8, scale);
-        if (g1 >= ngroups)
-            break;
-        if (!PF)
-            load_group<L, E, TPB>(a, in, g1, batch, tb, toff8);
+        g += stride;
         lds_sync<WAVE>();
-        g = g1;
+        left -= 2;
+    }
+    if (left == 1) {
+        load_group<L, E, TPB>(b, in, g + stride, batch, tb, toff8);
+        run2<L, E, S, TW, WAVE>(a, t, rows, tws, my);
+        store_group<L, E, TPB>(a, out, g, batch, tb, toff8, scale);
+        g += stride;
+        lds_sync<WAVE>();
+        run2<L, E, S, TW, WAVE>(b, t, rows, tws, my);
+        store_group<L, E, TPB>(b, out, g, batch, tb, toff8, scale);
+    } else {
+        run2<L, E, S, TW, WAVE>(a, t, rows, tws, my);
+        store_group<L, E, TPB>(a, out, g, batch, tb, toff8, scale);
     }
 }
 

@@ -137,21 +137,26 @@ __global__ __launch_bounds__(WG) void k_fft_loss_grad(const cf* __restrict__ x, 
     const int64_t stride = gridDim.x;
     cf a[EPT], b[EPT];
     load_group<L, E, TPB>(a, x, g, batch, tb, toff8);
-    while (true) {
-        int64_t g1 = g + stride;
-        if (g1 < ngroups)
-            load_group<L, E, TPB>(b, x, g1, batch, tb, toff8);
+    // `left` groups follow the current one.  Inside the loop the next
+    // group's load is unconditional (a conditional one makes the wait
+    // before the current group's first use cover the prefetch too).
+    int64_t left = (ngroups - 1 - g) / stride;
+    while (left >= 2) {
+        load_group<L, E, TPB>(b, x, g + stride, batch, tb, toff8);
         loss_grad_group<L, E, WG, S>(a, w, grad, loss, rows, g, batch, tb, t, toff8, scale, my, red);
-        if (g1 >= ngroups)
-            break;
-        g = g1;
-        g1 = g + stride;
-        if (g1 < ngroups)
-            load_group<L, E, TPB>(a, x, g1, batch, tb, toff8);
+        g += stride;
+        load_group<L, E, TPB>(a, x, g + stride, batch, tb, toff8);
         loss_grad_group<L, E, WG, S>(b, w, grad, loss, rows, g, batch, tb, t, toff8, scale, my, red);
-        if (g1 >= ngroups)
-            break;
-        g = g1;
+        g += stride;
+        left -= 2;
+    }
+    if (left == 1) {
+        load_group<L, E, TPB>(b, x, g + stride, batch, tb, toff8);
+        loss_grad_group<L, E, WG, S>(a, w, grad, loss, rows, g, batch, tb, t, toff8, scale, my, red);
+        g += stride;
+        loss_grad_group<L, E, WG, S>(b, w, grad, loss, rows, g, batch, tb, t, toff8, scale, my, red);
+    } else {
+        loss_grad_group<L, E, WG, S>(a, w, grad, loss, rows, g, batch, tb, t, toff8, scale, my, red);
     }
 }
 

@@ -192,8 +192,13 @@ __device__ __forceinline__ void half_transform(const HalfCtx& c, uint32_t (&cur)
     // ---- pass A: radix 8 on the VALU in FP32 over x[tid + 256 m]
     cf v[8];
     unpack8<BF>(cur, v);
-    if (refill < batch)
-        load_raw(cur, in, refill, c.tid);
+    // This transform's input exponent is read before the refill is issued,
+    // and the refill itself is unconditional (past the end of the batch it
+    // re-reads the last transform, which every workgroup shares through
+    // the cache): a load issued after the refill, or a refill under a
+    // condition, would make the first wait below cover the refill as well.
+    const int e_in = in_exp ? in_exp[b] : 0;
+    load_raw(cur, in, refill < batch ? refill : batch - 1, c.tid);
     float mx = 0.f;
 #pragma unroll
     for (int m = 0; m < 8; m++)
@@ -212,7 +217,6 @@ __device__ __forceinline__ void half_transform(const HalfCtx& c, uint32_t (&cur)
     if (mx > 0.f && mx <= 3.4e38f)
         (void)frexpf(mx, &e_max);  // mx < 2^e_max
     const float sc = ldexpf(1.0f, 4 - e_max);
-    const int e_in = in_exp ? in_exp[b] : 0;
     const int e_out = e_in + e_max - 4 + scale_log2;
     // outputs to the Stockham position d = 8 tid + r, scaled, as FP16 pairs
     // (pass B's twiddles are in its operands)
@@ -334,8 +338,8 @@ __global__ __launch_bounds__(HWG, 4) void k_fft_half_2048(const uint32_t* __rest
     uint32_t ua[8], ub[8];
     const int64_t stride = gridDim.x;
     load_raw(ua, in, b, c.tid);
-    if (b + stride < batch)
-        load_raw(ub, in, b + stride, c.tid);
+    load_raw(ub, in, b + stride < batch ? b + stride : batch - 1, c.tid);
+    __builtin_amdgcn_sched_barrier(0);  // the first transform's loads are issued before the second's
     while (true) {
         half_transform<S, BF>(c, ua, buf0, buf1, s_red[0], in, in_exp, out, out_exp, b, b + 2 * stride, batch,
                               scale_log2);

@@ -65,18 +65,23 @@ __device__ __forceinline__ void load_bins(cf (&a)[1 << E], cf& aM, const cf* __r
     constexpr int M = RS::M, TPT = RS::TPT;
     const int64_t first = g * RS::TPB;
     const char* ib = reinterpret_cast<const char*>(in + first * (M + 1));
-    const unsigned o8 = (unsigned)(tb * (M + 1) + t) * 8u;
-    const bool live = first + tb < batch;
+    // Threads of a transform past the end of the batch re-read the batch's
+    // last transform (never stored), and every thread reads bin M of its
+    // transform: the loads are the same for every thread, with no branch
+    // around them.
+    const int64_t tr = first + tb < batch ? tb : batch - 1 - first;
+    const unsigned o8 = (unsigned)(tr * (M + 1) + t) * 8u;
 #pragma unroll
     for (int m = 0; m < RS::EPT; m++)
-        a[m] = live ? *reinterpret_cast<const cf*>(ib + (o8 + (unsigned)(m * TPT * 8))) : cf{0.f, 0.f};
-    aM = (live && t == 0) ? *reinterpret_cast<const cf*>(ib + (o8 + (unsigned)(M * 8))) : cf{0.f, 0.f};
+        a[m] = *reinterpret_cast<const cf*>(ib + (o8 + (unsigned)(m * TPT * 8)));
+    const cf binM = *reinterpret_cast<const cf*>(ib + (unsigned)(tr * (M + 1) + M) * 8u);
+    aM = t == 0 ? binM : cf{0.f, 0.f};
 }
 
 // One transform group, R2C: v holds z (loaded), leaves X in `out`.
 template <int L, int E, int WG, int TW, bool WAVE>
 __device__ __forceinline__ void r2c_group(cf (&v)[1 << E], cf* __restrict__ out, const cf* __restrict__ rows,
-                                          const cf* __restrict__ wn, const TwRegs<L, E>& tws, cf* my, int64_t g,
+                                          const cf (&wv)[1 << E], const TwRegs<L, E>& tws, cf* my, int64_t g,
                                           int64_t batch, int tb, int t, float we, float wi)
 {
     using RS = RealShape<L, E, WG>;
@@ -105,7 +110,7 @@ __device__ __forceinline__ void r2c_group(cf (&v)[1 << E], cf* __restrict__ out,
     const unsigned o8 = (unsigned)(tb * (M + 1) + t) * 8u;
 #pragma unroll
     for (int m = 0; m < EPT; m++) {
-        const cf x = r2c_bin(v[m], zp[m], wn[t + m * TPT]);
+        const cf x = r2c_bin(v[m], zp[m], wv[m]);
         const float s = (m == 0 && t == 0) ? we : wi;
         *reinterpret_cast<cf*>(ob + (o8 + (unsigned)(m * TPT * 8))) = cscale(x, s);
     }
@@ -117,7 +122,7 @@ __device__ __forceinline__ void r2c_group(cf (&v)[1 << E], cf* __restrict__ out,
 // thread 0; leaves x in `out`.
 template <int L, int E, int WG, int TW, bool WAVE>
 __device__ __forceinline__ void c2r_group(cf (&v)[1 << E], cf vM, cf* __restrict__ out, const cf* __restrict__ rows,
-                                          const cf* __restrict__ wn, const TwRegs<L, E>& tws, cf* my, int64_t g,
+                                          const cf (&wv)[1 << E], const TwRegs<L, E>& tws, cf* my, int64_t g,
                                           int64_t batch, int tb, int t, float we, float wi)
 {
     using RS = RealShape<L, E, WG>;
@@ -147,7 +152,7 @@ __device__ __forceinline__ void c2r_group(cf (&v)[1 << E], cf vM, cf* __restrict
 #pragma unroll
     for (int m = 0; m < EPT; m++) {
         const float s = (m == 0 && t == 0) ? we : wi;
-        v[m] = cscale(c2r_pre(v[m], bp[m], wn[t + m * TPT]), s);
+        v[m] = cscale(c2r_pre(v[m], bp[m], wv[m]), s);
     }
     run2<L, E, +1, TW, WAVE>(v, t, rows, tws, my);
     store_group<L, E, RS::TPB>(v, out, g, batch, tb, (unsigned)(tb * M + t) * 8u, 1.f);
@@ -185,37 +190,61 @@ __global__ __launch_bounds__(WG) void k_real(const cf* __restrict__ in, cf* __re
         else
             load_bins<L, E, WG>(v, vM, in, gg, batch, tb, t);
     };
+    // The split's twiddles w[t + m TPT] are read at the top of each group,
+    // before the next group's loads are issued: read after them, their
+    // wait would cover the prefetch as well.
+    cf wv[EPT];
+    auto wload = [&]() {
+#pragma unroll
+        for (int m = 0; m < EPT; m++)
+            wv[m] = wn[t + m * TPT];
+        __builtin_amdgcn_sched_barrier(0);
+    };
     auto process = [&](cf(&v)[EPT], cf vM, int64_t gg) {
         if constexpr (DIR == 0)
-            r2c_group<L, E, WG, TW, WAVE>(v, out, rows, wn, tws, my, gg, batch, tb, t, we, wi);
+            r2c_group<L, E, WG, TW, WAVE>(v, out, rows, wv, tws, my, gg, batch, tb, t, we, wi);
         else
-            c2r_group<L, E, WG, TW, WAVE>(v, vM, out, rows, wn, tws, my, gg, batch, tb, t, we, wi);
+            c2r_group<L, E, WG, TW, WAVE>(v, vM, out, rows, wv, tws, my, gg, batch, tb, t, we, wi);
     };
     load(a, aM, g);
     if constexpr (!PF) {
+        wload();
         process(a, aM, g);  // one group per workgroup (the grid covers every group)
         return;
     }
+    // `left` groups follow the current one.  Inside the loop the next
+    // group's load is unconditional (a conditional one makes the wait
+    // before the current group's first use cover the prefetch too).
     const int64_t stride = gridDim.x;
-    while (true) {
-        int64_t g1 = g + stride;
-        if (g1 < ngroups)
-            load(b, bM, g1);
-        process(a, aM, g);
-        if (g1 >= ngroups)
-            break;
+    auto sync = [&]() {
         if constexpr (RS::XCH)
             lds_sync<WAVE>();  // LDS is reused by the next group
-        g = g1;
-        g1 = g + stride;
-        if (g1 < ngroups)
-            load(a, aM, g1);
+    };
+    int64_t left = (ngroups - 1 - g) / stride;
+    while (left >= 2) {
+        wload();
+        load(b, bM, g + stride);
+        process(a, aM, g);
+        g += stride;
+        sync();
+        wload();
+        load(a, aM, g + stride);
         process(b, bM, g);
-        if (g1 >= ngroups)
-            break;
-        if constexpr (RS::XCH)
-            lds_sync<WAVE>();
-        g = g1;
+        g += stride;
+        sync();
+        left -= 2;
+    }
+    if (left == 1) {
+        wload();
+        load(b, bM, g + stride);
+        process(a, aM, g);
+        g += stride;
+        sync();
+        wload();
+        process(b, bM, g);
+    } else {
+        wload();
+        process(a, aM, g);
     }
 }
 
