@@ -253,6 +253,9 @@ int fft_execute_scaled(fft_plan p, const void *in, const int32_t *in_exp, void *
  * complex convention (dL/dRe x + i dL/dIm x).  One pass: x and w are read
  * once and grad written once.  x and grad must not overlap, nor w/loss
  * overlap grad.  Used by the differentiable loss of the Python binding.
+ * The kernel's shape (elements per thread, workgroup size) comes from its
+ * own tuned table ("loss" lines of MIFFT_TUNE_TABLE), or from the plan's
+ * forced variant for a plan made by fft_plan_create_config.
  */
 int fft_execute_loss_grad(fft_plan p, const void *x, const float *w, void *grad, float *loss, void *stream);
 

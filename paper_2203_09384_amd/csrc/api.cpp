@@ -203,14 +203,36 @@ const Variant kDefaultR32[15] = {
     {4, 1024, 2},  // n=2^15
 };
 
+// Fused loss-gradient kernel (two transforms per group, so its own best
+// shape differs from the plain transform's), per log2 N (index 1..11):
+// the autotuner's pick on MI355X at 2^25 elements (log2 EPT, workgroup
+// size; the kind field is unused).
+const Variant kDefaultLoss[12] = {
+    {0, 0, 0},     // unused
+    {1, 256, 0},   // N=2
+    {2, 64, 0},    // N=4
+    {1, 128, 0},   // N=8
+    {2, 64, 0},    // N=16
+    {2, 256, 0},   // N=32
+    {2, 256, 0},   // N=64
+    {3, 256, 0},   // N=128
+    {3, 256, 0},   // N=256
+    {3, 256, 0},   // N=512
+    {3, 128, 0},   // N=1024
+    {3, 256, 0},   // N=2048
+};
+
 std::once_flag g_tune_once;
 Variant g_tuned_c32[21];
 bool g_have_tuned_c32[21];
 Variant g_tuned_r32[15];
 bool g_have_tuned_r32[15];
+Variant g_tuned_loss[12];
+bool g_have_tuned_loss[12];
 
-// MIFFT_TUNE_TABLE: text lines "c32 <log2n> <ept> <wg> <kind>" and
-// "r32 <log2(n/2)> <ept> <wg> <kind>"; '#' starts a comment.
+// MIFFT_TUNE_TABLE: text lines "c32 <log2n> <ept> <wg> <kind>",
+// "r32 <log2(n/2)> <ept> <wg> <kind>" and "loss <log2n> <ept> <wg>"; '#'
+// starts a comment.
 void load_tune_table()
 {
     const char* path = getenv("MIFFT_TUNE_TABLE");
@@ -237,6 +259,10 @@ void load_tune_table()
             g_tuned_r32[l] = Variant{ilog2(ept), wg, kind};
             g_have_tuned_r32[l] = true;
         }
+        if (dt == "loss" && l >= 1 && l <= 11 && is_pow2(ept) && ept >= 2 && ept <= 16) {
+            g_tuned_loss[l] = Variant{ilog2(ept), wg, 0};
+            g_have_tuned_loss[l] = true;
+        }
     }
 }
 
@@ -249,6 +275,12 @@ Variant choose_c32(int log2n)
             return v;
     }
     return kDefaultC32[log2n];
+}
+
+Variant choose_loss(int log2n)
+{
+    std::call_once(g_tune_once, load_tune_table);
+    return g_have_tuned_loss[log2n] ? g_tuned_loss[log2n] : kDefaultLoss[log2n];
 }
 
 Variant choose_r32(int log2m)
@@ -527,12 +559,14 @@ int make_rows(mifft_plan_s* p)
     return FFT_OK;
 }
 
-// The fused loss-gradient kernel of a batched FP32 plan: the plan's own
-// (EPT, WG) when compiled, else the first compiled one; its twiddle rows are
-// shared with the plan's when the schedules agree.
-int make_loss_grad(mifft_plan_s* p)
+// The fused loss-gradient kernel of a batched FP32 plan: the tuned shape
+// for its length (a plan created with a forced variant: that variant's
+// EPT and WG) when compiled, else the first compiled one; its twiddle rows
+// are shared with the plan's when the schedules agree.
+int make_loss_grad(mifft_plan_s* p, bool forced)
 {
-    const KernelLossGrad* k = find_loss_grad(p->log2n, p->var.log2ept, p->var.wg, p->sign);
+    const Variant want = forced ? p->var : choose_loss(p->log2n);
+    const KernelLossGrad* k = find_loss_grad(p->log2n, want.log2ept, want.wg, p->sign);
     for (int e = 4; e >= 1 && !k; e--)
         for (int wg : {256, 128, 64})
             if (!k)
@@ -818,7 +852,7 @@ fft_plan create_batched(int64_t n, int64_t batch, int sign, int dtype, const Var
         free_plan(p);
         return nullptr;
     }
-    if (dtype == FFT_C32 && n <= 2048 && make_loss_grad(p) != FFT_OK) {
+    if (dtype == FFT_C32 && n <= 2048 && make_loss_grad(p, force != nullptr) != FFT_OK) {
         free_plan(p);
         return nullptr;
     }

@@ -71,6 +71,48 @@ def tune_c32(total: int = 1 << 26, steps: int = 30, warmup: int = 5, log2ns=rang
     return best, record
 
 
+def tune_loss(total: int = 1 << 25, steps: int = 30, warmup: int = 5, log2ns=range(1, 12), log=print):
+    """Fused loss-gradient kernel: every compiled (ept, wg) shape, selected
+    through a plan forced to that shape (any compiled FP32 variant of it),
+    timed on `total` elements."""
+    import torch
+    from . import api, synth
+    from .native import MifftError
+    x = torch.from_numpy(synth.uniform_complex(synth.SEED_AUTOGRAD, (total,), key=(0,))).cuda()
+    w = torch.from_numpy(synth.uniform_weights(synth.SEED_AUTOGRAD, (total,))).cuda()
+    g = torch.empty_like(x)
+    best, record = {}, []
+    for L in log2ns:
+        n = 1 << L
+        b = total // n
+        xs, ws, gs = x[: b * n].view(b, n), w[: b * n].view(b, n), g[: b * n].view(b, n)
+        lv = torch.empty(b, dtype=torch.float32, device=x.device)
+        for ept in EPTS:
+            for wg in (64, 128, 256):
+                p = None
+                for var in (0, 2, 1, 6, 3):
+                    try:
+                        p = api.Plan(n, b, -1, ept=ept, wg=wg, variant=var)
+                        break
+                    except MifftError:
+                        continue
+                if p is None:
+                    continue
+                try:
+                    ms = _time(lambda: p.loss_grad(xs, ws, gs, lv), steps, warmup, torch)
+                except MifftError:
+                    p.close()
+                    continue
+                rec = {"n": n, "ept": ept, "wg": wg, "us": round(ms * 1e3, 2),
+                       "GBps": round(20.0 * b * n / (ms * 1e-3) / 1e9, 1)}
+                record.append(rec)
+                log(f"[tune-loss] {rec}")
+                if L not in best or ms < best[L][2]:
+                    best[L] = (ept, wg, ms)
+                p.close()
+    return best, record
+
+
 REAL_EPTS = (1, 2, 4, 8, 16)
 REAL_VARIANTS = (0, 2, 3, 6, 7)
 
@@ -158,7 +200,8 @@ def tune_ragged(count: int = 4096, iters: int = 300, log=print):
             "us": round(best[2] * 1e3, 2)}, record
 
 
-def write_table(path: str, best_c32: dict, ragged: dict | None = None, best_r32: dict | None = None):
+def write_table(path: str, best_c32: dict, ragged: dict | None = None, best_r32: dict | None = None,
+                best_loss: dict | None = None):
     with open(path, "w") as f:
         f.write("# mifft tuned variants for gfx950 (written by paper_2203_09384_amd.tune)\n")
         for L in sorted(best_c32):
@@ -167,6 +210,9 @@ def write_table(path: str, best_c32: dict, ragged: dict | None = None, best_r32:
         for L in sorted(best_r32 or {}):
             ept, wg, var, ms = best_r32[L]
             f.write(f"r32 {L} {ept} {wg} {var}  # r2c + c2r {ms * 1e3:.2f} us\n")
+        for L in sorted(best_loss or {}):
+            ept, wg, ms = best_loss[L]
+            f.write(f"loss {L} {ept} {wg}  # fused loss + gradient {ms * 1e3:.2f} us\n")
         if ragged:
             for L in sorted(ragged.get("ept", {})):
                 f.write(f"ragged {L} {ragged['ept'][L]}\n")
@@ -183,20 +229,24 @@ def main(argv=None):
     ap.add_argument("--skip-c32", action="store_true")
     ap.add_argument("--skip-ragged", action="store_true")
     ap.add_argument("--skip-real", action="store_true")
+    ap.add_argument("--skip-loss", action="store_true")
     args = ap.parse_args(argv)
     log = lambda m: print(m, file=sys.stderr, flush=True)
     best, rec = ({}, []) if args.skip_c32 else tune_c32(1 << args.total_log2, args.steps, log=log)
     rbest, rrec = (None, []) if args.skip_ragged else tune_ragged(log=log)
     real_best, real_rec = ({}, []) if args.skip_real else tune_real(1 << (args.total_log2 + 1), args.steps,
                                                                       log=log)
-    write_table(args.out, best, rbest, real_best)
+    loss_best, loss_rec = ({}, []) if args.skip_loss else tune_loss(1 << (args.total_log2 - 1), args.steps, log=log)
+    write_table(args.out, best, rbest, real_best, loss_best)
     if args.json:
         with open(args.json, "w") as f:
             json.dump({"c32": rec, "best": {L: best[L][:3] for L in best}, "ragged": rrec,
                        "ragged_best": rbest, "real": real_rec,
-                       "real_best": {L: real_best[L][:3] for L in real_best}}, f, indent=1)
+                       "real_best": {L: real_best[L][:3] for L in real_best}, "loss": loss_rec,
+                       "loss_best": {L: loss_best[L][:2] for L in loss_best}}, f, indent=1)
     print(json.dumps({"c32": {L: best[L][:3] for L in best}, "ragged": rbest,
-                      "r32": {L: real_best[L][:3] for L in real_best}}))
+                      "r32": {L: real_best[L][:3] for L in real_best},
+                      "loss": {L: loss_best[L][:2] for L in loss_best}}))
 
 
 if __name__ == "__main__":
