@@ -232,6 +232,18 @@ def bench_ragged(api, synth, torch, dev, iters):
     with torch.cuda.graph(g2):
         per_length()
     t_pl_graph = time_launches(g2.replay, iters, 50, torch)
+    # the same two paths with REPS batches captured in one graph: per-batch
+    # GPU time once the graph launch itself is amortised
+    reps = 20
+    g3, g4 = torch.cuda.CUDAGraph(), torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g3):
+        for _ in range(reps):
+            rp.execute(x, y)
+    with torch.cuda.graph(g4):
+        for _ in range(reps):
+            per_length()
+    t_graph_rep = time_launches(g3.replay, max(10, iters // reps), 5, torch) / reps
+    t_pl_graph_rep = time_launches(g4.replay, max(10, iters // reps), 5, torch) / reps
     flops = float(np.sum(5.0 * lengths * np.log2(lengths)))
     bytes_ = 16.0 * total
     us = lambda ms: round(ms * 1e3, 2)
@@ -243,6 +255,9 @@ def bench_ragged(api, synth, torch, dev, iters):
         "launches_per_length_path": len(groups),
         "speedup_vs_per_length_eager": round(t_pl / t_eager, 2),
         "speedup_graph_vs_per_length_graph": round(t_pl_graph / t_graph, 2),
+        "graph_of_20_batches": {"persistent_us_per_batch": us(t_graph_rep),
+                                "per_length_us_per_batch": us(t_pl_graph_rep),
+                                "speedup": round(t_pl_graph_rep / t_graph_rep, 2)},
         "persistent_graph_GFLOPs": round(flops / (t_graph * 1e-3) / 1e9, 1),
         "persistent_graph_effective_GBps": round(bytes_ / (t_graph * 1e-3) / 1e9, 1),
         "note": "about 30 MB moved: cache-resident, so effective GB/s is not an HBM figure",
