@@ -173,8 +173,8 @@ const Variant kDefaultC32[21] = {
     {3, 64, 6},    // N=128
     {3, 64, 5},    // N=256
     {3, 64, 6},    // N=512
-    {3, 128, 2},   // N=1024
-    {4, 256, 3},   // N=2048  persistent, next-group prefetch
+    {4, 64, 3},    // N=1024  persistent, next-group prefetch
+    {4, 128, 3},   // N=2048  persistent, next-group prefetch
     {3, 512, 3},   // N=2^12  one transform per workgroup
     {4, 512, 3},   // N=2^13
     {4, 1024, 2},  // N=2^14  135 KiB LDS

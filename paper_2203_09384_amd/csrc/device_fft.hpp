@@ -537,6 +537,28 @@ __device__ __forceinline__ void load_group(cf (&v)[1 << E], const cf* __restrict
         v[m] = ld_data<NT>(gb + (off + (unsigned)(m * TPT * 8)));
 }
 
+// Elements m in [K EPT/NK, (K+1) EPT/NK) of a group load (slice K of NK),
+// with the same threads-past-the-end rule as load_group.
+template <int L, int E, int TPB, int K, int NK>
+__device__ __forceinline__ void load_group_part(cf (&v)[1 << E], const cf* __restrict__ in, int64_t g,
+                                                int64_t batch, int tb, unsigned toff8)
+{
+    using SC = Sched<L, E>;
+    constexpr int N = SC::N, EPT = SC::EPT, TPT = SC::TPT;
+    constexpr bool NT = stream_nt<N, TPT>();
+    constexpr int M0 = K * EPT / NK, M1 = (K + 1) * EPT / NK;
+    const int64_t first = g * TPB;
+    const char* gb = reinterpret_cast<const char*>(in + first * N);
+    unsigned off = toff8;
+    if constexpr (TPB > 1) {
+        const int64_t last = batch - 1 - first;
+        off = first + tb < batch ? toff8 : (unsigned)(last * N + (toff8 / 8u) % (unsigned)TPT) * 8u;
+    }
+#pragma unroll
+    for (int m = M0; m < M1; m++)
+        v[m] = ld_data<NT>(gb + (off + (unsigned)(m * TPT * 8)));
+}
+
 template <int L, int E, int TPB>
 __device__ __forceinline__ void store_group(const cf (&v)[1 << E], cf* __restrict__ out, int64_t g, int64_t batch,
                                             int tb, unsigned toff8, float scale)
@@ -589,6 +611,37 @@ __device__ __forceinline__ void run2(cf (&v)[1 << E], int t, const cf* __restric
             lds_sync<WAVE>();  // all reads of the previous exchange are done
         exchange2<L, E, P, WAVE>(v, t, lds);
         run2<L, E, S, TW, WAVE, P + 1>(v, t, rows, tws, lds);
+    }
+}
+
+// run2 that also loads the next group (transform group `gn` of `in`) into
+// `nx`, one slice before each pass, so a workgroup's loads reach HBM spread
+// over its passes rather than in one burst per group.
+template <int L, int E, int S, int TW, bool WAVE, int TPB, int P = 0>
+__device__ __forceinline__ void run2_prefetch(cf (&v)[1 << E], int t, const cf* __restrict__ rows,
+                                              const TwRegs<L, E>& tws, cf* lds, cf (&nx)[1 << E],
+                                              const cf* __restrict__ in, int64_t gn, int64_t batch, int tb,
+                                              unsigned toff8)
+{
+    using SC = Sched<L, E>;
+    constexpr int EPT = SC::EPT;
+    load_group_part<L, E, TPB, P, SC::NP>(nx, in, gn, batch, tb, toff8);
+    if constexpr (SC::log2ns(P) > 0) {
+        if constexpr (TW == 0) {
+            pass_compute2<L, E, S, P>(v, tws[P]);
+        } else {
+            cf w[EPT];
+            load_row<L, E, S, P>(w, rows, t);
+            pass_compute2<L, E, S, P>(v, w);
+        }
+    } else {
+        pass_compute2<L, E, S, P>(v, tws[0]);
+    }
+    if constexpr (P + 1 < SC::NP) {
+        if constexpr (P > 0)
+            lds_sync<WAVE>();  // all reads of the previous exchange are done
+        exchange2<L, E, P, WAVE>(v, t, lds);
+        run2_prefetch<L, E, S, TW, WAVE, TPB, P + 1>(v, t, rows, tws, lds, nx, in, gn, batch, tb, toff8);
     }
 }
 

@@ -145,28 +145,26 @@ __global__ __launch_bounds__(WG) void k_fft_c32_v2(const cf* __restrict__ in, cf
     }
     // Groups g, g + stride, ... ; `left` more after the current one.  The
     // loop body issues the next group's loads unconditionally (two groups
-    // per trip, one per register set), and the last one or two groups run
-    // after it.  A prefetch under a condition would let the path without
-    // it meet the path with it before the current group is used, and the
-    // wait placed there would then cover most of the prefetched loads.
+    // per trip, one per register set), a slice before each pass, and the
+    // last one or two groups run after it.  A prefetch under a condition
+    // would let the path without it meet the path with it before the
+    // current group is used, and the wait placed there would then cover
+    // most of the prefetched loads.
     const int64_t stride = gridDim.x;
     int64_t left = (ngroups - 1 - g) / stride;
     while (left >= 2) {
-        load_group<L, E, TPB>(b, in, g + stride, batch, tb, toff8);
-        run2<L, E, S, TW, WAVE>(a, t, rows, tws, my);
+        run2_prefetch<L, E, S, TW, WAVE, TPB>(a, t, rows, tws, my, b, in, g + stride, batch, tb, toff8);
         store_group<L, E, TPB>(a, out, g, batch, tb, toff8, scale);
         g += stride;
         lds_sync<WAVE>();  // LDS is reused by the next group
-        load_group<L, E, TPB>(a, in, g + stride, batch, tb, toff8);
-        run2<L, E, S, TW, WAVE>(b, t, rows, tws, my);
+        run2_prefetch<L, E, S, TW, WAVE, TPB>(b, t, rows, tws, my, a, in, g + stride, batch, tb, toff8);
         store_group<L, E, TPB>(b, out, g, batch, tb, toff8, scale);
         g += stride;
         lds_sync<WAVE>();
         left -= 2;
     }
     if (left == 1) {
-        load_group<L, E, TPB>(b, in, g + stride, batch, tb, toff8);
-        run2<L, E, S, TW, WAVE>(a, t, rows, tws, my);
+        run2_prefetch<L, E, S, TW, WAVE, TPB>(a, t, rows, tws, my, b, in, g + stride, batch, tb, toff8);
         store_group<L, E, TPB>(a, out, g, batch, tb, toff8, scale);
         g += stride;
         lds_sync<WAVE>();
