@@ -625,16 +625,24 @@ __device__ __forceinline__ void run2_prefetch(cf (&v)[1 << E], int t, const cf* 
 {
     using SC = Sched<L, E>;
     constexpr int EPT = SC::EPT;
-    load_group_part<L, E, TPB, P, SC::NP>(nx, in, gn, batch, tb, toff8);
     if constexpr (SC::log2ns(P) > 0) {
         if constexpr (TW == 0) {
+            load_group_part<L, E, TPB, P, SC::NP>(nx, in, gn, batch, tb, toff8);
             pass_compute2<L, E, S, P>(v, tws[P]);
         } else {
+            // The pass's twiddle row is read before the slice (read after
+            // it, its wait would cover the slice as well), and the
+            // scheduling barrier keeps both ahead of the pass's arithmetic.
             cf w[EPT];
             load_row<L, E, S, P>(w, rows, t);
+            load_group_part<L, E, TPB, P, SC::NP>(nx, in, gn, batch, tb, toff8);
+            __builtin_amdgcn_sched_barrier(0);
             pass_compute2<L, E, S, P>(v, w);
         }
     } else {
+        load_group_part<L, E, TPB, P, SC::NP>(nx, in, gn, batch, tb, toff8);
+        if constexpr (TW != 0)
+            __builtin_amdgcn_sched_barrier(0);
         pass_compute2<L, E, S, P>(v, tws[0]);
     }
     if constexpr (P + 1 < SC::NP) {

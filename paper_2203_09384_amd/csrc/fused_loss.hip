@@ -28,14 +28,21 @@ __device__ __forceinline__ void load_weights(float (&wv)[1 << E], const float* _
     constexpr bool NT = TPT >= 32;
     const int64_t first = g * TPB;
     const char* gb = reinterpret_cast<const char*>(w + first * N);
-    const bool live = first + tb < batch;
+    unsigned off = toff4;
+    if constexpr (TPB > 1) {
+        // threads of a transform past the end of the batch read the last
+        // transform's weights (their loss and gradient are not stored), so
+        // that every thread issues the same loads with no branch around them
+        const int64_t last = batch - 1 - first;
+        off = first + tb < batch ? toff4 : (unsigned)(last * N + (toff4 / 4u) % (unsigned)TPT) * 4u;
+    }
 #pragma unroll
     for (int m = 0; m < EPT; m++) {
-        const float* p = reinterpret_cast<const float*>(gb + (toff4 + (unsigned)(m * TPT * 4)));
+        const float* p = reinterpret_cast<const float*>(gb + (off + (unsigned)(m * TPT * 4)));
         if constexpr (NT)
-            wv[m] = live ? __builtin_nontemporal_load(p) : 0.f;
+            wv[m] = __builtin_nontemporal_load(p);
         else
-            wv[m] = live ? *p : 0.f;
+            wv[m] = *p;
     }
 }
 
@@ -85,8 +92,36 @@ __device__ __forceinline__ void transform_passes(cf (&v)[1 << E], int t, const c
         run2<L, E, S, 1, (SC::TPT <= 64)>(v, t, rows, tws, lds);
 }
 
-template <int L, int E, int WG, int S>
-__device__ __forceinline__ void loss_grad_group(cf (&v)[1 << E], const float* __restrict__ w,
+// The forward passes of a group, loading the next group `gn` into `nx` a
+// slice per pass (PF), or not at all.
+template <int L, int E, int S, int TPB, bool PF>
+__device__ __forceinline__ void forward_passes(cf (&v)[1 << E], int t, const cf* __restrict__ rows, cf* lds,
+                                               cf (&nx)[1 << E], const cf* __restrict__ x, int64_t gn,
+                                               int64_t batch, int tb, unsigned toff8)
+{
+    using SC = Sched<L, E>;
+    if constexpr (!PF) {
+        transform_passes<L, E, S>(v, t, rows, lds);
+    } else if constexpr (SC::TPT == 1) {
+        load_group<L, E, TPB>(nx, x, gn, batch, tb, toff8);
+        transform_passes<L, E, S>(v, t, rows, lds);
+    } else {
+        TwRegs<L, E> tws;
+#pragma unroll
+        for (int p = 0; p < SC::NP; p++)
+#pragma unroll
+            for (int r = 0; r < SC::EPT; r++)
+                tws[p][r] = cf{1.f, 0.f};
+        run2_prefetch<L, E, S, 1, (SC::TPT <= 64), TPB>(v, t, rows, tws, lds, nx, x, gn, batch, tb, toff8);
+    }
+}
+
+// One group: loss and gradient of the transforms in `v`.  With PF the
+// next group `gn` is loaded into `nx` during the forward passes; the
+// weights are read first, so that their wait does not cover those loads.
+template <int L, int E, int WG, int S, bool PF>
+__device__ __forceinline__ void loss_grad_group(cf (&v)[1 << E], cf (&nx)[1 << E], const cf* __restrict__ x,
+                                                int64_t gn, const float* __restrict__ w,
                                                 cf* __restrict__ grad, float* __restrict__ loss,
                                                 const cf* __restrict__ rows, int64_t g, int64_t batch, int tb,
                                                 int t, unsigned toff8, float scale, cf* lds, float* red)
@@ -96,7 +131,7 @@ __device__ __forceinline__ void loss_grad_group(cf (&v)[1 << E], const float* __
     constexpr bool WAVE = TPT <= 64;
     float wv[EPT];
     load_weights<L, E, TPB>(wv, w, g, batch, tb, toff8 / 2);
-    transform_passes<L, E, S>(v, t, rows, lds);  // X = A x (before its scale)
+    forward_passes<L, E, S, TPB, PF>(v, t, rows, lds, nx, x, gn, batch, tb, toff8);  // X = A x (before its scale)
     float part = 0.f;
 #pragma unroll
     for (int m = 0; m < EPT; m++) {
@@ -139,25 +174,25 @@ __global__ __launch_bounds__(WG) void k_fft_loss_grad(const cf* __restrict__ x, 
     load_group<L, E, TPB>(a, x, g, batch, tb, toff8);
     // `left` groups follow the current one.  Inside the loop the next
     // group's load is unconditional (a conditional one makes the wait
-    // before the current group's first use cover the prefetch too).
+    // before the current group's first use cover the prefetch too) and
+    // spread over the forward passes.
     int64_t left = (ngroups - 1 - g) / stride;
+#define LG(PF, V, NX, GN) loss_grad_group<L, E, WG, S, PF>(V, NX, x, GN, w, grad, loss, rows, g, batch, tb, t, toff8, scale, my, red)
     while (left >= 2) {
-        load_group<L, E, TPB>(b, x, g + stride, batch, tb, toff8);
-        loss_grad_group<L, E, WG, S>(a, w, grad, loss, rows, g, batch, tb, t, toff8, scale, my, red);
+        LG(true, a, b, g + stride);
         g += stride;
-        load_group<L, E, TPB>(a, x, g + stride, batch, tb, toff8);
-        loss_grad_group<L, E, WG, S>(b, w, grad, loss, rows, g, batch, tb, t, toff8, scale, my, red);
+        LG(true, b, a, g + stride);
         g += stride;
         left -= 2;
     }
     if (left == 1) {
-        load_group<L, E, TPB>(b, x, g + stride, batch, tb, toff8);
-        loss_grad_group<L, E, WG, S>(a, w, grad, loss, rows, g, batch, tb, t, toff8, scale, my, red);
+        LG(true, a, b, g + stride);
         g += stride;
-        loss_grad_group<L, E, WG, S>(b, w, grad, loss, rows, g, batch, tb, t, toff8, scale, my, red);
+        LG(false, b, a, 0);
     } else {
-        loss_grad_group<L, E, WG, S>(a, w, grad, loss, rows, g, batch, tb, t, toff8, scale, my, red);
+        LG(false, a, b, 0);
     }
+#undef LG
 }
 
 template <int L, int E, int WG, int S>
