@@ -209,17 +209,17 @@ const Variant kDefaultR32[15] = {
 // size; the kind field is unused).
 const Variant kDefaultLoss[12] = {
     {0, 0, 0},     // unused
-    {1, 256, 0},   // N=2
+    {1, 128, 0},   // N=2
     {2, 64, 0},    // N=4
-    {1, 128, 0},   // N=8
+    {3, 256, 0},   // N=8
     {2, 64, 0},    // N=16
     {2, 256, 0},   // N=32
     {2, 256, 0},   // N=64
     {3, 256, 0},   // N=128
-    {3, 256, 0},   // N=256
+    {4, 64, 0},    // N=256
     {3, 256, 0},   // N=512
-    {3, 128, 0},   // N=1024
-    {3, 256, 0},   // N=2048
+    {4, 256, 0},   // N=1024
+    {4, 128, 0},   // N=2048
 };
 
 std::once_flag g_tune_once;
