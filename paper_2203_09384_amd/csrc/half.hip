@@ -143,16 +143,26 @@ struct HalfCtx {
     int tid, lane, wave;
 };
 
+// Two floats to one word of two halves (a low, b high), each rounded to
+// nearest even: one packed convert (v_cvt_pk_f16_f32 / v_cvt_pk_bf16_f32).
+typedef float v2f32 __attribute__((ext_vector_type(2)));
+typedef _Float16 v2f16 __attribute__((ext_vector_type(2)));
+typedef __bf16 v2bf16 __attribute__((ext_vector_type(2)));
+
 __device__ __forceinline__ uint32_t pack_f16(float a, float b)
 {
-    return (uint32_t)__builtin_bit_cast(uint16_t, (_Float16)a) |
-           ((uint32_t)__builtin_bit_cast(uint16_t, (_Float16)b) << 16);
+    const v2f32 f = {a, b};
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(f, v2f16));
 }
 
 template <bool BF>
 __device__ __forceinline__ uint32_t pack_store(float a, float b)
 {
-    return (uint32_t)from_f32<BF>(a) | ((uint32_t)from_f32<BF>(b) << 16);
+    const v2f32 f = {a, b};
+    if constexpr (BF)
+        return __builtin_bit_cast(uint32_t, __builtin_convertvector(f, v2bf16));
+    else
+        return __builtin_bit_cast(uint32_t, __builtin_convertvector(f, v2f16));
 }
 
 // An MFMA operand from 8 packed words: this lane's half (re or im) of each.
@@ -268,13 +278,23 @@ __device__ __forceinline__ void half_transform(const HalfCtx& c, uint32_t (&cur)
         yre[gg] = mfma(c.f_re, bo, z);
         yim[gg] = mfma(c.f_im, bo, z);
     }
-    const float osc = out_exp ? 1.0f : ldexpf(1.0f, e_out);
+    if (out_exp) {  // block floating point: the exponent carries the scale
 #pragma unroll
-    for (int gg = 0; gg < 2; gg++) {
-        uint32_t* wc = X + c.oWC[gg];
+        for (int gg = 0; gg < 2; gg++) {
+            uint32_t* wc = X + c.oWC[gg];
 #pragma unroll
-        for (int i = 0; i < 4; i++)
-            wc[dWC[i]] = pack_store<BF>(yre[gg][i] * osc, yim[gg][i] * osc);
+            for (int i = 0; i < 4; i++)
+                wc[dWC[i]] = pack_store<BF>(yre[gg][i], yim[gg][i]);
+        }
+    } else {  // unit scale
+        const float osc = ldexpf(1.0f, e_out);
+#pragma unroll
+        for (int gg = 0; gg < 2; gg++) {
+            uint32_t* wc = X + c.oWC[gg];
+#pragma unroll
+            for (int i = 0; i < 4; i++)
+                wc[dWC[i]] = pack_store<BF>(yre[gg][i] * osc, yim[gg][i] * osc);
+        }
     }
     __syncthreads();
 
