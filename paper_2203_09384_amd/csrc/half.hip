@@ -177,6 +177,23 @@ __device__ __forceinline__ Op8 gather_op(const uint32_t (&w)[8], uint32_t sel)
     return o;
 }
 
+// Maximum over the wavefront of a non-negative float, in every lane.
+// Non-negative floats order like their bit patterns, so the reduction runs
+// on integers with DPP row shifts (a prefix maximum within each row of 16
+// lanes), then row broadcasts 15 and 31, leaving the maximum in lane 63.
+// Lanes without a DPP source read 0, the identity here.
+__device__ __forceinline__ float wave_max_nonneg(float x)
+{
+    int v = __builtin_bit_cast(int, x);
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, false));  // row_shr:1
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, false));  // row_shr:2
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, false));  // row_shr:4
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, false));  // row_shr:8
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false));  // row_bcast:15 -> rows 1, 3
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false));  // row_bcast:31 -> rows 2, 3
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(v, 63));
+}
+
 __device__ __forceinline__ void load_raw(uint32_t (&u)[8], const uint32_t* __restrict__ in, int64_t b, int tid)
 {
     const uint32_t* src = in + b * HN;
@@ -213,9 +230,7 @@ __device__ __forceinline__ void half_transform(const HalfCtx& c, uint32_t (&cur)
 #pragma unroll
     for (int m = 0; m < 8; m++)
         mx = fmaxf(mx, fmaxf(fabsf(v[m].x), fabsf(v[m].y)));
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1)
-        mx = fmaxf(mx, __shfl_xor(mx, off));
+    mx = wave_max_nonneg(mx);
     if (c.lane == 0)
         red[c.wave] = mx;
     dft8<S>(v);
