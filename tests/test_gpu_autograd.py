@@ -132,6 +132,33 @@ def test_fused_loss_grad_vs_oracle(n, sign):
     assert per_transform_relerr(grad.cpu().numpy(), ref_grad) <= TOL
 
 
+@pytest.mark.parametrize("n", [8, 64, 256, 1024, 2048])
+def test_fused_loss_persistent_tails(n):
+    """Batches of 2^23 elements plus three transforms: every persistent
+    workgroup walks several groups (the loop body, the one- and two-group
+    tails, the next group loaded during the forward passes) and the last
+    group is partly filled.  Every transform's loss, and the gradient of
+    sampled transforms (first, last, random), against the oracle."""
+    batch = (1 << 23) // n + 3
+    x = synth.uniform_complex(43, (batch, n), key=(n,))
+    w = synth.uniform_weights(43, (batch, n), key=(n, 1))
+    plan = api.Plan(n, batch, -1)
+    print(f"[case] fused tails n={n} batch={batch}", flush=True)
+    loss, grad = plan.loss_grad(to_gpu(x), to_gpu(w))
+    torch.cuda.synchronize()
+    loss, grad = loss.cpu().numpy(), grad.cpu().numpy()
+    ref_loss = np.empty(batch)
+    step = (1 << 20) // n  # 2^20 elements per oracle call
+    for c in range(0, batch, step):
+        y = oracle.forward(x[c:c + step].astype(np.complex128))
+        ref_loss[c:c + step] = np.sum(w[c:c + step] * np.abs(y) ** 2, axis=-1)
+    assert np.max(np.abs(loss - ref_loss) / ref_loss) <= TOL
+    rng = np.random.default_rng(n)
+    idx = np.unique(np.concatenate([[0, 1, batch - 2, batch - 1], rng.integers(0, batch, 60)]))
+    _, g_ref = oracle.loss_grad(x[idx].astype(np.complex128), w[idx].astype(np.float64))
+    assert per_transform_relerr(grad[idx], g_ref) <= TOL
+
+
 def test_fused_loss_full_size_and_autograd():
     """The differentiable workload (N=2048, batch 16384) through the fused
     autograd function, against the oracle on sampled transforms and against
