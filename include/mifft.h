@@ -106,7 +106,9 @@ typedef struct {
                            5..8 as 1..4 with wavefront-local exchanges
                            (transforms of at most 64 threads); 9 the
                            four-step split (n > 2048); 10 the single-pass
-                           2D kernel (multidimensional plans)             */
+                           2D kernel (multidimensional plans); 11 one
+                           transform per thread (n <= 16) with the block
+                           staged through LDS in 16-byte vectors       */
     int ept_by_log2n[12]; /* ragged: elements per thread used for length 2^L */
     int rank;           /* multidimensional plans: number of axes (else 0)   */
     int64_t dims[3];    /* multidimensional plans: axis lengths, first to last */
@@ -146,7 +148,7 @@ fft_plan fft_plan_create(int64_t n, int64_t batch, int sign, int dtype);
 /*
  * As fft_plan_create, forcing the kernel variant: `ept` complex elements
  * per thread (2, 4, 8 or 16), `wg` threads per workgroup (64 .. 1024) and
- * the kernel family `variant` (0..8, see fft_plan_desc.variant; 9 = the
+ * the kernel family `variant` (0..8 or 11, see fft_plan_desc.variant; 9 = the
  * four-step split, n > 2048).  FFT_C32 and FFT_R32 only; for FFT_R32 ept
  * and wg describe the half-length transform (ept 1..16) and variant is 0
  * (a whole half-length transform per thread), 2, 3, 6 or 7.  Used by the

@@ -164,10 +164,10 @@ struct Variant {
 // MI355X at 2^26 elements per launch (log2 EPT, workgroup size, variant).
 const Variant kDefaultC32[21] = {
     {0, 0, 0},     // unused
-    {1, 64, 0},    // N=2     one thread per transform
-    {2, 128, 0},   // N=4
-    {3, 256, 0},   // N=8     one thread per transform
-    {2, 256, 2},   // N=16
+    {1, 64, 11},   // N=2     one thread per transform, block staged through LDS
+    {2, 128, 11},  // N=4
+    {3, 64, 11},   // N=8
+    {4, 128, 11},  // N=16
     {2, 128, 6},   // N=32
     {2, 128, 5},   // N=64    wavefront-local exchanges
     {3, 64, 6},    // N=128
@@ -1191,8 +1191,8 @@ fft_plan fft_plan_create_config(int64_t n, int64_t batch, int sign, int dtype, i
         return nullptr;
     }
     if (variant != 9 && (!is_pow2(ept) || ept < 2 || ept > 16 || !is_pow2(wg) || wg < 64 || wg > 1024 ||
-                         variant < 0 || variant > 8)) {
-        set_err(FFT_EINVAL_CONFIG, "ept=%d must be 2..16, wg=%d 64..1024 (powers of two), variant=%d 0..9",
+                         variant < 0 || (variant > 8 && variant != 11))) {
+        set_err(FFT_EINVAL_CONFIG, "ept=%d must be 2..16, wg=%d 64..1024 (powers of two), variant=%d 0..9 or 11",
                 ept, wg, variant);
         return nullptr;
     }

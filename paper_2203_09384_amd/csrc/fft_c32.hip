@@ -176,6 +176,84 @@ __global__ __launch_bounds__(WG) void k_fft_c32_v2(const cf* __restrict__ in, cf
     }
 }
 
+// ---------------------------------------------------------------- staged
+// Short lengths (N <= 16), one transform per thread, with the workgroup's
+// block of WG transforms moved between HBM and LDS in 16-byte vectors at
+// consecutive lane addresses: each wave instruction covers 1 KiB of
+// contiguous input or output.  In LDS each transform is a row of N/2
+// vectors, padded by one vector when N >= 4 so that the per-thread row
+// accesses hit distinct banks.  A thread reads its row, transforms it in
+// registers, writes its row back (no other thread touches it), and the
+// block leaves LDS the way it came in.
+template <int L, int WG, int S>
+__global__ __launch_bounds__(WG) void k_fft_c32_st(const cf* __restrict__ in, cf* __restrict__ out,
+                                                   const cf* __restrict__ tw, int64_t batch, float scale)
+{
+    constexpr int N = 1 << L, H = N / 2, ROW = H + (H >= 2 ? 1 : 0);
+    static_assert(L >= 1 && L <= 4, "one transform per thread: N = 2..16");
+    __shared__ v4f lds[WG * ROW];
+    const int tid = threadIdx.x;
+    const int64_t first = (int64_t)blockIdx.x * WG;
+    const int64_t count = batch - first < WG ? batch - first : WG;  // transforms of this workgroup
+    const int nv = (int)count * H;                                   // its 16-byte vectors
+    const v4f* src = reinterpret_cast<const v4f*>(in + first * N);
+    v4f* dst = reinterpret_cast<v4f*>(out + first * N);
+    v4f q[H];
+    if (count == WG) {  // every load of the block issued before any is used
+#pragma unroll
+        for (int k = 0; k < H; k++)
+            q[k] = __builtin_nontemporal_load(src + tid + WG * k);
+    } else {
+#pragma unroll
+        for (int k = 0; k < H; k++)
+            q[k] = tid + WG * k < nv ? __builtin_nontemporal_load(src + tid + WG * k) : v4f{0.f, 0.f, 0.f, 0.f};
+    }
+#pragma unroll
+    for (int k = 0; k < H; k++) {
+        const int i = tid + WG * k;
+        lds[(i / H) * ROW + i % H] = q[k];
+    }
+    __syncthreads();
+    cf v[N];
+#pragma unroll
+    for (int j = 0; j < H; j++) {
+        const v4f q = lds[tid * ROW + j];
+        v[2 * j] = cf{q.x, q.y};
+        v[2 * j + 1] = cf{q.z, q.w};
+    }
+    pass_compute<L, L, S, 0>(v, 0, tw);
+#pragma unroll
+    for (int j = 0; j < H; j++)
+        lds[tid * ROW + j] = v4f{v[2 * j].x * scale, v[2 * j].y * scale, v[2 * j + 1].x * scale,
+                                 v[2 * j + 1].y * scale};
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < H; k++) {
+        const int i = tid + WG * k;
+        q[k] = lds[(i / H) * ROW + i % H];
+    }
+    if (count == WG) {
+#pragma unroll
+        for (int k = 0; k < H; k++)
+            __builtin_nontemporal_store(q[k], dst + tid + WG * k);
+    } else {
+#pragma unroll
+        for (int k = 0; k < H; k++)
+            if (tid + WG * k < nv)
+                __builtin_nontemporal_store(q[k], dst + tid + WG * k);
+    }
+}
+
+template <int L, int WG, int S>
+hipError_t launch_c32_st(const void* in, void* out, const void* tw, const void*, int64_t batch, float scale,
+                         int64_t, hipStream_t stream)
+{
+    const int64_t grid = (batch + WG - 1) / WG;
+    hipLaunchKernelGGL((k_fft_c32_st<L, WG, S>), dim3((unsigned)grid), dim3(WG), 0, stream,
+                       static_cast<const cf*>(in), static_cast<cf*>(out), static_cast<const cf*>(tw), batch, scale);
+    return hipGetLastError();
+}
+
 template <int LOG2N, int LOG2EPT, int WG, int S>
 hipError_t launch_c32(const void* in, void* out, const void* tw, const void*, int64_t batch, float scale,
                       int64_t, hipStream_t stream)
@@ -275,11 +353,23 @@ void add_v2()
     }
 }
 
+// kind 11: the staged one-transform-per-thread kernel, N = 2..16, EPT = N,
+// 64..256 threads
+template <int LOG2N, int LOG2EPT, int WG, int S>
+void add_st()
+{
+    if constexpr (LOG2N >= 1 && LOG2N <= 4 && LOG2EPT == LOG2N && WG <= 256)
+        register_c32(KernelC32{LOG2N, LOG2EPT, WG, S, 11, &launch_c32_st<LOG2N, WG, S>, nullptr, 0,
+                               WG * ((1 << LOG2N) / 2 + ((1 << LOG2N) >= 4 ? 1 : 0)) * 16});
+}
+
 template <int LOG2N, int LOG2EPT, int WG>
 void add_signs()
 {
     add_one<LOG2N, LOG2EPT, WG, -1>();
     add_one<LOG2N, LOG2EPT, WG, +1>();
+    add_st<LOG2N, LOG2EPT, WG, -1>();
+    add_st<LOG2N, LOG2EPT, WG, +1>();
     // kinds: 1 = TW0 PF0, 2 = TW1 PF0, 3 = TW0 PF1, 4 = TW1 PF1; 5..8 the same
     // with wave-local exchanges (transforms of at most 64 threads)
     add_v2<LOG2N, LOG2EPT, WG, -1, 0, 0>();
