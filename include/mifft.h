@@ -108,7 +108,9 @@ typedef struct {
                            four-step split (n > 2048); 10 the single-pass
                            2D kernel (multidimensional plans); 11 one
                            transform per thread (n <= 16) with the block
-                           staged through LDS in 16-byte vectors       */
+                           staged through LDS in 16-byte vectors; 12 the
+                           same staging for n = 32, 64 (several threads
+                           per transform, wavefront-local exchanges)   */
     int ept_by_log2n[12]; /* ragged: elements per thread used for length 2^L */
     int rank;           /* multidimensional plans: number of axes (else 0)   */
     int64_t dims[3];    /* multidimensional plans: axis lengths, first to last */
@@ -148,7 +150,7 @@ fft_plan fft_plan_create(int64_t n, int64_t batch, int sign, int dtype);
 /*
  * As fft_plan_create, forcing the kernel variant: `ept` complex elements
  * per thread (2, 4, 8 or 16), `wg` threads per workgroup (64 .. 1024) and
- * the kernel family `variant` (0..8 or 11, see fft_plan_desc.variant; 9 = the
+ * the kernel family `variant` (0..8, 11 or 12, see fft_plan_desc.variant; 9 = the
  * four-step split, n > 2048).  FFT_C32 and FFT_R32 only; for FFT_R32 ept
  * and wg describe the half-length transform (ept 1..16) and variant is 0
  * (a whole half-length transform per thread), 2, 3, 6 or 7.  Used by the

@@ -168,11 +168,11 @@ const Variant kDefaultC32[21] = {
     {2, 128, 11},  // N=4
     {3, 64, 11},   // N=8
     {4, 128, 11},  // N=16
-    {2, 128, 6},   // N=32
-    {2, 128, 5},   // N=64    wavefront-local exchanges
-    {3, 64, 6},    // N=128
-    {3, 64, 5},    // N=256
-    {3, 64, 6},    // N=512
+    {3, 64, 12},   // N=32    several threads per transform, block staged through LDS
+    {3, 256, 12},  // N=64
+    {3, 64, 12},   // N=128
+    {4, 128, 12},  // N=256
+    {3, 64, 12},   // N=512
     {4, 64, 3},    // N=1024  persistent, next-group prefetch
     {4, 128, 3},   // N=2048  persistent, next-group prefetch
     {3, 512, 3},   // N=2^12  one transform per workgroup
@@ -1191,8 +1191,8 @@ fft_plan fft_plan_create_config(int64_t n, int64_t batch, int sign, int dtype, i
         return nullptr;
     }
     if (variant != 9 && (!is_pow2(ept) || ept < 2 || ept > 16 || !is_pow2(wg) || wg < 64 || wg > 1024 ||
-                         variant < 0 || (variant > 8 && variant != 11))) {
-        set_err(FFT_EINVAL_CONFIG, "ept=%d must be 2..16, wg=%d 64..1024 (powers of two), variant=%d 0..9 or 11",
+                         variant < 0 || (variant > 8 && variant != 11 && variant != 12))) {
+        set_err(FFT_EINVAL_CONFIG, "ept=%d must be 2..16, wg=%d 64..1024 (powers of two), variant=%d 0..9, 11 or 12",
                 ept, wg, variant);
         return nullptr;
     }

@@ -244,6 +244,90 @@ __global__ __launch_bounds__(WG) void k_fft_c32_st(const cf* __restrict__ in, cf
     }
 }
 
+// The same staging for short lengths shared by TPT = N/EPT threads (at most
+// one wavefront): after the block is in LDS, thread t of a transform reads
+// its elements t + m TPT from the row, runs the passes with wavefront-local
+// exchanges in a separate region, and writes them back to the row.
+template <int L, int E, int WG, int S>
+__global__ __launch_bounds__(WG) void k_fft_c32_st2(const cf* __restrict__ in, cf* __restrict__ out,
+                                                    const cf* __restrict__ rows, int64_t batch, float scale)
+{
+    using SC = Sched<L, E>;
+    constexpr int N = SC::N, EPT = SC::EPT, TPT = SC::TPT, TPB = WG / TPT, NP = SC::NP;
+    constexpr int H = N / 2, ROW = H + 1, RC = 2 * ROW;  // row length in vectors / complex values
+    constexpr int REG = Layout2<L, E>::region();
+    static_assert(TPT >= 2 && TPT <= 64, "transforms of 2..64 threads");
+    __shared__ v4f blk[TPB * ROW];
+    __shared__ cf xch[TPB * REG];
+    const int tid = threadIdx.x, tb = tid / TPT, t = tid % TPT;
+    const int64_t first = (int64_t)blockIdx.x * TPB;
+    const int64_t count = batch - first < TPB ? batch - first : TPB;
+    const int nv = (int)count * H;
+    const v4f* src = reinterpret_cast<const v4f*>(in + first * N);
+    v4f* dst = reinterpret_cast<v4f*>(out + first * N);
+    constexpr int K = TPB * H / WG;  // vectors per thread = EPT / 2
+    cf tws[NP][EPT];
+#pragma unroll
+    for (int p = 0; p < NP; p++)
+#pragma unroll
+        for (int r = 0; r < EPT; r++)
+            tws[p][r] = cf{1.f, 0.f};
+    load_all_rows<L, E, S>(tws, rows, t);
+    v4f q[K];
+    if (count == TPB) {
+#pragma unroll
+        for (int k = 0; k < K; k++)
+            q[k] = __builtin_nontemporal_load(src + tid + WG * k);
+    } else {
+#pragma unroll
+        for (int k = 0; k < K; k++)
+            q[k] = tid + WG * k < nv ? __builtin_nontemporal_load(src + tid + WG * k) : v4f{0.f, 0.f, 0.f, 0.f};
+    }
+#pragma unroll
+    for (int k = 0; k < K; k++) {
+        const int i = tid + WG * k;
+        blk[(i / H) * ROW + i % H] = q[k];
+    }
+    __syncthreads();
+    cf* row = reinterpret_cast<cf*>(blk) + tb * RC;
+    cf v[EPT];
+#pragma unroll
+    for (int m = 0; m < EPT; m++)
+        v[m] = row[t + m * TPT];
+    run2<L, E, S, 0, true>(v, t, rows, tws, xch + tb * REG);
+#pragma unroll
+    for (int m = 0; m < EPT; m++)
+        row[t + m * TPT] = cscale(v[m], scale);
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < K; k++) {
+        const int i = tid + WG * k;
+        q[k] = blk[(i / H) * ROW + i % H];
+    }
+    if (count == TPB) {
+#pragma unroll
+        for (int k = 0; k < K; k++)
+            __builtin_nontemporal_store(q[k], dst + tid + WG * k);
+    } else {
+#pragma unroll
+        for (int k = 0; k < K; k++)
+            if (tid + WG * k < nv)
+                __builtin_nontemporal_store(q[k], dst + tid + WG * k);
+    }
+}
+
+template <int L, int E, int WG, int S>
+hipError_t launch_c32_st2(const void* in, void* out, const void*, const void* rows, int64_t batch, float scale,
+                          int64_t, hipStream_t stream)
+{
+    constexpr int TPB = WG / Sched<L, E>::TPT;
+    const int64_t grid = (batch + TPB - 1) / TPB;
+    hipLaunchKernelGGL((k_fft_c32_st2<L, E, WG, S>), dim3((unsigned)grid), dim3(WG), 0, stream,
+                       static_cast<const cf*>(in), static_cast<cf*>(out), static_cast<const cf*>(rows), batch,
+                       scale);
+    return hipGetLastError();
+}
+
 template <int L, int WG, int S>
 hipError_t launch_c32_st(const void* in, void* out, const void* tw, const void*, int64_t batch, float scale,
                          int64_t, hipStream_t stream)
@@ -363,9 +447,24 @@ void add_st()
                                WG * ((1 << LOG2N) / 2 + ((1 << LOG2N) >= 4 ? 1 : 0)) * 16});
 }
 
+// kind 12: staged, several threads per transform (N = 32 .. 1024), 64..256 threads
+template <int L, int E, int WG, int S>
+void add_st2()
+{
+    if constexpr (L >= 5 && L <= 10 && E >= 2 && E < L && WG <= 256) {
+        constexpr int TPT = (1 << L) >> E;
+        if constexpr (TPT >= 2 && TPT <= 64 && TPT <= WG)
+            register_c32(KernelC32{L, E, WG, S, 12, &launch_c32_st2<L, E, WG, S>, nullptr,
+                                   Layout2<L, E>::rows_total(),
+                                   (WG / TPT) * ((1 << L) / 2 + 1) * 16 + (WG / TPT) * Layout2<L, E>::region() * 8});
+    }
+}
+
 template <int LOG2N, int LOG2EPT, int WG>
 void add_signs()
 {
+    add_st2<LOG2N, LOG2EPT, WG, -1>();
+    add_st2<LOG2N, LOG2EPT, WG, +1>();
     add_one<LOG2N, LOG2EPT, WG, -1>();
     add_one<LOG2N, LOG2EPT, WG, +1>();
     add_st<LOG2N, LOG2EPT, WG, -1>();

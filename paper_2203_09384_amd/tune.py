@@ -22,7 +22,7 @@ import sys
 
 EPTS = (2, 4, 8, 16)
 WGS = (64, 128, 256, 512, 1024)
-VARIANTS = tuple(range(10)) + (11,)  # 9: four-step, lengths above 2048 only; 11: staged, n <= 16
+VARIANTS = tuple(range(10)) + (11, 12)  # 9: four-step, lengths above 2048 only; 11, 12: staged, n <= 64
 
 
 def _time(fn, steps, warmup, torch):

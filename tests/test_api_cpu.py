@@ -228,7 +228,7 @@ def test_compiled_variant_listing(L):
     vs = api.c32_variants(n)
     assert len(vs) == len(set(vs)) >= 1
     for ept, wg, var in vs:
-        assert ept in (2, 4, 8, 16) and 64 <= wg <= 1024 and (0 <= var <= 8 or (var == 11 and ept == n))
+        assert ept in (2, 4, 8, 16) and 64 <= wg <= 1024 and (0 <= var <= 8 or (var == 11 and ept == n) or (var == 12 and 32 <= n <= 1024))
         assert ept <= n
     rc, d = q(n, 1000, -1)
     assert rc == 0 and (d.ept, d.wg, d.variant) in vs
