@@ -26,6 +26,8 @@
 namespace mifft {
 namespace {
 
+typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+
 template <bool BF>
 __device__ __forceinline__ float h_to_f32(uint32_t h)
 {
@@ -87,11 +89,48 @@ __global__ __launch_bounds__(WG) void k_half_small(const uint32_t* __restrict__ 
     const int tid = threadIdx.x, tb = tid / TPT, t = tid % TPT;
     const int64_t b = (int64_t)blockIdx.x * TPB + tb;
     const bool live = b < batch;
+    // Staged lengths (EPT >= 4; measured faster at N = 4..32 and 1024, slower
+    // at 64..512): the workgroup's block of TPB transforms moves between
+    // HBM and LDS in 16-byte vectors at consecutive lanes (1 KiB per wave
+    // instruction); in LDS each transform is a row of N words padded so
+    // that the threads of neighbouring transforms read distinct banks.
+    constexpr bool STAGED = EPT >= 4 && (L <= 5 || L == 10);
+    constexpr int ROWW = N + (TPT == 1 ? 0 : (TPT > 4 ? TPT : 4));
+    constexpr int K = STAGED ? EPT / 4 : 1;  // 16-byte vectors per thread
+    __shared__ __attribute__((aligned(16))) uint32_t blk[STAGED ? TPB * ROWW : 4];
+    const int64_t first = (int64_t)blockIdx.x * TPB;
+    const int64_t count = batch - first < TPB ? batch - first : TPB;
+    const int nv = (int)count * (N / 4);
+    v4u q[K];
     cf v[EPT];
+    if constexpr (STAGED) {
+        const v4u* src = reinterpret_cast<const v4u*>(in + first * N);
+        if (count == TPB) {
 #pragma unroll
-    for (int m = 0; m < EPT; m++) {
-        const uint32_t u = live ? in[b * N + t + m * TPT] : 0u;
-        v[m] = cf{h_to_f32<BF>(u & 0xffffu), h_to_f32<BF>(u >> 16)};
+            for (int k = 0; k < K; k++)
+                q[k] = __builtin_nontemporal_load(src + tid + WG * k);
+        } else {
+#pragma unroll
+            for (int k = 0; k < K; k++)
+                q[k] = tid + WG * k < nv ? __builtin_nontemporal_load(src + tid + WG * k) : v4u{0u, 0u, 0u, 0u};
+        }
+#pragma unroll
+        for (int k = 0; k < K; k++) {
+            const int w = 4 * (tid + WG * k);  // first word of the vector in the block
+            *reinterpret_cast<v4u*>(blk + (w / N) * ROWW + w % N) = q[k];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < EPT; m++) {
+            const uint32_t u = blk[tb * ROWW + t + m * TPT];
+            v[m] = cf{h_to_f32<BF>(u & 0xffffu), h_to_f32<BF>(u >> 16)};
+        }
+    } else {
+#pragma unroll
+        for (int m = 0; m < EPT; m++) {
+            const uint32_t u = live ? in[b * N + t + m * TPT] : 0u;
+            v[m] = cf{h_to_f32<BF>(u & 0xffffu), h_to_f32<BF>(u >> 16)};
+        }
     }
     // normalise: largest component into [1/2, 1)
     const int e_in = exp_above(group_max<TPT>(abs_max<E>(v)));
@@ -117,11 +156,33 @@ __global__ __launch_bounds__(WG) void k_half_small(const uint32_t* __restrict__ 
     for (int m = 0; m < EPT; m++) {
         const cf y = out_exp ? cscale(v[m], ldexpf(1.0f, 15 - e_o))
                              : cf{ldexpf(v[m].x, ein + e_in + scale_log2), ldexpf(v[m].y, ein + e_in + scale_log2)};
-        if (live)
-            out[b * N + t + m * TPT] = f32_to_h<BF>(y.x) | (f32_to_h<BF>(y.y) << 16);
+        const uint32_t u = f32_to_h<BF>(y.x) | (f32_to_h<BF>(y.y) << 16);
+        if constexpr (STAGED)
+            blk[tb * ROWW + t + m * TPT] = u;  // this thread's own elements: no other thread reads them yet
+        else if (live)
+            out[b * N + t + m * TPT] = u;
     }
     if (out_exp && live && t == 0)
         out_exp[b] = e_total;
+    if constexpr (STAGED) {
+        __syncthreads();
+        v4u* dst = reinterpret_cast<v4u*>(out + first * N);
+#pragma unroll
+        for (int k = 0; k < K; k++) {
+            const int w = 4 * (tid + WG * k);
+            q[k] = *reinterpret_cast<const v4u*>(blk + (w / N) * ROWW + w % N);
+        }
+        if (count == TPB) {
+#pragma unroll
+            for (int k = 0; k < K; k++)
+                __builtin_nontemporal_store(q[k], dst + tid + WG * k);
+        } else {
+#pragma unroll
+            for (int k = 0; k < K; k++)
+                if (tid + WG * k < nv)
+                    __builtin_nontemporal_store(q[k], dst + tid + WG * k);
+        }
+    }
 }
 
 template <int L, int E, int WG, int S, bool BF>
