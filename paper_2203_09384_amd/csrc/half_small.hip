@@ -89,12 +89,12 @@ __global__ __launch_bounds__(WG) void k_half_small(const uint32_t* __restrict__ 
     const int tid = threadIdx.x, tb = tid / TPT, t = tid % TPT;
     const int64_t b = (int64_t)blockIdx.x * TPB + tb;
     const bool live = b < batch;
-    // Staged lengths (EPT >= 4; measured faster at N = 4..32 and 1024, slower
-    // at 64..512): the workgroup's block of TPB transforms moves between
+    // Staged lengths (EPT >= 4; measured faster at N = 4..64 and 1024, slower
+    // at 128..512): the workgroup's block of TPB transforms moves between
     // HBM and LDS in 16-byte vectors at consecutive lanes (1 KiB per wave
     // instruction); in LDS each transform is a row of N words padded so
     // that the threads of neighbouring transforms read distinct banks.
-    constexpr bool STAGED = EPT >= 4 && (L <= 5 || L == 10);
+    constexpr bool STAGED = EPT >= 4 && (L <= 6 || L == 10);
     constexpr int ROWW = N + (TPT == 1 ? 0 : (TPT > 4 ? TPT : 4));
     constexpr int K = STAGED ? EPT / 4 : 1;  // 16-byte vectors per thread
     __shared__ __attribute__((aligned(16))) uint32_t blk[STAGED ? TPB * ROWW : 4];
@@ -198,7 +198,7 @@ hipError_t launch_half_small(const void* in, const int32_t* in_exp, void* out, i
 }
 
 // One configuration per length: elements per thread and workgroup size.
-constexpr int small_e(int L) { return L <= 2 ? L : (L <= 6 ? 2 : (L == 7 || L == 9 ? 3 : 4)); }
+constexpr int small_e(int L) { return L <= 2 ? L : (L <= 5 ? 2 : (L == 6 || L == 7 || L == 9 ? 3 : 4)); }
 constexpr int small_wg(int L) { return L <= 2 ? 64 : (L <= 5 || L == 8 ? 256 : 64); }
 
 template <int L>
