@@ -76,29 +76,53 @@ __device__ __forceinline__ int exp_above(float m)
     return e;
 }
 
-template <int L, int E, int WG, int S, bool BF>
-__global__ __launch_bounds__(WG) void k_half_small(const uint32_t* __restrict__ in, const int32_t* __restrict__ in_exp,
-                                                   uint32_t* __restrict__ out, int32_t* __restrict__ out_exp,
-                                                   const cf* __restrict__ rows, int64_t batch, int scale_log2)
+// Lengths 2^8..2^10 launch a capped grid whose workgroups loop over groups
+// of transforms, so each pass's twiddle row is read into registers once per
+// workgroup rather than once per group (N = 256: 113 -> 102 us, 512: 114 ->
+// 107 us, 1024: 144 -> 120 us at 2^26 elements).  The caps are the measured
+// best per length.
+template <int L>
+constexpr bool small_persistent()
+{
+    return L >= 8;
+}
+constexpr int64_t small_persist_grid(int L) { return L == 8 ? 8192 : (L == 9 ? 32768 : 16384); }
+
+template <int L, int E>
+constexpr bool small_staged()
+{
+    constexpr int EPT = 1 << E;
+    return EPT >= 4 && (L <= 6 || L == 10);
+}
+template <int L, int E>
+constexpr int small_roww()
+{
+    constexpr int N = 1 << L, TPT = N >> E;
+    return N + (TPT == 1 ? 0 : (TPT > 4 ? TPT : 4));
+}
+
+// One group of TPB transforms (group index g) through the kernel's steps.
+template <int L, int E, int WG, int S, bool BF, int TW>
+__device__ __forceinline__ void small_group(const uint32_t* __restrict__ in, const int32_t* __restrict__ in_exp,
+                                            uint32_t* __restrict__ out, int32_t* __restrict__ out_exp,
+                                            const cf* __restrict__ rows, int64_t batch, int scale_log2, int64_t g,
+                                            const TwRegs<L, E>& tws, cf* lds, uint32_t* blk)
 {
     using SC = Sched<L, E>;
     constexpr int N = SC::N, EPT = SC::EPT, TPT = SC::TPT, TPB = WG / TPT;
-    static_assert(TPT <= 64, "a transform's threads share one wavefront");
     constexpr int REG = TPT > 1 ? Layout2<L, E>::region() : 1;
-    __shared__ cf lds[TPT > 1 ? TPB * REG : 1];
     const int tid = threadIdx.x, tb = tid / TPT, t = tid % TPT;
-    const int64_t b = (int64_t)blockIdx.x * TPB + tb;
+    const int64_t first = g * TPB;
+    const int64_t b = first + tb;
     const bool live = b < batch;
     // Staged lengths (EPT >= 4; measured faster at N = 4..64 and 1024, slower
     // at 128..512): the workgroup's block of TPB transforms moves between
     // HBM and LDS in 16-byte vectors at consecutive lanes (1 KiB per wave
     // instruction); in LDS each transform is a row of N words padded so
     // that the threads of neighbouring transforms read distinct banks.
-    constexpr bool STAGED = EPT >= 4 && (L <= 6 || L == 10);
-    constexpr int ROWW = N + (TPT == 1 ? 0 : (TPT > 4 ? TPT : 4));
+    constexpr bool STAGED = small_staged<L, E>();
+    constexpr int ROWW = small_roww<L, E>();
     constexpr int K = STAGED ? EPT / 4 : 1;  // 16-byte vectors per thread
-    __shared__ __attribute__((aligned(16))) uint32_t blk[STAGED ? TPB * ROWW : 4];
-    const int64_t first = (int64_t)blockIdx.x * TPB;
     const int64_t count = batch - first < TPB ? batch - first : TPB;
     const int nv = (int)count * (N / 4);
     v4u q[K];
@@ -138,16 +162,10 @@ __global__ __launch_bounds__(WG) void k_half_small(const uint32_t* __restrict__ 
 #pragma unroll
     for (int m = 0; m < EPT; m++)
         v[m] = cscale(v[m], s_in);
-    TwRegs<L, E> tws;
-#pragma unroll
-    for (int p = 0; p < SC::NP; p++)
-#pragma unroll
-        for (int r = 0; r < EPT; r++)
-            tws[p][r] = cf{1.f, 0.f};
     if constexpr (TPT == 1)
         pass_compute2<L, E, S, 0>(v, tws[0]);
     else
-        run2<L, E, S, 1, true>(v, t, rows, tws, lds + tb * REG);
+        run2<L, E, S, TW, true>(v, t, rows, tws, lds + tb * REG);
     // output: largest component into [2^14, 2^15), or the logical value
     const int e_o = exp_above(group_max<TPT>(abs_max<E>(v)));
     const int ein = (live && in_exp) ? in_exp[b] : 0;
@@ -186,11 +204,43 @@ __global__ __launch_bounds__(WG) void k_half_small(const uint32_t* __restrict__ 
 }
 
 template <int L, int E, int WG, int S, bool BF>
+__global__ __launch_bounds__(WG) void k_half_small(const uint32_t* __restrict__ in, const int32_t* __restrict__ in_exp,
+                                                   uint32_t* __restrict__ out, int32_t* __restrict__ out_exp,
+                                                   const cf* __restrict__ rows, int64_t batch, int scale_log2)
+{
+    using SC = Sched<L, E>;
+    constexpr int EPT = SC::EPT, TPT = SC::TPT, TPB = WG / TPT;
+    static_assert(TPT <= 64, "a transform's threads share one wavefront");
+    constexpr int REG = TPT > 1 ? Layout2<L, E>::region() : 1;
+    __shared__ cf lds[TPT > 1 ? TPB * REG : 1];
+    __shared__ __attribute__((aligned(16))) uint32_t blk[small_staged<L, E>() ? TPB * small_roww<L, E>() : 4];
+    TwRegs<L, E> tws;
+#pragma unroll
+    for (int p = 0; p < SC::NP; p++)
+#pragma unroll
+        for (int r = 0; r < EPT; r++)
+            tws[p][r] = cf{1.f, 0.f};
+    if constexpr (small_persistent<L>() && TPT > 1) {
+        load_all_rows<L, E, S>(tws, rows, threadIdx.x % TPT);
+        const int64_t ngroups = (batch + TPB - 1) / TPB;
+        for (int64_t g = blockIdx.x; g < ngroups; g += gridDim.x) {
+            if (g != blockIdx.x)
+                __syncthreads();  // the previous group's block and exchanges are read out
+            small_group<L, E, WG, S, BF, 0>(in, in_exp, out, out_exp, rows, batch, scale_log2, g, tws, lds, blk);
+        }
+    } else {
+        small_group<L, E, WG, S, BF, 1>(in, in_exp, out, out_exp, rows, batch, scale_log2, blockIdx.x, tws, lds, blk);
+    }
+}
+
+template <int L, int E, int WG, int S, bool BF>
 hipError_t launch_half_small(const void* in, const int32_t* in_exp, void* out, int32_t* out_exp, const void* rows,
                              int64_t batch, int scale_log2, hipStream_t stream)
 {
     constexpr int TPB = WG / ((1 << L) >> E);
-    const int64_t grid = (batch + TPB - 1) / TPB;
+    const int64_t ngroups = (batch + TPB - 1) / TPB;
+    constexpr int64_t cap = small_persist_grid(L);
+    const int64_t grid = small_persistent<L>() && ngroups > cap ? cap : ngroups;
     hipLaunchKernelGGL((k_half_small<L, E, WG, S, BF>), dim3((unsigned)grid), dim3(WG), 0, stream,
                        static_cast<const uint32_t*>(in), in_exp, static_cast<uint32_t*>(out), out_exp,
                        static_cast<const cf*>(rows), batch, scale_log2);

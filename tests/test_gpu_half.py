@@ -202,3 +202,34 @@ def test_half_adjoint(n, dtype, sign):
     ref = oracle.adjoint(from_half(xh), sign, 1.0 if sign < 0 else 1.0 / n)
     bar = SMALL_TOL[dtype] if n < 2048 else TOL
     assert rel(from_half(out), ref) <= bar
+
+
+# Transforms per workgroup and the grid cap of the looping launches at
+# N = 256, 512, 1024 (each workgroup walks groups g, g + cap, g + 2 cap, ...).
+PERSIST = {256: (16, 8192), 512: (1, 32768), 1024: (1, 16384)}
+
+
+@pytest.mark.parametrize("n", sorted(PERSIST))
+@pytest.mark.parametrize("dtype", ["c16", "cbf16"])
+def test_small_lengths_looping_grid(n, dtype):
+    """Batches past the grid cap with a ragged last group: sampled transforms
+    at the ends of the first and second sweeps and in the last group against
+    the oracle, and the stored range of every transform."""
+    tpb, cap = PERSIST[n]
+    batch = cap * tpb * 3 // 2 + 3
+    gen = torch.Generator(device="cuda").manual_seed(2203 + n)
+    x = (2 * torch.rand(batch, n, 2, device="cuda", generator=gen) - 1).to(TORCH[dtype])
+    p = api.Plan(n, batch, -1, dtype=dtype)
+    print(f"[case] half looping grid n={n} {dtype} batch={batch} {p.describe()}", flush=True)
+    yh, ex = p.execute_scaled(x)
+    torch.cuda.synchronize()
+    mx = yh.float().abs().amax(dim=(1, 2))
+    assert float(mx.max()) <= 2.0 ** 15 and float(mx.min()) >= 2.0 ** 14
+    idx = []
+    for g in (0, cap - 1, cap, (batch - 1) // tpb):
+        idx += [g * tpb, min(g * tpb + tpb - 1, batch - 1)]
+    idx = np.unique(np.array(idx + [batch - 1]))
+    it = torch.from_numpy(idx).cuda()
+    y = from_half(yh[it], ex[it])
+    ref = oracle.forward(from_half(x[it]))
+    assert rel(y, ref) <= SMALL_TOL[dtype]
