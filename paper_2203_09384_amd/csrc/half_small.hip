@@ -76,17 +76,17 @@ __device__ __forceinline__ int exp_above(float m)
     return e;
 }
 
-// Lengths 2^8..2^10 launch a capped grid whose workgroups loop over groups
+// Lengths 2^5..2^10 launch a capped grid whose workgroups loop over groups
 // of transforms, so each pass's twiddle row is read into registers once per
-// workgroup rather than once per group (N = 256: 113 -> 102 us, 512: 114 ->
-// 107 us, 1024: 144 -> 120 us at 2^26 elements).  The caps are the measured
-// best per length.
+// workgroup rather than once per group (at 2^26 elements N = 32: 126 -> 113
+// us, 64: 105 -> 94, 128: 114 -> 108, 256: 113 -> 104, 512: 114 -> 107,
+// 1024: 145 -> 123 us).  The caps are the measured best per length.
 template <int L>
 constexpr bool small_persistent()
 {
-    return L >= 8;
+    return L >= 5;
 }
-constexpr int64_t small_persist_grid(int L) { return L == 8 ? 8192 : (L == 9 ? 32768 : 16384); }
+constexpr int64_t small_persist_grid(int L) { return L == 8 ? 8192 : (L == 10 ? 16384 : 32768); }
 
 template <int L, int E>
 constexpr bool small_staged()
