@@ -76,17 +76,18 @@ __device__ __forceinline__ int exp_above(float m)
     return e;
 }
 
-// Lengths 2^5..2^10 launch a capped grid whose workgroups loop over groups
+// Lengths 2^3..2^10 launch a capped grid whose workgroups loop over groups
 // of transforms, so each pass's twiddle row is read into registers once per
-// workgroup rather than once per group (at 2^26 elements N = 32: 126 -> 113
-// us, 64: 105 -> 94, 128: 114 -> 108, 256: 113 -> 104, 512: 114 -> 107,
-// 1024: 145 -> 123 us).  The caps are the measured best per length.
+// workgroup rather than once per group (at 2^26 elements N = 8: 107 -> 93
+// us, 16: 107 -> 92, 32: 126 -> 113, 64: 105 -> 94, 128: 114 -> 108, 256:
+// 113 -> 104, 512: 114 -> 107, 1024: 145 -> 123 us).  The caps are the
+// measured best per length.
 template <int L>
 constexpr bool small_persistent()
 {
-    return L >= 5;
+    return L >= 3;
 }
-constexpr int64_t small_persist_grid(int L) { return L == 8 ? 8192 : (L == 10 ? 16384 : 32768); }
+constexpr int64_t small_persist_grid(int L) { return L == 8 ? 8192 : (L <= 4 || L == 10 ? 16384 : 32768); }
 
 template <int L, int E>
 constexpr bool small_staged()

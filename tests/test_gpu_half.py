@@ -205,8 +205,8 @@ def test_half_adjoint(n, dtype, sign):
 
 
 # Transforms per workgroup and the grid cap of the looping launches at
-# N = 32..1024 (each workgroup walks groups g, g + cap, g + 2 cap, ...).
-PERSIST = {32: (32, 32768), 64: (8, 32768), 128: (4, 32768), 256: (16, 8192), 512: (1, 32768), 1024: (1, 16384)}
+# N = 8..1024 (each workgroup walks groups g, g + cap, g + 2 cap, ...).
+PERSIST = {8: (128, 16384), 16: (64, 16384), 32: (32, 32768), 64: (8, 32768), 128: (4, 32768), 256: (16, 8192), 512: (1, 32768), 1024: (1, 16384)}
 
 
 @pytest.mark.parametrize("n", sorted(PERSIST))
