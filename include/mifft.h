@@ -29,8 +29,10 @@
  *     FFT_R32: the real side holds n float32 values per transform
  *     (floats [b*n, (b+1)*n)), the spectrum side n/2 + 1 complex float32
  *     bins per transform (bins [b*(n/2+1), (b+1)*(n/2+1))).
- *   - `in` and `out` are device pointers owned by the caller, 16-byte
- *     aligned, and must not overlap (out of place only).
+ *   - `in` and `out` are device pointers owned by the caller, aligned to
+ *     their element (FFT_C32 and complex bins: 8 bytes; FFT_C16 / FFT_CBF16
+ *     pairs and FFT_R32 reals: 4 bytes; any offset view of a tensor of that
+ *     element type qualifies), and must not overlap (out of place only).
  *   - `stream` is a hipStream_t (NULL = the legacy default stream).  Every
  *     execute call only enqueues work: it allocates nothing, synchronises
  *     nothing and copies nothing, so it may be captured into a hipGraph.
@@ -77,9 +79,11 @@ enum {
     FFT_EHIP = 8,           /* a HIP call failed (message has the HIP string)   */
     FFT_ENOMEM = 9,         /* host or device allocation failed                 */
     FFT_EINVAL_CONFIG = 10, /* requested kernel variant does not exist          */
-    FFT_EALIGN = 11,        /* in/out not 16-byte aligned                       */
-    FFT_EDEVICE = 12        /* current device is not a gfx950 GPU, or plan used
+    FFT_EALIGN = 11,        /* a buffer not aligned to its element (complex64:
+                               8 bytes; 16-bit pairs, float32: 4 bytes)         */
+    FFT_EDEVICE = 12,       /* current device is not a gfx950 GPU, or plan used
                                while another device is current                  */
+    FFT_ECAPTURE = 13       /* plan creation while a stream capture is active   */
 };
 
 /* Description of what a plan launches (fft_plan_describe / fft_plan_query). */

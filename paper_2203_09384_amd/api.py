@@ -256,12 +256,22 @@ _cache: dict = {}
 _cache_lock = threading.Lock()
 
 
+def _refuse_under_capture(what):
+    """Plan creation allocates device memory and waits for its tables, which
+    a stream capture cannot contain: raise before touching the device (the
+    capture stays intact) rather than let the capture be invalidated."""
+    if torch.cuda.is_current_stream_capturing():
+        raise MifftError(native.FFT_ECAPTURE, f"{what}: no cached plan for this shape, and plans cannot be "
+                                              "created during stream capture; run the call once before capturing")
+
+
 def get_plan(n: int, batch: int, sign: int, dtype: str = "c32", device=None) -> Plan:
     dev = torch.cuda.current_device() if device is None else device
     key = (dev, n, batch, sign, dtype)
     with _cache_lock:
         p = _cache.get(key)
         if p is None:
+            _refuse_under_capture(f"plan n={n} batch={batch} sign={sign} {dtype}")
             with torch.cuda.device(dev):
                 p = Plan(n, batch, sign, dtype)
             _cache[key] = p
@@ -313,21 +323,19 @@ class WeightedPowerLossFn(torch.autograd.Function):
     """L = sum_b sum_k w |(A x_b)_k|^2 in one fused kernel that also produces
     dL/dx = A^H (2 w A x) (PyTorch's complex convention); backward scales the
     saved gradient by the incoming scalar.  w is treated as a constant.
-    Longer transforms take the plan's transform, the weighting in torch and
-    the plan's adjoint (three launches, the same result)."""
+    Lengths 2..2048 (the fused kernel's range); for longer transforms
+    compose fft_differentiable with the loss in torch."""
 
     @staticmethod
     def forward(ctx, x, w, sign: int = -1):
         x = x.contiguous()
         w = w.contiguous()
         n = x.shape[-1]
+        if n > FUSED_LOSS_MAX_N:
+            raise ValueError(f"the fused loss kernel covers n <= {FUSED_LOSS_MAX_N} (got n={n}); "
+                             "use fft_differentiable and the loss in torch")
         plan = get_plan(n, x.numel() // n, sign, "c32", x.device.index)
-        if n <= FUSED_LOSS_MAX_N:
-            loss, grad = plan.loss_grad(x, w)
-        else:
-            y = plan.execute(x)
-            loss = (w * (y.real ** 2 + y.imag ** 2)).sum(dim=-1)
-            grad = plan.adjoint((2.0 * w) * y)
+        loss, grad = plan.loss_grad(x, w)
         ctx.save_for_backward(grad)
         return loss.sum()
 
@@ -427,6 +435,7 @@ def _nd_plan(shape, batch, sign, device):
     with _cache_lock:
         p = _cache.get(key)
         if p is None:
+            _refuse_under_capture(f"plan dims={tuple(shape)} batch={batch} sign={sign}")
             with torch.cuda.device(dev):
                 p = PlanND(shape, batch, sign)
             _cache[key] = p

@@ -19,6 +19,7 @@
 #include "fourstep.hpp"
 #include "fused_loss.hpp"
 #include "half.hpp"
+#include "index_maps.hpp"
 #include "nd.hpp"
 #include "nd2.hpp"
 #include "ragged.hpp"
@@ -56,6 +57,10 @@ int ok()
 
 int hip_err(hipError_t e, const char* what)
 {
+    if (e == hipErrorStreamCaptureUnsupported || e == hipErrorStreamCaptureImplicit ||
+        e == hipErrorStreamCaptureInvalidated)
+        return set_err(FFT_ECAPTURE, "%s: %s (%d): plans must be created outside stream capture", what,
+                       hipGetErrorString(e), (int)e);
     return set_err(FFT_EHIP, "%s: %s (%d)", what, hipGetErrorString(e), (int)e);
 }
 
@@ -295,15 +300,12 @@ Variant choose_r32(int log2m)
 }
 
 // Stockham schedule of (log2 N, log2 EPT): a remainder pass first, then
-// passes of radix EPT.  Mirrors Sched<> in device_fft.hpp.
+// passes of radix EPT (the schedule functions the kernels use).
 int schedule(int log2n, int log2ept, int* radices)
 {
-    const int rem = log2n % log2ept;
-    int np = 0;
-    if (rem)
-        radices[np++] = 1 << rem;
-    for (int i = 0; i < log2n / log2ept; i++)
-        radices[np++] = 1 << log2ept;
+    const int np = idx::sched_np(log2n, log2ept);
+    for (int p = 0; p < np; p++)
+        radices[p] = 1 << idx::sched_log2r(log2n, log2ept, p);
     return np;
 }
 }  // namespace
@@ -470,11 +472,31 @@ int fill_desc_r32(int64_t n, int64_t batch, int sign, Variant v, int64_t grid_li
     return FFT_OK;
 }
 
+// Plan creation allocates device memory and fills tables on the legacy
+// default stream, then waits for them: none of that may happen while a
+// stream capture is active (it would end or invalidate the capture).  A
+// query of the legacy stream reports a capture in progress on any stream of
+// the process (global capture mode) or of this thread.
+int check_not_capturing()
+{
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    const hipError_t e = hipStreamIsCapturing(nullptr, &st);
+    if (e == hipErrorStreamCaptureImplicit || (e == hipSuccess && st != hipStreamCaptureStatusNone))
+        return set_err(FFT_ECAPTURE, "plan creation during stream capture (it allocates and synchronises); "
+                                     "create plans before capturing");
+    if (e != hipSuccess)
+        return hip_err(e, "hipStreamIsCapturing");
+    return FFT_OK;
+}
+
+// Device checks of plan creation: not capturing, and a gfx950 device current.
 int current_gfx950(int* dev)
 {
     hipError_t e = hipGetDevice(dev);
     if (e != hipSuccess)
         return hip_err(e, "hipGetDevice");
+    if (check_not_capturing() != FFT_OK)
+        return g_err;
     hipDeviceProp_t prop;
     e = hipGetDeviceProperties(&prop, *dev);
     if (e != hipSuccess)
@@ -1065,13 +1087,19 @@ int check_exec(fft_plan p, const void* in, const void* out, bool to_bins = false
         return set_err(FFT_ENULL, "plan is NULL");
     if (!in || !out)
         return set_err(FFT_ENULL, "in/out pointer is NULL");
-    if ((reinterpret_cast<uintptr_t>(in) | reinterpret_cast<uintptr_t>(out)) & 15)
-        return set_err(FFT_EALIGN, "in/out must be 16-byte aligned");
     uintptr_t in_bytes = (uintptr_t)p->total * elem_bytes(p->dtype), out_bytes = in_bytes;
+    // element alignment: complex64 8 bytes; 16-bit (re, im) pairs and
+    // float32 reals 4 bytes
+    uintptr_t in_align = elem_bytes(p->dtype), out_align = in_align;
     if (p->dtype == FFT_R32) {
         in_bytes = to_bins ? real_side_bytes(p) : bins_side_bytes(p);
         out_bytes = to_bins ? bins_side_bytes(p) : real_side_bytes(p);
+        in_align = to_bins ? 4 : 8;
+        out_align = to_bins ? 8 : 4;
     }
+    if ((reinterpret_cast<uintptr_t>(in) & (in_align - 1)) || (reinterpret_cast<uintptr_t>(out) & (out_align - 1)))
+        return set_err(FFT_EALIGN, "in (%p) must be %d-byte and out (%p) %d-byte aligned (element alignment)", in,
+                       (int)in_align, out, (int)out_align);
     const uintptr_t a = reinterpret_cast<uintptr_t>(in), b = reinterpret_cast<uintptr_t>(out);
     if (a < b + out_bytes && b < a + in_bytes)
         return set_err(FFT_EOVERLAP, "in [%p, +%zu) and out [%p, +%zu) overlap (out of place only)", in,

@@ -22,6 +22,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "index_maps.hpp"
+
 namespace mifft {
 
 struct alignas(8) cf {
@@ -202,11 +204,8 @@ struct Sched {
     static constexpr int TPT = N / EPT;  // threads per transform
     static constexpr int REM = LOG2N % LOG2EPT;
     static constexpr int NP = LOG2N / LOG2EPT + (REM ? 1 : 0);
-    static constexpr int log2r(int p) { return (REM && p == 0) ? REM : LOG2EPT; }
-    static constexpr int log2ns(int p)
-    {
-        return p == 0 ? 0 : (REM ? REM + (p - 1) * LOG2EPT : p * LOG2EPT);
-    }
+    static constexpr int log2r(int p) { return idx::sched_log2r(LOG2N, LOG2EPT, p); }
+    static constexpr int log2ns(int p) { return idx::sched_log2ns(LOG2N, LOG2EPT, p); }
     static_assert(LOG2EPT >= 1 && LOG2EPT <= 4, "EPT must be 2..16");
     static_assert(LOG2EPT <= LOG2N, "EPT must not exceed N");
 };
@@ -256,12 +255,7 @@ __device__ __forceinline__ void pass_compute(cf (&v)[1 << LOG2EPT], int t, const
 template <int LOG2N, int LOG2EPT, int P>
 __device__ __forceinline__ int pass_dst(int t, int q, int r)
 {
-    using SC = Sched<LOG2N, LOG2EPT>;
-    constexpr int LR = SC::log2r(P);
-    constexpr int LNS = SC::log2ns(P), NS = 1 << LNS;
-    const int j = t + q * SC::TPT;
-    const int k = j & (NS - 1);
-    return ((j >> LNS) << (LNS + LR)) + k + r * NS;
+    return idx::stockham_dst(LOG2N, LOG2EPT, P, t + q * Sched<LOG2N, LOG2EPT>::TPT, r);
 }
 
 // All passes of one transform held by a set of TPT threads.
@@ -308,93 +302,25 @@ __device__ __forceinline__ void run_passes(cf (&v)[1 << LOG2EPT], int t, const c
 // immediate offset, no per-element index arithmetic -- and (b) the modelled
 // bank conflicts of the 64-bank LDS are lowest among such B.  B = 0 means
 // no padding.
-constexpr int pad_bits(int L, int E, int P)
-{
-    // rows: exchanges 0.. of (log2 N, log2 EPT); 0 = unpadded
-    if (E == 4) {
-        if (L == 5) return 1;
-        if (L == 6) return 2;
-        if (L == 7) return 3;
-        if (L == 8) return 4;
-        if (L == 9) return 5;
-        if (L == 10) return P == 0 ? 5 : 6;
-        if (L == 11) return P == 0 ? 5 : 3;
-        if (L == 12) return P == 0 ? 5 : 4;
-        if (L == 13) return 5;
-        if (L == 14) return P == 1 ? 6 : 5;
-    } else if (E == 3) {
-        if (L == 4) return 1;
-        if (L == 5) return 2;
-        if (L == 6) return 3;
-        if (L == 7) return P == 0 ? 1 : 4;
-        if (L == 8) return P == 0 ? 5 : 2;
-        if (L == 9) return P == 0 ? 5 : 3;
-        if (L == 10) return P == 2 ? 7 : 5;
-        if (L == 11) return P == 1 ? 2 : 5;
-        if (L == 12) return P == 1 ? 3 : 5;
-        if (L == 13) return P == 2 ? 7 : 5;
-        if (L == 14) return P == 1 ? 2 : 5;
-    } else if (E == 2) {
-        if (L == 3) return 1;
-        if (L == 4) return 2;
-        if (L == 5) return 1;
-        if (L == 6) return 2;
-        if (L == 7) return P == 2 ? 1 : 5;
-        if (L == 8) return P == 1 ? 2 : (P == 2 ? 6 : 5);
-        if (L == 9) return P == 2 ? 1 : 5;
-        if (L == 10) return P == 1 ? 2 : (P == 2 ? 6 : 5);
-        if (L == 11) return P == 2 ? 1 : 5;
-    }
-    return 0;
-}
-
-// The write addresses of pass P are affine in (q, r) and the read addresses
-// of pass P+1 affine in m under padding B: the r field of pass P and the m
-// field of the reads lie entirely on one side of bit B.
-constexpr bool pad_is_affine(int L, int E, int P, int B)
-{
-    if (B == 0 || B >= L) return true;
-    const int rem = L % E;
-    const int lr = (rem && P == 0) ? rem : E;
-    const int lns = P == 0 ? 0 : (rem ? rem + (P - 1) * E : P * E);
-    const int lt = L - E;
-    bool w = (lns + lr <= B) || (lns >= B);
-    if ((1 << E) > (1 << lr)) w = w && (lt + lr >= B);
-    return w && (lt >= B);
-}
+using idx::pad_bits;
+using idx::pad_is_affine;
 
 template <int B>
 __device__ __forceinline__ int pad(int d)
 {
-    if constexpr (B == 0)
-        return d;
-    else
-        return d + (d >> B);
+    return idx::pad_index(B, d);
 }
 
 template <int L, int E>
 struct Layout2 {
     using SC = Sched<L, E>;
     static constexpr int N = SC::N;
-    static constexpr int padded(int B) { return B == 0 ? N : N + (N >> B); }
     // LDS elements per transform: the largest padded size over the exchanges
-    static constexpr int region()
-    {
-        int m = N;
-        for (int p = 0; p + 1 < SC::NP; p++)
-            m = padded(pad_bits(L, E, p)) > m ? padded(pad_bits(L, E, p)) : m;
-        return m;
-    }
+    static constexpr int region() { return idx::region(L, E); }
     // twiddle rows: for each pass P >= 1 (NS > 1), NS rows of EPT entries
     // w_{NS R}^{r k}, r < R = EPT (entry 0 is 1).
-    static constexpr int rows_offset(int P)
-    {
-        int off = 0;
-        for (int p = 0; p < P; p++)
-            if (SC::log2ns(p) > 0) off += (1 << SC::log2ns(p)) * SC::EPT;
-        return off;
-    }
-    static constexpr int rows_total() { return rows_offset(SC::NP); }
+    static constexpr int rows_offset(int P) { return idx::rows_offset(L, E, P); }
+    static constexpr int rows_total() { return idx::rows_total(L, E); }
 };
 
 // Twiddles of pass P for thread t, read as EPT/2 16-byte loads of one row.
@@ -452,12 +378,10 @@ __device__ __forceinline__ void exchange2(cf (&v)[1 << E], int t, cf* lds)
 {
     using SC = Sched<L, E>;
     constexpr int LR = SC::log2r(P), R = 1 << LR, LNS = SC::log2ns(P), NS = 1 << LNS;
-    constexpr int EPT = SC::EPT, TPT = SC::TPT, Q = EPT / R;
-    constexpr int B = pad_bits(L, E, P);
+    constexpr int EPT = SC::EPT, Q = EPT / R;
+    constexpr idx::Strides ST = idx::exchange_strides(L, E, P);
+    constexpr int B = ST.B, DR = ST.DR, DQ = ST.DQ, DM = ST.DM;
     static_assert(pad_is_affine(L, E, P, B), "padding must keep addresses affine");
-    constexpr int DR = B == 0 ? NS : (LNS >= B ? NS + (NS >> B) : NS);
-    constexpr int DQ = B == 0 ? TPT * R : (TPT * R + ((TPT * R) >> B));
-    constexpr int DM = B == 0 ? TPT : (TPT + (TPT >> B));
     // base: r = 0, q = 0
     const int k = t & (NS - 1);
     const int d0 = ((t >> LNS) << (LNS + LR)) + k;
@@ -476,6 +400,14 @@ __device__ __forceinline__ void exchange2(cf (&v)[1 << E], int t, cf* lds)
 
 // ---------------------------------------------------------------- global data access
 typedef float v2f __attribute__((ext_vector_type(2)));
+// Types for HBM data: declared 4-byte aligned, so buffers need only be
+// aligned to their element (complex64: 8 bytes; float32 reals and 16-bit
+// (re, im) pairs: 4 bytes).  gfx950 serves dword-aligned multi-dword global
+// accesses in hardware, and the compiler still emits one dwordx2 / dwordx4
+// instruction for each.
+typedef float gv2 __attribute__((ext_vector_type(2), aligned(4)));
+typedef float gv4 __attribute__((ext_vector_type(4), aligned(4)));
+typedef uint32_t gu4 __attribute__((ext_vector_type(4), aligned(4)));
 
 // Transform data is streamed: read once, written once.  Nontemporal
 // accesses (NT) keep it from displacing the twiddle tables in the caches
@@ -493,26 +425,31 @@ constexpr bool stream_nt()
 template <bool NT>
 __device__ __forceinline__ cf ld_data(const char* p)
 {
-    if constexpr (NT) {
-        const v2f v = __builtin_nontemporal_load(reinterpret_cast<const v2f*>(p));
-        return cf{v.x, v.y};
-    } else {
-        return *reinterpret_cast<const cf*>(p);
-    }
+    const gv2* q = reinterpret_cast<const gv2*>(p);
+    gv2 v;
+    if constexpr (NT)
+        v = __builtin_nontemporal_load(q);
+    else
+        v = *q;
+    return cf{v.x, v.y};
 }
 
 template <bool NT>
 __device__ __forceinline__ void st_data(char* p, cf v)
 {
-    if constexpr (NT) {
-        v2f w;
-        w.x = v.x;
-        w.y = v.y;
-        __builtin_nontemporal_store(w, reinterpret_cast<v2f*>(p));
-    } else {
-        *reinterpret_cast<cf*>(p) = v;
-    }
+    gv2 w;
+    w.x = v.x;
+    w.y = v.y;
+    gv2* q = reinterpret_cast<gv2*>(p);
+    if constexpr (NT)
+        __builtin_nontemporal_store(w, q);
+    else
+        *q = w;
 }
+
+// One complex value of HBM data at any 4-byte-aligned address.
+__device__ __forceinline__ cf ld_c(const cf* p) { return ld_data<false>(reinterpret_cast<const char*>(p)); }
+__device__ __forceinline__ void st_c(cf* p, cf v) { st_data<false>(reinterpret_cast<char*>(p), v); }
 
 template <int L, int E, int TPB>
 __device__ __forceinline__ void load_group(cf (&v)[1 << E], const cf* __restrict__ in, int64_t g, int64_t batch,

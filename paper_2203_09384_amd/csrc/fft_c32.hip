@@ -10,6 +10,7 @@
 // runs every pass in registers with LDS exchanges in between, and stores
 // X[t + m TPT] (natural order), multiplied by the plan's scale.
 #include "device_fft.hpp"
+#include "launch.hpp"
 #include "registry.hpp"
 
 #ifndef MIFFT_LOG2N
@@ -22,7 +23,7 @@ namespace {
 typedef float v4f __attribute__((ext_vector_type(4)));
 
 template <bool NT>
-__device__ __forceinline__ v4f ld_data4(const v4f* p)
+__device__ __forceinline__ v4f ld_data4(const gv4* p)
 {
     if constexpr (NT)
         return __builtin_nontemporal_load(p);
@@ -31,7 +32,7 @@ __device__ __forceinline__ v4f ld_data4(const v4f* p)
 }
 
 template <bool NT>
-__device__ __forceinline__ void st_data4(v4f* p, v4f v)
+__device__ __forceinline__ void st_data4(gv4* p, v4f v)
 {
     if constexpr (NT)
         __builtin_nontemporal_store(v, p);
@@ -59,7 +60,7 @@ __global__ __launch_bounds__(WG) void k_fft_c32(const cf* __restrict__ in, cf* _
         // consecutive elements, a single in-register DFT, no LDS.
         static_assert(SC::NP == 1, "single pass expected");
         if (live) {
-            const v4f* s4 = reinterpret_cast<const v4f*>(src);
+            const gv4* s4 = reinterpret_cast<const gv4*>(src);
 #pragma unroll
             for (int m = 0; m < EPT / 2; m++) {
                 const v4f q = ld_data4<NT>(s4 + m);
@@ -73,7 +74,7 @@ __global__ __launch_bounds__(WG) void k_fft_c32(const cf* __restrict__ in, cf* _
         }
         pass_compute<LOG2N, LOG2EPT, S, 0>(v, 0, tw);
         if (live) {
-            v4f* d4 = reinterpret_cast<v4f*>(dst);
+            gv4* d4 = reinterpret_cast<gv4*>(dst);
 #pragma unroll
             for (int m = 0; m < EPT / 2; m++) {
                 v4f q;
@@ -196,8 +197,8 @@ __global__ __launch_bounds__(WG) void k_fft_c32_st(const cf* __restrict__ in, cf
     const int64_t first = (int64_t)blockIdx.x * WG;
     const int64_t count = batch - first < WG ? batch - first : WG;  // transforms of this workgroup
     const int nv = (int)count * H;                                   // its 16-byte vectors
-    const v4f* src = reinterpret_cast<const v4f*>(in + first * N);
-    v4f* dst = reinterpret_cast<v4f*>(out + first * N);
+    const gv4* src = reinterpret_cast<const gv4*>(in + first * N);
+    gv4* dst = reinterpret_cast<gv4*>(out + first * N);
     v4f q[H];
     if (count == WG) {  // every load of the block issued before any is used
 #pragma unroll
@@ -263,8 +264,8 @@ __global__ __launch_bounds__(WG) void k_fft_c32_st2(const cf* __restrict__ in, c
     const int64_t first = (int64_t)blockIdx.x * TPB;
     const int64_t count = batch - first < TPB ? batch - first : TPB;
     const int nv = (int)count * H;
-    const v4f* src = reinterpret_cast<const v4f*>(in + first * N);
-    v4f* dst = reinterpret_cast<v4f*>(out + first * N);
+    const gv4* src = reinterpret_cast<const gv4*>(in + first * N);
+    gv4* dst = reinterpret_cast<gv4*>(out + first * N);
     constexpr int K = TPB * H / WG;  // vectors per thread = EPT / 2
     cf tws[NP][EPT];
 #pragma unroll
@@ -322,10 +323,9 @@ hipError_t launch_c32_st2(const void* in, void* out, const void*, const void* ro
 {
     constexpr int TPB = WG / Sched<L, E>::TPT;
     const int64_t grid = (batch + TPB - 1) / TPB;
-    hipLaunchKernelGGL((k_fft_c32_st2<L, E, WG, S>), dim3((unsigned)grid), dim3(WG), 0, stream,
+    return launch_kernel((k_fft_c32_st2<L, E, WG, S>), dim3((unsigned)grid), dim3(WG), 0, stream,
                        static_cast<const cf*>(in), static_cast<cf*>(out), static_cast<const cf*>(rows), batch,
                        scale);
-    return hipGetLastError();
 }
 
 template <int L, int WG, int S>
@@ -333,9 +333,8 @@ hipError_t launch_c32_st(const void* in, void* out, const void* tw, const void*,
                          int64_t, hipStream_t stream)
 {
     const int64_t grid = (batch + WG - 1) / WG;
-    hipLaunchKernelGGL((k_fft_c32_st<L, WG, S>), dim3((unsigned)grid), dim3(WG), 0, stream,
+    return launch_kernel((k_fft_c32_st<L, WG, S>), dim3((unsigned)grid), dim3(WG), 0, stream,
                        static_cast<const cf*>(in), static_cast<cf*>(out), static_cast<const cf*>(tw), batch, scale);
-    return hipGetLastError();
 }
 
 template <int LOG2N, int LOG2EPT, int WG, int S>
@@ -344,10 +343,9 @@ hipError_t launch_c32(const void* in, void* out, const void* tw, const void*, in
 {
     constexpr int TPB = WG / Sched<LOG2N, LOG2EPT>::TPT;
     const int64_t grid = (batch + TPB - 1) / TPB;
-    hipLaunchKernelGGL((k_fft_c32<LOG2N, LOG2EPT, WG, S>), dim3((unsigned)grid), dim3(WG), 0, stream,
+    return launch_kernel((k_fft_c32<LOG2N, LOG2EPT, WG, S>), dim3((unsigned)grid), dim3(WG), 0, stream,
                        static_cast<const cf*>(in), static_cast<cf*>(out), static_cast<const cf*>(tw), batch,
                        scale);
-    return hipGetLastError();
 }
 
 // grid_limit > 0 caps the number of (persistent) workgroups.
@@ -359,10 +357,9 @@ hipError_t launch_c32_v2(const void* in, void* out, const void*, const void* row
     int64_t grid = (batch + TPB - 1) / TPB;
     if (grid_limit > 0 && grid > grid_limit)
         grid = grid_limit;
-    hipLaunchKernelGGL((k_fft_c32_v2<L, E, WG, S, TW, PF, WAVE>), dim3((unsigned)grid), dim3(WG), 0, stream,
+    return launch_kernel((k_fft_c32_v2<L, E, WG, S, TW, PF, WAVE>), dim3((unsigned)grid), dim3(WG), 0, stream,
                        static_cast<const cf*>(in), static_cast<cf*>(out), static_cast<const cf*>(rows), batch,
                        scale);
-    return hipGetLastError();
 }
 
 template <int L, int E, int WG, int S, int TW, int PF, bool WAVE>

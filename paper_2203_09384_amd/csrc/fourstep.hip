@@ -18,6 +18,7 @@
 // w_N^j is built from a two-level FP32 table (w_N^{1024 a} and w_N^{b},
 // both from FP64 sincospi).
 #include "device_fft.hpp"
+#include "launch.hpp"
 #include "fourstep.hpp"
 #include "tile_fft.hpp"
 
@@ -56,7 +57,7 @@ __global__ __launch_bounds__(col_tile(L1)*((1 << L1) >> inner_e(L1))) void k_fou
     const cf* __restrict__ thi, int64_t ntiles)
 {
     constexpr int T = col_tile(L1), LT = T == 16 ? 4 : 3;
-    constexpr int E = inner_e(L1), N1 = 1 << L1, N2 = 1 << L2, N = N1 * N2;
+    constexpr int E = inner_e(L1), N1 = 1 << L1, N2 = 1 << L2;
     constexpr int EPT = 1 << E, TPT = N1 / EPT, WG = T * TPT, ST = stage_stride<L1, E>();
     constexpr bool DIRECT = col_direct(L1);
     static_assert(T == 16 || DIRECT, "8-column tiles load directly");
@@ -66,13 +67,11 @@ __global__ __launch_bounds__(col_tile(L1)*((1 << L1) >> inner_e(L1))) void k_fou
     if constexpr (T < 16) {
         // tiles 2i and 2i+1 share 128-byte lines: same XCD (blocks b, b + 8)
         const int64_t g = blockIdx.x;
-        tile = (g & ~int64_t(15)) + 2 * (g & 7) + ((g >> 3) & 1);
+        tile = idx::xcd_group_tile(g, 2);
     }
     if (tile >= ntiles)
         return;
-    const int64_t b = tile / (N2 / T);
     const int nb = (int)(tile % (N2 / T));
-    const cf* src = in + b * N + nb * T;
     // thread (tb, t): transform tb of the tile, thread t of that transform
     const int tb = DIRECT ? (tid & (T - 1)) : tid / TPT;
     const int t = DIRECT ? (tid >> LT) : tid % TPT;
@@ -81,14 +80,14 @@ __global__ __launch_bounds__(col_tile(L1)*((1 << L1) >> inner_e(L1))) void k_fou
     if constexpr (DIRECT) {
 #pragma unroll
         for (int m = 0; m < EPT; m++)
-            v[m] = src[(int64_t)(t + m * TPT) * N2 + tb];
+            v[m] = ld_c(in + idx::fourstep_col_in(tile, tb, t + m * TPT, L1, L2, T));
     } else {
         // stage: 16 consecutive columns per row n1 (one 128-byte line)
 #pragma unroll
         for (int i = 0; i < T * N1 / WG; i++) {
-            const int idx = tid + i * WG;
-            const int c = idx & (T - 1), n1 = idx >> LT;
-            lds[c * ST + n1] = src[(int64_t)n1 * N2 + c];
+            const int w = tid + i * WG;
+            const int c = w & (T - 1), n1 = w >> LT;
+            lds[c * ST + n1] = ld_c(in + idx::fourstep_col_in(tile, c, n1, L1, L2, T));
         }
         __syncthreads();
 #pragma unroll
@@ -113,12 +112,11 @@ __global__ __launch_bounds__(col_tile(L1)*((1 << L1) >> inner_e(L1))) void k_fou
     for (int m = 0; m < EPT; m++)
         my[t + m * TPT] = v[m];
     __syncthreads();
-    cf* dst = out + b * N + (int64_t)nb * T * N1;
 #pragma unroll
     for (int i = 0; i < T * N1 / WG; i++) {
-        const int idx = tid + i * WG;
-        const int c = idx / N1, k1 = idx % N1;
-        dst[idx] = lds[c * ST + k1];
+        const int w = tid + i * WG;
+        const int c = w / N1, k1 = w % N1;
+        st_c(out + idx::fourstep_col_out(tile, c, k1, L1, L2, T), lds[c * ST + k1]);
     }
 }
 
@@ -148,15 +146,14 @@ hipError_t launch_fourstep(const void* in, void* out, const void* rows1, const v
     constexpr int WG2 = TILE * ((1 << L2) >> inner_e(L2));
     const int64_t t1 = batch * ((1 << L2) / T1), g2 = batch * ((1 << L1) / TILE);
     const int64_t g1 = T1 < 16 ? (t1 + 15) & ~int64_t(15) : t1;  // whole chunks for the XCD pairing
-    hipLaunchKernelGGL((k_fourstep1<L1, L2, S>), dim3((unsigned)g1), dim3(WG1), 0, stream,
-                       static_cast<const cf*>(in), static_cast<cf*>(out), static_cast<const cf*>(rows1),
-                       static_cast<const cf*>(tlo), static_cast<const cf*>(thi), t1);
-    hipError_t e = hipGetLastError();
+    const hipError_t e = launch_kernel((k_fourstep1<L1, L2, S>), dim3((unsigned)g1), dim3(WG1), 0, stream,
+                                       static_cast<const cf*>(in), static_cast<cf*>(out),
+                                       static_cast<const cf*>(rows1), static_cast<const cf*>(tlo),
+                                       static_cast<const cf*>(thi), t1);
     if (e != hipSuccess)
         return e;
-    hipLaunchKernelGGL((k_fourstep2<L1, L2, S>), dim3((unsigned)g2), dim3(WG2), 0, stream, static_cast<cf*>(out),
+    return launch_kernel((k_fourstep2<L1, L2, S>), dim3((unsigned)g2), dim3(WG2), 0, stream, static_cast<cf*>(out),
                        static_cast<const cf*>(rows2), batch << L1, scale);
-    return hipGetLastError();
 }
 
 template <int L>
@@ -211,9 +208,8 @@ __global__ void k_twiddle_big(float2* __restrict__ lo, float2* __restrict__ hi, 
 hipError_t launch_twiddle_big(void* lo, void* hi, int L, hipStream_t stream)
 {
     const int total = 1024 + (1 << (L - 10));
-    hipLaunchKernelGGL(k_twiddle_big, dim3((total + 255) / 256), dim3(256), 0, stream, static_cast<float2*>(lo),
+    return launch_kernel(k_twiddle_big, dim3((total + 255) / 256), dim3(256), 0, stream, static_cast<float2*>(lo),
                        static_cast<float2*>(hi), L);
-    return hipGetLastError();
 }
 
 }  // namespace mifft

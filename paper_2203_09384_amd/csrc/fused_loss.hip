@@ -10,6 +10,7 @@
 // the forward passes a thread holds X[t + m N/EPT], exactly the layout the
 // adjoint's first pass loads.
 #include "device_fft.hpp"
+#include "launch.hpp"
 #include "fused_loss.hpp"
 
 #ifndef MIFFT_LOG2N
@@ -203,10 +204,9 @@ hipError_t launch_loss_grad(const void* x, const float* w, void* grad, float* lo
     int64_t grid = (batch + TPB - 1) / TPB;
     if (grid_limit > 0 && grid > grid_limit)
         grid = grid_limit;
-    hipLaunchKernelGGL((k_fft_loss_grad<L, E, WG, S>), dim3((unsigned)grid), dim3(WG), 0, stream,
+    return launch_kernel((k_fft_loss_grad<L, E, WG, S>), dim3((unsigned)grid), dim3(WG), 0, stream,
                        static_cast<const cf*>(x), w, static_cast<cf*>(grad), loss, static_cast<const cf*>(rows),
                        batch, scale);
-    return hipGetLastError();
 }
 
 template <int L, int E, int WG, int S>

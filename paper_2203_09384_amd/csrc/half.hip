@@ -34,6 +34,7 @@
 #include <vector>
 
 #include "device_fft.hpp"
+#include "launch.hpp"
 #include "half.hpp"
 
 namespace mifft {
@@ -241,14 +242,17 @@ __device__ __forceinline__ void half_transform(const HalfCtx& c, uint32_t (&cur)
     int e_max = 0;
     if (mx > 0.f && mx <= 3.4e38f)
         (void)frexpf(mx, &e_max);  // mx < 2^e_max
-    const float sc = ldexpf(1.0f, 4 - e_max);
+    // applied as an exponent shift of each value (v_ldexp_f32): exact, and
+    // unlike a multiply by 2^(4 - e_max) it cannot overflow when the
+    // transform's largest component is near the bottom of the format's range
+    const int sh = 4 - e_max;
     const int e_out = e_in + e_max - 4 + scale_log2;
     // outputs to the Stockham position d = 8 tid + r, scaled, as FP16 pairs
     // (pass B's twiddles are in its operands)
     uint32_t* wa = X + c.oWA;
 #pragma unroll
     for (int r = 0; r < 8; r++)
-        wa[r] = pack_f16(v[r].x * sc, v[r].y * sc);
+        wa[r] = pack_f16(ldexpf(v[r].x, sh), ldexpf(v[r].y, sh));
     __syncthreads();
 
     // ---- pass B: radix 16 (NS = 8) on MFMA.  Group g holds the 16 butterflies
@@ -301,20 +305,19 @@ __device__ __forceinline__ void half_transform(const HalfCtx& c, uint32_t (&cur)
             for (int i = 0; i < 4; i++)
                 wc[dWC[i]] = pack_store<BF>(yre[gg][i], yim[gg][i]);
         }
-    } else {  // unit scale
-        const float osc = ldexpf(1.0f, e_out);
+    } else {  // unit scale: the exponent applied to each value
 #pragma unroll
         for (int gg = 0; gg < 2; gg++) {
             uint32_t* wc = X + c.oWC[gg];
 #pragma unroll
             for (int i = 0; i < 4; i++)
-                wc[dWC[i]] = pack_store<BF>(yre[gg][i] * osc, yim[gg][i] * osc);
+                wc[dWC[i]] = pack_store<BF>(ldexpf(yre[gg][i], e_out), ldexpf(yim[gg][i], e_out));
         }
     }
     __syncthreads();
 
     // ---- store: 4 consecutive elements (16 bytes) per lane and instruction
-    v4u* dst = reinterpret_cast<v4u*>(out + b * HN);
+    gu4* dst = reinterpret_cast<gu4*>(out + b * HN);
 #pragma unroll
     for (int h = 0; h < 2; h++) {
         const uint32_t* rs = X + (h ? c.oRS1 : c.oRS0);
@@ -394,10 +397,9 @@ hipError_t launch_half(const void* in, const int32_t* in_exp, void* out, int32_t
                        int64_t batch, int scale_log2, int64_t grid_limit, hipStream_t stream)
 {
     const int64_t grid = grid_limit > 0 && batch > grid_limit ? grid_limit : batch;
-    hipLaunchKernelGGL((k_fft_half_2048<S, BF>), dim3((unsigned)grid), dim3(HWG), 0, stream,
+    return launch_kernel((k_fft_half_2048<S, BF>), dim3((unsigned)grid), dim3(HWG), 0, stream,
                        static_cast<const uint32_t*>(in), in_exp, static_cast<uint32_t*>(out), out_exp,
                        static_cast<const cf*>(tw), batch, scale_log2);
-    return hipGetLastError();
 }
 
 template <int S, bool BF>
@@ -555,6 +557,8 @@ void half_query(int64_t n, int64_t batch, fft_plan_desc* d)
         d->wg = k->wg;
         d->transforms_per_wg = k->wg / tpt;
         d->grid = (batch + d->transforms_per_wg - 1) / d->transforms_per_wg;
+        if (k->grid_cap > 0 && d->grid > k->grid_cap)
+            d->grid = k->grid_cap;  // the launch's cap: workgroups loop over groups
         const int rem = L % k->log2ept;
         int np = 0;
         if (rem)

@@ -18,7 +18,8 @@ struct KernelHalfSmall {
     int log2n, log2ept, wg, sign;
     bool bf16;
     LaunchHalfSmall fn;
-    int rows;  // twiddle-row entries (float2)
+    int rows;          // twiddle-row entries (float2)
+    int64_t grid_cap;  // > 0: at most this many workgroups, each looping over groups of transforms
 };
 void register_half_small(const KernelHalfSmall& k);
 

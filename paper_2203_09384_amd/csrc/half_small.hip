@@ -17,6 +17,7 @@
 #include <stdint.h>
 
 #include "device_fft.hpp"
+#include "launch.hpp"
 #include "half.hpp"
 
 #ifndef MIFFT_LOG2N
@@ -129,7 +130,7 @@ __device__ __forceinline__ void small_group(const uint32_t* __restrict__ in, con
     v4u q[K];
     cf v[EPT];
     if constexpr (STAGED) {
-        const v4u* src = reinterpret_cast<const v4u*>(in + first * N);
+        const gu4* src = reinterpret_cast<const gu4*>(in + first * N);
         if (count == TPB) {
 #pragma unroll
             for (int k = 0; k < K; k++)
@@ -157,12 +158,13 @@ __device__ __forceinline__ void small_group(const uint32_t* __restrict__ in, con
             v[m] = cf{h_to_f32<BF>(u & 0xffffu), h_to_f32<BF>(u >> 16)};
         }
     }
-    // normalise: largest component into [1/2, 1)
+    // normalise: largest component into [1/2, 1), as an exponent shift of
+    // each value (exact, and no overflow of a 2^-e_in factor when the
+    // largest component is near the bottom of the format's range)
     const int e_in = exp_above(group_max<TPT>(abs_max<E>(v)));
-    const float s_in = ldexpf(1.0f, -e_in);
 #pragma unroll
     for (int m = 0; m < EPT; m++)
-        v[m] = cscale(v[m], s_in);
+        v[m] = cf{ldexpf(v[m].x, -e_in), ldexpf(v[m].y, -e_in)};
     if constexpr (TPT == 1)
         pass_compute2<L, E, S, 0>(v, tws[0]);
     else
@@ -173,7 +175,7 @@ __device__ __forceinline__ void small_group(const uint32_t* __restrict__ in, con
     const int e_total = ein + e_in + e_o - 15 + scale_log2;  // logical = stored * 2^e_total
 #pragma unroll
     for (int m = 0; m < EPT; m++) {
-        const cf y = out_exp ? cscale(v[m], ldexpf(1.0f, 15 - e_o))
+        const cf y = out_exp ? cf{ldexpf(v[m].x, 15 - e_o), ldexpf(v[m].y, 15 - e_o)}
                              : cf{ldexpf(v[m].x, ein + e_in + scale_log2), ldexpf(v[m].y, ein + e_in + scale_log2)};
         const uint32_t u = f32_to_h<BF>(y.x) | (f32_to_h<BF>(y.y) << 16);
         if constexpr (STAGED)
@@ -185,7 +187,7 @@ __device__ __forceinline__ void small_group(const uint32_t* __restrict__ in, con
         out_exp[b] = e_total;
     if constexpr (STAGED) {
         __syncthreads();
-        v4u* dst = reinterpret_cast<v4u*>(out + first * N);
+        gu4* dst = reinterpret_cast<gu4*>(out + first * N);
 #pragma unroll
         for (int k = 0; k < K; k++) {
             const int w = 4 * (tid + WG * k);
@@ -242,10 +244,9 @@ hipError_t launch_half_small(const void* in, const int32_t* in_exp, void* out, i
     const int64_t ngroups = (batch + TPB - 1) / TPB;
     constexpr int64_t cap = small_persist_grid(L);
     const int64_t grid = small_persistent<L>() && ngroups > cap ? cap : ngroups;
-    hipLaunchKernelGGL((k_half_small<L, E, WG, S, BF>), dim3((unsigned)grid), dim3(WG), 0, stream,
+    return launch_kernel((k_half_small<L, E, WG, S, BF>), dim3((unsigned)grid), dim3(WG), 0, stream,
                        static_cast<const uint32_t*>(in), in_exp, static_cast<uint32_t*>(out), out_exp,
                        static_cast<const cf*>(rows), batch, scale_log2);
-    return hipGetLastError();
 }
 
 // One configuration per length: elements per thread and workgroup size.
@@ -257,10 +258,11 @@ void add_small()
 {
     constexpr int E = small_e(L), WG = small_wg(L), TPT = (1 << L) >> E;
     const int rows = TPT > 1 ? Layout2<L, E>::rows_total() : 0;
-    register_half_small(KernelHalfSmall{L, E, WG, -1, false, &launch_half_small<L, E, WG, -1, false>, rows});
-    register_half_small(KernelHalfSmall{L, E, WG, +1, false, &launch_half_small<L, E, WG, +1, false>, rows});
-    register_half_small(KernelHalfSmall{L, E, WG, -1, true, &launch_half_small<L, E, WG, -1, true>, rows});
-    register_half_small(KernelHalfSmall{L, E, WG, +1, true, &launch_half_small<L, E, WG, +1, true>, rows});
+    const int64_t cap = small_persistent<L>() ? small_persist_grid(L) : 0;
+    register_half_small(KernelHalfSmall{L, E, WG, -1, false, &launch_half_small<L, E, WG, -1, false>, rows, cap});
+    register_half_small(KernelHalfSmall{L, E, WG, +1, false, &launch_half_small<L, E, WG, +1, false>, rows, cap});
+    register_half_small(KernelHalfSmall{L, E, WG, -1, true, &launch_half_small<L, E, WG, -1, true>, rows, cap});
+    register_half_small(KernelHalfSmall{L, E, WG, +1, true, &launch_half_small<L, E, WG, +1, true>, rows, cap});
 }
 
 struct HalfSmallRegistrar {

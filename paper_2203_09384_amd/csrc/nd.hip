@@ -11,6 +11,7 @@
 // when TILE = 16).  Each transform runs the Stockham passes with its own
 // LDS region, and the result is written over the input.
 #include "device_fft.hpp"
+#include "launch.hpp"
 #include "nd.hpp"
 #include "tile_fft.hpp"
 
@@ -30,7 +31,7 @@ __global__ __launch_bounds__(axis_wg<L>()) void k_axis(cf* __restrict__ io, cons
         // ... of a chunk of 8 G blocks).
         constexpr int G = 16 / TILE;
         const int64_t b = blockIdx.x;
-        tile = (b & ~int64_t(8 * G - 1)) + G * (b & 7) + ((b >> 3) & (G - 1));
+        tile = idx::xcd_group_tile(b, G);
     }
     const int64_t q0 = tile * TILE;
     if (q0 >= count)
@@ -48,9 +49,8 @@ hipError_t launch_axis(void* io, const void* rows, int64_t count, int log2s, flo
     int64_t grid = (count + TILE - 1) / TILE;
     if (TILE < 16)
         grid = (grid + 127) & ~int64_t(127);  // whole chunks for the XCD grouping
-    hipLaunchKernelGGL((k_axis<L, S>), dim3((unsigned)grid), dim3(axis_wg<L>()), 0, stream, static_cast<cf*>(io),
+    return launch_kernel((k_axis<L, S>), dim3((unsigned)grid), dim3(axis_wg<L>()), 0, stream, static_cast<cf*>(io),
                        static_cast<const cf*>(rows), count, log2s, scale);
-    return hipGetLastError();
 }
 
 template <int L>

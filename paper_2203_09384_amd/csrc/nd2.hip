@@ -16,6 +16,7 @@
 //            a column's threads span wavefronts) and stores X[n0][c]
 //            straight to HBM: consecutive lanes, consecutive addresses.
 #include "device_fft.hpp"
+#include "launch.hpp"
 #include "nd2.hpp"
 
 #include <utility>
@@ -122,10 +123,9 @@ hipError_t launch_nd2(const void* in, void* out, const void* rows0, const void* 
 {
     using Z = Nd2Shape<L0, L1>;
     const int64_t grid = (batch + Z::AP - 1) / Z::AP;
-    hipLaunchKernelGGL((k_nd2<L0, L1, S>), dim3((unsigned)grid), dim3(Z::WG), 0, stream,
+    return launch_kernel((k_nd2<L0, L1, S>), dim3((unsigned)grid), dim3(Z::WG), 0, stream,
                        static_cast<const cf*>(in), static_cast<cf*>(out), static_cast<const cf*>(rows0),
                        static_cast<const cf*>(rows1), batch, scale);
-    return hipGetLastError();
 }
 
 template <int L0, int L1>

@@ -17,6 +17,7 @@
 // MI355X, which made them most of the launch); the static deal needs no
 // device state, so a launch replays from a hipGraph as it is.
 #include "device_fft.hpp"
+#include "launch.hpp"
 #include "ragged_kernel.hpp"
 
 #ifndef MIFFT_RAGGED_WG
@@ -38,16 +39,7 @@ constexpr int ragged_lds_elems()
             const int tpt = (1 << L) >> E;
             if (tpt < 2)
                 continue;
-            // region(): N + N >> B for the largest padding of the schedule
-            int reg = 1 << L;
-            const int rem = L % E;
-            const int np = L / E + (rem ? 1 : 0);
-            for (int p = 0; p + 1 < np; p++) {
-                const int B = pad_bits(L, E, p);
-                const int r = B == 0 ? (1 << L) : (1 << L) + ((1 << L) >> B);
-                reg = r > reg ? r : reg;
-            }
-            const int need = (WG / tpt) * reg;
+            const int need = (WG / tpt) * idx::region(L, E);
             m = need > m ? need : m;
         }
     return m > 0 ? m : 1;
@@ -135,8 +127,7 @@ __global__ __launch_bounds__(WG) void k_fft_ragged(RaggedArgs a)
 template <int WG, int MAXE, int S>
 hipError_t launch_ragged(const RaggedArgs& a, int grid, hipStream_t stream)
 {
-    hipLaunchKernelGGL((k_fft_ragged<WG, MAXE, S>), dim3(grid), dim3(WG), 0, stream, a);
-    return hipGetLastError();
+    return launch_kernel((k_fft_ragged<WG, MAXE, S>), dim3(grid), dim3(WG), 0, stream, a);
 }
 
 template <int WG, int MAXE, int S>

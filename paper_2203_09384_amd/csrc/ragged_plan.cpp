@@ -16,6 +16,7 @@
 #include <vector>
 
 #include "../../include/mifft.h"
+#include "index_maps.hpp"
 #include "ragged.hpp"
 #include "ragged_kernel.hpp"
 
@@ -40,21 +41,9 @@ std::vector<KernelRagged>& reg()
     return r;
 }
 
-// Rows of the twiddle table for a (log2 N, log2 EPT) schedule: NS * EPT
-// entries for every pass with NS > 1 (mirrors Layout2<>::rows_total()).
-int rows_total(int L, int E)
-{
-    if (((1 << L) >> E) < 2)
-        return 0;
-    const int rem = L % E;
-    const int np = L / E + (rem ? 1 : 0);
-    int total = 0;
-    for (int p = 1; p < np; p++) {
-        const int lns = rem ? rem + (p - 1) * E : p * E;
-        total += (1 << lns) << E;
-    }
-    return total;
-}
+// Rows of the twiddle table for a (log2 N, log2 EPT) schedule (none when
+// one thread holds the whole transform).
+int rows_total(int L, int E) { return ((1 << L) >> E) < 2 ? 0 : idx::rows_total(L, E); }
 
 // Built-in per-length log2 EPT (index = log2 N) and launch shape.  EPT 8
 // up to N = 2048 keeps the kernel at 62 VGPRs and 24 KiB of LDS, so every

@@ -23,6 +23,7 @@
 // (1/n, 1/n); the adjoints are the other direction with (1, 1/2) for the
 // adjoint of R2C and (1/n, 2/n) for the adjoint of C2R.
 #include "device_fft.hpp"
+#include "launch.hpp"
 #include "real.hpp"
 
 #ifndef MIFFT_LOG2M
@@ -101,7 +102,7 @@ __device__ __forceinline__ void r2c_group(cf (&v)[1 << E], cf* __restrict__ out,
         lds_sync<WAVE>();
 #pragma unroll
         for (int m = 0; m < EPT; m++)
-            zp[m] = my[(M - t - m * TPT) & (M - 1)];
+            zp[m] = my[idx::real_partner(M, t + m * TPT)];
     }
     const int64_t first = g * RS::TPB;
     if (first + tb >= batch)
@@ -140,7 +141,7 @@ __device__ __forceinline__ void c2r_group(cf (&v)[1 << E], cf vM, cf* __restrict
         lds_sync<WAVE>();
 #pragma unroll
         for (int m = 0; m < EPT; m++)
-            bp[m] = my[(M - t - m * TPT) & (M - 1)];
+            bp[m] = my[idx::real_partner(M, t + m * TPT)];
         if (t == 0)
             bp[0] = vM;
         lds_sync<WAVE>();  // partners read before the passes reuse LDS
@@ -270,9 +271,8 @@ template <int DIR>
 hipError_t launch_real_n2(const void* in, void* out, const void*, const void*, int64_t batch, float we, float wi,
                           int64_t, hipStream_t stream)
 {
-    hipLaunchKernelGGL((k_real_n2<DIR>), dim3((unsigned)((batch + 255) / 256)), dim3(256), 0, stream,
+    return launch_kernel((k_real_n2<DIR>), dim3((unsigned)((batch + 255) / 256)), dim3(256), 0, stream,
                        static_cast<const cf*>(in), static_cast<cf*>(out), batch, we, wi);
-    return hipGetLastError();
 }
 
 template <int L, int E, int WG, int DIR, int TW, int PF, bool WAVE>
@@ -283,10 +283,9 @@ hipError_t launch_real(const void* in, void* out, const void* rows, const void* 
     int64_t grid = (batch + TPB - 1) / TPB;
     if (PF && grid_limit > 0 && grid > grid_limit)
         grid = grid_limit;
-    hipLaunchKernelGGL((k_real<L, E, WG, DIR, TW, PF, WAVE>), dim3((unsigned)grid), dim3(WG), 0, stream,
+    return launch_kernel((k_real<L, E, WG, DIR, TW, PF, WAVE>), dim3((unsigned)grid), dim3(WG), 0, stream,
                        static_cast<const cf*>(in), static_cast<cf*>(out), static_cast<const cf*>(rows),
                        static_cast<const cf*>(wn), batch, we, wi);
-    return hipGetLastError();
 }
 
 template <int L, int E, int WG, int DIR, int TW, int PF, bool WAVE>

@@ -76,18 +76,18 @@ __device__ __forceinline__ void axis_tile_direct(cf* __restrict__ io, const cf* 
     const int tid = threadIdx.x, c = tid & (TILE - 1), t = tid >> LT;
     const int64_t q = q0 + c;
     const bool live = q < count;
-    const int64_t base = ((q >> log2s) << (L + log2s)) + (q & ((int64_t(1) << log2s) - 1));
+    const int64_t base = idx::axis_elem(q, 0, L, log2s);
     cf v[EPT];
 #pragma unroll
     for (int m = 0; m < EPT; m++)
-        v[m] = live ? io[base + ((int64_t)(t + m * TPT) << log2s)] : cf{0.f, 0.f};
+        v[m] = live ? ld_c(io + base + ((int64_t)(t + m * TPT) << log2s)) : cf{0.f, 0.f};
     TwRegs<L, E> tws;
     unit_rows<L, E>(tws);
     run2<L, E, S, 1, WAVE>(v, t, rows, tws, lds + c * ST);
     if (live) {
 #pragma unroll
         for (int m = 0; m < EPT; m++)
-            io[base + ((int64_t)(t + m * TPT) << log2s)] = cscale(v[m], scale);
+            st_c(io + base + ((int64_t)(t + m * TPT) << log2s), cscale(v[m], scale));
     }
 }
 
@@ -102,18 +102,14 @@ __device__ __forceinline__ void axis_tile_staged(cf* __restrict__ io, const cf* 
     constexpr int N = 1 << L, EPT = 1 << E, TPT = N / EPT, ST = stage_stride<L, E>(), WG = TILE * TPT;
     constexpr bool WAVE = TPT <= 64;
     const int tid = threadIdx.x;
-    const int64_t smask = (int64_t(1) << log2s) - 1;
     // element n of tile transform c
-    auto addr = [&](int c, int n) -> int64_t {
-        const int64_t q = q0 + c;
-        return ((q >> log2s) << (L + log2s)) + ((int64_t)n << log2s) + (q & smask);
-    };
+    auto addr = [&](int c, int n) -> int64_t { return idx::axis_elem(q0 + c, n, L, log2s); };
 #pragma unroll
     for (int i = 0; i < TILE * N / WG; i++) {
         const int idx = tid + i * WG;
         const int c = idx & (TILE - 1), n = idx >> LT;
         if (q0 + c < count)
-            lds[c * ST + n] = io[addr(c, n)];
+            lds[c * ST + n] = ld_c(io + addr(c, n));
     }
     __syncthreads();
     const int tb = tid / TPT, t = tid % TPT;
@@ -136,7 +132,7 @@ __device__ __forceinline__ void axis_tile_staged(cf* __restrict__ io, const cf* 
         const int idx = tid + i * WG;
         const int c = idx & (TILE - 1), n = idx >> LT;
         if (q0 + c < count)
-            io[addr(c, n)] = lds[c * ST + n];
+            st_c(io + addr(c, n), lds[c * ST + n]);
     }
 }
 

@@ -12,6 +12,8 @@
 // Eq. (twiddle).  Hence w^{m + 512} = -i w^m holds bit for bit and the
 // points at multiples of 1/8 turn are exact (to FP32 rounding of 1/sqrt 2).
 #include <hip/hip_runtime.h>
+#include "index_maps.hpp"
+#include "launch.hpp"
 #include <stdint.h>
 
 namespace mifft {
@@ -51,8 +53,7 @@ __global__ void k_twiddle_2048(float2* __restrict__ tw)
 
 hipError_t launch_twiddle_2048(void* tw, hipStream_t stream)
 {
-    hipLaunchKernelGGL(k_twiddle_2048, dim3(8), dim3(256), 0, stream, static_cast<float2*>(tw));
-    return hipGetLastError();
+    return launch_kernel(k_twiddle_2048, dim3(8), dim3(256), 0, stream, static_cast<float2*>(tw));
 }
 
 }  // namespace mifft
@@ -70,28 +71,15 @@ __global__ void k_twiddle_rows(const float2* __restrict__ tw, float2* __restrict
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= total)
         return;
-    const int rem = L % E;
-    const int np = L / E + (rem ? 1 : 0);
-    int off = 0;
-    for (int p = 0; p < np; p++) {
-        const int lns = p == 0 ? 0 : (rem ? rem + (p - 1) * E : p * E);
-        if (lns == 0)
-            continue;
-        const int size = (1 << lns) << E;
-        if (i < off + size) {
-            const int k = (i - off) >> E;
-            const int r = (i - off) & ((1 << E) - 1);
-            const int shift = 11 - lns - E;
-            if (shift >= 0) {
-                rows[i] = tw[(r * k) << shift];
-            } else {
-                double sn, cs;
-                sincospi(2.0 * (double)(r * k) / (double)(1 << (lns + E)), &sn, &cs);
-                rows[i] = float2{(float)cs, (float)(-sn)};
-            }
-            return;
-        }
-        off += size;
+    const idx::RowEntry w = idx::twiddle_row_entry(L, E, i);
+    if (w.pass < 0)
+        return;
+    if (w.table >= 0) {
+        rows[i] = tw[w.table];
+    } else {
+        double sn, cs;
+        sincospi(2.0 * (double)(w.r * w.k) / (double)(1 << w.mlog2), &sn, &cs);
+        rows[i] = float2{(float)cs, (float)(-sn)};
     }
 }
 
@@ -99,9 +87,8 @@ hipError_t launch_twiddle_rows(const void* tw, void* rows, int L, int E, int tot
 {
     if (total <= 0)
         return hipSuccess;
-    hipLaunchKernelGGL(k_twiddle_rows, dim3((total + 255) / 256), dim3(256), 0, stream,
+    return launch_kernel(k_twiddle_rows, dim3((total + 255) / 256), dim3(256), 0, stream,
                        static_cast<const float2*>(tw), static_cast<float2*>(rows), L, E, total);
-    return hipGetLastError();
 }
 
 }  // namespace mifft
@@ -128,9 +115,8 @@ __global__ void k_twiddle_real(const float2* __restrict__ tw, float2* __restrict
 hipError_t launch_twiddle_real(const void* tw, void* wn, int log2n, hipStream_t stream)
 {
     const int m = 1 << (log2n - 1);
-    hipLaunchKernelGGL(k_twiddle_real, dim3((m + 255) / 256), dim3(256), 0, stream, static_cast<const float2*>(tw),
+    return launch_kernel(k_twiddle_real, dim3((m + 255) / 256), dim3(256), 0, stream, static_cast<const float2*>(tw),
                        static_cast<float2*>(wn), log2n);
-    return hipGetLastError();
 }
 
 }  // namespace mifft
@@ -213,14 +199,13 @@ hipError_t launch_real_split(int dir, const void* src, void* dst, const void* tl
     const int64_t kblocks = (((int64_t(1) << log2m) / 2 + 1) + 255) / 256;
     const dim3 grid((unsigned)(kblocks * batch));
     if (dir == 0)
-        hipLaunchKernelGGL(k_real_split<0>, grid, dim3(256), 0, stream, static_cast<const cf2*>(src),
+        return launch_kernel(k_real_split<0>, grid, dim3(256), 0, stream, static_cast<const cf2*>(src),
                            static_cast<cf2*>(dst), static_cast<const cf2*>(tlo), static_cast<const cf2*>(thi), log2m,
                            kblocks, we, wi);
     else
-        hipLaunchKernelGGL(k_real_split<1>, grid, dim3(256), 0, stream, static_cast<const cf2*>(src),
+        return launch_kernel(k_real_split<1>, grid, dim3(256), 0, stream, static_cast<const cf2*>(src),
                            static_cast<cf2*>(dst), static_cast<const cf2*>(tlo), static_cast<const cf2*>(thi), log2m,
                            kblocks, we, wi);
-    return hipGetLastError();
 }
 
 }  // namespace mifft

@@ -18,7 +18,9 @@ STATUS = {
     0: "FFT_OK", 1: "FFT_EINVAL_N", 2: "FFT_EINVAL_BATCH", 3: "FFT_EINVAL_SIGN",
     4: "FFT_EINVAL_DTYPE", 5: "FFT_ENULL", 6: "FFT_EOVERLAP", 7: "FFT_EINVAL_OFFSETS",
     8: "FFT_EHIP", 9: "FFT_ENOMEM", 10: "FFT_EINVAL_CONFIG", 11: "FFT_EALIGN", 12: "FFT_EDEVICE",
+    13: "FFT_ECAPTURE",
 }
+FFT_ECAPTURE = 13
 EXPORTS = [
     "fft_plan_create", "fft_plan_create_config", "fft_plan_create_ragged",
     "fft_plan_create_ragged_config", "fft_execute", "fft_execute_adjoint",

@@ -178,7 +178,8 @@ def tune_ragged(count: int = 4096, iters: int = 300, log=print):
         return ms
 
     record, best = [], None
-    for wg in (64, 128, 256):
+    # a length's threads (at most 16 points each) must fit the workgroup
+    for wg in [w for w in (64, 128, 256) if int(lengths.max()) // 16 <= w]:
         table = [0, 2, 4, 8, 4, 4, 4, 8, 8, 8, 8, 8]
         cur = cost(table, wg)
         for _ in range(2):

@@ -1,0 +1,83 @@
+// Host build of the kernels' index maps (paper_2203_09384_amd/csrc/index_maps.hpp)
+// for the CPU tests: thin extern "C" wrappers, bulk where the tests sweep
+// every index.  No GPU code, no arithmetic of the transform itself.
+#include <stdint.h>
+
+#include "index_maps.hpp"
+
+using namespace mifft::idx;
+
+extern "C" {
+
+int im_np(int L, int E) { return sched_np(L, E); }
+int im_log2r(int L, int E, int p) { return sched_log2r(L, E, p); }
+int im_log2ns(int L, int E, int p) { return sched_log2ns(L, E, p); }
+
+// out[j * R + r] = destination of output r of butterfly j in pass p
+void im_pass_dsts(int L, int E, int p, int* out)
+{
+    const int R = 1 << sched_log2r(L, E, p), nb = (1 << L) / R;
+    for (int j = 0; j < nb; j++)
+        for (int r = 0; r < R; r++)
+            out[j * R + r] = stockham_dst(L, E, p, j, r);
+}
+
+int im_rows_offset(int L, int E, int P) { return rows_offset(L, E, P); }
+int im_rows_total(int L, int E) { return rows_total(L, E); }
+
+// out[5 i .. 5 i + 4] = (pass, r, k, mlog2, table) of row entry i, i < count
+void im_row_entries(int L, int E, int count, int* out)
+{
+    for (int i = 0; i < count; i++) {
+        const RowEntry w = twiddle_row_entry(L, E, i);
+        out[5 * i] = w.pass;
+        out[5 * i + 1] = w.r;
+        out[5 * i + 2] = w.k;
+        out[5 * i + 3] = w.mlog2;
+        out[5 * i + 4] = w.table;
+    }
+}
+
+int im_pad_bits(int L, int E, int P) { return pad_bits(L, E, P); }
+int im_pad_index(int B, int d) { return pad_index(B, d); }
+int im_region(int L, int E) { return region(L, E); }
+int im_pad_is_affine(int L, int E, int P, int B) { return pad_is_affine(L, E, P, B) ? 1 : 0; }
+void im_strides(int L, int E, int P, int* out)
+{
+    const Strides s = exchange_strides(L, E, P);
+    out[0] = s.B;
+    out[1] = s.DR;
+    out[2] = s.DQ;
+    out[3] = s.DM;
+}
+
+void im_xcd_group_tiles(int64_t n, int G, int64_t* out)
+{
+    for (int64_t b = 0; b < n; b++)
+        out[b] = xcd_group_tile(b, G);
+}
+
+// out[q * N + n] = axis_elem(q, n), q < count, n < N = 2^L
+void im_axis_elems(int64_t count, int L, int log2s, int64_t* out)
+{
+    for (int64_t q = 0; q < count; q++)
+        for (int64_t n = 0; n < (int64_t(1) << L); n++)
+            out[(q << L) + n] = axis_elem(q, n, L, log2s);
+}
+
+// column pass of the four-step split: out_in[(tile, c, n1)] and out_out[(tile, c, k1)]
+void im_fourstep_cols(int64_t ntiles, int L1, int L2, int T, int64_t* out_in, int64_t* out_out)
+{
+    const int N1 = 1 << L1;
+    for (int64_t t = 0; t < ntiles; t++)
+        for (int c = 0; c < T; c++)
+            for (int n = 0; n < N1; n++) {
+                const int64_t i = (t * T + c) * N1 + n;
+                out_in[i] = fourstep_col_in(t, c, n, L1, L2, T);
+                out_out[i] = fourstep_col_out(t, c, n, L1, L2, T);
+            }
+}
+
+int im_real_partner(int M, int k) { return real_partner(M, k); }
+
+}  // extern "C"

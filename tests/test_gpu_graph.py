@@ -139,3 +139,59 @@ def test_one_plan_on_two_streams():
     torch.cuda.synchronize()
     for o, r in zip(outs, refs):
         assert torch.equal(o, r)
+
+
+def test_plan_creation_during_capture_is_refused():
+    """Plan creation allocates and waits for its tables, which no capture can
+    hold.  The binding refuses an uncached shape under capture before
+    touching the device (the capture itself stays valid and replays), and
+    the C ABI called directly during a capture returns NULL with
+    FFT_ECAPTURE; plans created afterwards work as usual."""
+    import ctypes
+    import oracle
+    from paper_2203_09384_amd import native
+    from paper_2203_09384_amd.native import MifftError
+    from gpu_util import per_transform_relerr
+    n, batch = 512, 8
+    x = to_gpu(synth.uniform_complex(41, (batch, n)))
+    y = torch.empty_like(x)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    # 1. the binding: an uncached shape inside a capture
+    api._cache.pop((torch.cuda.current_device(), n // 4, batch * 4, -1, "c32"), None)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        y.copy_(x)
+        with pytest.raises(MifftError) as ei:
+            api.fft(x.view(batch * 4, n // 4))  # no plan cached for (128, 32)
+        y.mul_(2.0)
+    assert ei.value.status == "FFT_ECAPTURE"
+    y.zero_()
+    g.replay()
+    torch.cuda.synchronize()
+    assert torch.equal(y, 2.0 * x)
+    # 2. the C ABI directly, inside a capture
+    L = native.lib()
+    g2 = torch.cuda.CUDAGraph()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        g2.capture_begin()
+        try:
+            h = L.fft_plan_create(n, batch, -1, 0)
+            rc, msg = L.fft_last_error(), L.fft_last_error_string().decode()
+        finally:
+            try:
+                g2.capture_end()
+            except RuntimeError as e:  # the runtime may have invalidated the capture
+                print("capture end:", e)
+    torch.cuda.synchronize()
+    print(f"[case] plan create under capture: handle={h} status={rc} {msg!r}", flush=True)
+    if h:
+        L.fft_plan_destroy(h)
+    assert not h and native.STATUS.get(rc) == "FFT_ECAPTURE", (rc, msg)
+    # 3. afterwards the library works as usual
+    p = api.Plan(n, batch, -1)
+    out = p.execute(x)
+    ref = oracle.forward(x.cpu().numpy().astype(np.complex128))
+    assert per_transform_relerr(out.cpu().numpy(), ref) <= 1e-5

@@ -102,22 +102,39 @@ def test_graph_replay_matches_eager():
         p.execute(xg)              # and an eager launch of the same plan
 
 
+DEFAULT_EPT = [0, 2, 4, 8, 4, 4, 4, 8, 8, 8, 8, 8]  # the built-in per-length choice
+
+
 @pytest.mark.parametrize("wg", [64, 128, 256])
 @pytest.mark.parametrize("table", ["small", "default", "large"])
 def test_forced_configs(wg, table):
+    """Every compiled workgroup size with small, default and large elements
+    per thread.  A length's threads (2^L / ept) must fit one workgroup, so
+    the workload's longest length is the largest that the (wg, table) pair
+    holds: 64-thread kernels run lengths up to 256..1024, the others to
+    512..2048.  No case is skipped."""
     eps = {"small": [0, 2, 4, 4, 4, 4, 4, 4, 4, 4, 4, 4],
            "default": None,
            "large": [0, 2, 4, 8, 16, 16, 16, 16, 16, 16, 16, 16]}[table]
-    off, x = workload(800, 1, 11, seed=19)
-    try:
-        p = api.RaggedPlan(off, -1, ept_by_log2n=eps, wg=wg)
-    except MifftError as e:
-        assert e.status == "FFT_EINVAL_CONFIG"
-        pytest.skip(str(e))
-    print(f"[case] ragged wg={wg} table={table} {p.describe()}", flush=True)
+    table_e = eps or DEFAULT_EPT
+    hi = max(L for L in range(1, 12) if (1 << L) // table_e[L] <= wg)
+    off, x = workload(800, 1, hi, seed=19)
+    p = api.RaggedPlan(off, -1, ept_by_log2n=eps, wg=wg)
+    d = p.describe()
+    print(f"[case] ragged wg={wg} table={table} lengths 2..{1 << hi} {d}", flush=True)
+    assert d["wg"] == wg
     y = to_cpu(p.execute(to_gpu(x)))
     ref = oracle.fft_ragged(x.astype(np.complex128), off, -1)
     assert max_seg_err(y, ref, off) <= TOL
+
+
+def test_too_long_for_the_workgroup_is_refused():
+    """A 2048-point length needs at least 128 threads (16 per thread at
+    most): a 64-thread launch is refused at planning."""
+    off, _ = workload(50, 11, 11, seed=21)
+    with pytest.raises(MifftError) as ei:
+        api.RaggedPlan(off, -1, wg=64)
+    assert ei.value.status == "FFT_EINVAL_CONFIG"
 
 
 def test_single_transform_and_ctas_limit():
