@@ -14,9 +14,12 @@ Prints ONE JSON line.  Times come from HIP events recorded on the stream
 the kernels are launched on (torch's current stream).
 """
 import argparse
+import ctypes
+import hashlib
 import json
 import math
 import os
+import subprocess
 import sys
 import time
 
@@ -27,6 +30,40 @@ if ROOT not in sys.path:
 HBM_PEAK_GBPS = 8000.0
 METRIC = "FP32 C2C FFT GFLOP/s (5NlogN) & HBM GB/s at N=2048; fwd+adjoint vs plain fwd"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_fft_c32_n2048_b32768.json")
+COPY_LIB = os.path.join(ROOT, "paper_2203_09384_amd", "libstreamcopy.so")
+
+
+def tune_table_id():
+    """Which variant table the library plans with: the built-in one, or a
+    hash of the file named by MIFFT_TUNE_TABLE."""
+    path = os.environ.get("MIFFT_TUNE_TABLE", "")
+    if not path:
+        return "builtin"
+    with open(path, "rb") as f:
+        return "file:" + hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def read_clocks():
+    """Current GPU clocks as rocm-smi reports them (another process; no
+    effect on the run), or the error."""
+    try:
+        r = subprocess.run(["rocm-smi", "--showclocks", "--json"], capture_output=True, text=True, timeout=30)
+        d = json.loads(r.stdout)
+        card = d.get("card0") or next(iter(d.values()))
+        return {k.strip(" :"): v for k, v in card.items() if "clk" in k.lower()}
+    except Exception as e:  # noqa: BLE001
+        return {"error": f"{type(e).__name__}: {str(e)[:120]}"}
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def log(msg):
@@ -95,36 +132,98 @@ def cpu_baseline(n, batch, budget_s=12.0):
     return {"value": round(flops / dt / 1e9, 3), "unit": "GFLOP/s", "cores": threads, "kind": "oracle",
             "sample": f"{done} forward transforms of N={n} (the first {chunk} transforms of the headline "
                       f"batch, repeated; FP64 recursive radix-2 on {threads} threads, {dt:.1f} s)",
-            "seconds": round(dt, 2)}
+            "seconds": round(dt, 2), "cpu_model": cpu_model(), "host_cpus": os.cpu_count()}
 
 
-def bench_half(api, synth, torch, dev, steps, ms_fp32, x_all):
+def half_accuracy(samples):
+    """Per-transform relative L2 of the FP16/BF16 results against the FP64
+    oracle on the stored input (and on the raw FP64 draw), per dtype and
+    input class, over the sampled transforms the half section kept."""
+    import numpy as np
+    import oracle
+    res = {}
+    for (dt, cls), (x_stored, x_raw, y) in samples.items():
+        def worst(ref):
+            return float(np.max(np.linalg.norm(y - ref, axis=-1) / np.linalg.norm(ref, axis=-1)))
+        res.setdefault(dt, {})[cls] = {"max_rel_l2_vs_stored_input": worst(oracle.forward(x_stored)),
+                                       "max_rel_l2_vs_raw_draw": worst(oracle.forward(x_raw)),
+                                       "transforms": int(y.shape[0])}
+    return res
+
+
+def bench_half(api, synth, torch, dev, steps, ms_fp32, x_all, samples=None):
     """FP16 / BF16 block-floating-point forward FFT, N = 2048, batch 32768,
-    against the FP32 kernel at the same shape (ms_fp32)."""
+    against the FP32 kernel at the same shape (ms_fp32), for both input
+    classes (re, im uniform[-1, 1); magnitude log-uniform in [1e-3, 1e3] with
+    uniform phase).  Sampled transforms (inputs as stored, raw draws and
+    de-scaled outputs) go to `samples` for the accuracy check against the
+    FP64 oracle, outside the timed region."""
+    import numpy as np
     n, batch = 2048, 32768
     res = {"workload": "C2C forward FFT, N=2048, batch 32768, FP16/BF16 storage (4 B per element), "
-                       "per-transform int32 exponents, radix-16 passes on MFMA"}
+                       "per-transform int32 exponents, radix-16 passes on MFMA; classes: uniform[-1,1) re/im, "
+                       "log-uniform magnitude 1e-3..1e3 with uniform phase"}
+    rng = np.random.default_rng(20220320)
+    idx = np.unique(np.concatenate([[0, batch - 1], rng.integers(0, batch, 126)]))
     for dt, tdt in (("c16", torch.float16), ("cbf16", torch.bfloat16)):
-        xh = torch.view_as_real(x_all.view(batch, n)).to(tdt).contiguous()
-        yh = torch.empty_like(xh)
-        ex = torch.empty(batch, dtype=torch.int32, device=dev)
-        p = api.Plan(n, batch, -1, dtype=dt)
-        m = time_launches(lambda: p.execute_scaled(xh, out=yh, out_exp=ex), steps, 20, torch)
-        alg = 8.0 * n * batch + 4.0 * batch
-        res[dt] = {"us": round(m * 1e3, 2), "GBps": round(alg / (m * 1e-3) / 1e9, 1),
-                   "GFLOPs": round(5.0 * n * 11 * batch / (m * 1e-3) / 1e9, 1),
-                   "speedup_vs_fp32": round(ms_fp32 / m, 3)}
-        # a short length (FP32 passes with 16-bit storage), same bytes
-        ns, bs = 256, batch * 8
-        ps = api.Plan(ns, bs, -1, dtype=dt)
-        xs, ys = xh.view(bs, ns, 2), yh.view(bs, ns, 2)
-        exs = torch.empty(bs, dtype=torch.int32, device=dev)
-        ms_s = time_launches(lambda: ps.execute_scaled(xs, out=ys, out_exp=exs), steps, 20, torch)
-        res[dt]["n256_batch262144"] = {"us": round(ms_s * 1e3, 2),
-                                       "GBps": round((8.0 * ns * bs + 4.0 * bs) / (ms_s * 1e-3) / 1e9, 1)}
-        ps.close()
-        del xh, yh
+        res[dt] = {}
+        for cls in ("uniform", "loguniform"):
+            if cls == "uniform":
+                xc = x_all.view(batch, n)
+                raw = None
+            else:
+                raw = synth.log_uniform_polar(synth.SEED_HALF, (batch, n), key=(1, 1))
+                xc = torch.from_numpy(raw.astype(np.complex64)).to(dev)
+            xh = torch.view_as_real(xc).to(tdt).contiguous()
+            yh = torch.empty_like(xh)
+            ex = torch.empty(batch, dtype=torch.int32, device=dev)
+            p = api.Plan(n, batch, -1, dtype=dt)
+            m = time_launches(lambda: p.execute_scaled(xh, out=yh, out_exp=ex), steps, 20, torch)
+            alg = 8.0 * n * batch + 4.0 * batch
+            res[dt][cls] = {"us": round(m * 1e3, 2), "GBps": round(alg / (m * 1e-3) / 1e9, 1),
+                            "GFLOPs": round(5.0 * n * 11 * batch / (m * 1e-3) / 1e9, 1),
+                            "speedup_vs_fp32": round(ms_fp32 / m, 3)}
+            if samples is not None:
+                it = torch.from_numpy(idx).to(dev)
+                xs = xh[it].float().cpu().numpy().astype(np.float64)
+                ys = yh[it].float().cpu().numpy().astype(np.float64)
+                e = np.exp2(ex[it].cpu().numpy().astype(np.float64))[:, None]
+                x_raw = (x_all.view(batch, n)[it].cpu().numpy().astype(np.complex128) if raw is None
+                         else raw[idx])
+                samples[(dt, cls)] = (xs[..., 0] + 1j * xs[..., 1], x_raw, (ys[..., 0] + 1j * ys[..., 1]) * e)
+            p.close()
+            del xh, yh
+        # the headline figures of this dtype: the uniform class
+        res[dt].update({k: res[dt]["uniform"][k] for k in ("us", "GBps", "GFLOPs", "speedup_vs_fp32")})
     return res
+
+
+def bench_copy(torch, x_all, y_all, steps, warmup):
+    """The practical HBM ceiling: a hand-written 512 MiB streaming copy
+    (16-byte nontemporal loads and stores, several workgroup shapes; the
+    best is reported), and torch's elementwise copy for reference."""
+    lib = ctypes.CDLL(COPY_LIB)
+    lib.stream_copy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_void_p]
+    lib.stream_copy_shape.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
+    nbytes = x_all.numel() * x_all.element_size()
+    st = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    shapes = {}
+    for i in range(lib.stream_copy_shapes()):
+        wg, k = ctypes.c_int(), ctypes.c_int()
+        lib.stream_copy_shape(i, ctypes.byref(wg), ctypes.byref(k))
+
+        def run():
+            rc = lib.stream_copy(ctypes.c_void_p(x_all.data_ptr()), ctypes.c_void_p(y_all.data_ptr()), nbytes, i, st)
+            if rc != 0:
+                raise RuntimeError(f"stream_copy shape {i} failed: {rc}")
+        ms = time_launches(run, steps, warmup, torch)
+        shapes[f"wg{wg.value}_k{k.value}"] = round(2.0 * nbytes / (ms * 1e-3) / 1e9, 1)
+    ms_t = time_launches(lambda: torch.mul(x_all, 1.0, out=y_all), steps, warmup, torch)
+    assert torch.equal(x_all, y_all)
+    return {"GBps": max(shapes.values()), "shapes_GBps": shapes,
+            "torch_elementwise_GBps": round(2.0 * nbytes / (ms_t * 1e-3) / 1e9, 1),
+            "bytes_each_way": nbytes,
+            "kernel": "k_stream_copy<WG, K>: K 16-byte nontemporal vectors per thread, 1 KiB per wave instruction"}
 
 
 def bench_real(api, torch, dev, steps, x_all):
@@ -272,11 +371,15 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--only-headline", action="store_true",
-                    help="time only the headline kernel (for profiler runs)")
+    ap.add_argument("--only", choices=["headline", "half", "loss", "copy", "large", "nd"], default=None,
+                    help="time one section only (for profiler runs); 'headline' with --with-copy also runs "
+                         "the streaming copy (counter calibration)")
+    ap.add_argument("--only-headline", action="store_true", help="same as --only headline")
     ap.add_argument("--with-copy", action="store_true",
-                    help="with --only-headline: also run the 512 MiB copy kernel (counter calibration)")
+                    help="with --only headline: also run the 512 MiB streaming copy (counter calibration)")
     args = ap.parse_args()
+    if args.only_headline:
+        args.only = "headline"
     if args.gpus != 1:
         print(f"bench.py measures one GPU: the batched transforms are independent, so the path "
               f"has no multi-GPU step to run here (got --gpus {args.gpus}).", file=sys.stderr)
@@ -303,9 +406,14 @@ def main():
     y_all = torch.empty_like(x_all)
     x = x_all.view(batch, n)
     y = y_all.view(batch, n)
+    only = args.only
+    if only in ("half", "loss", "copy", "large", "nd"):
+        run_section(only, args, api, synth, torch, dev, x_all, y_all)
+        return
     plan = api.Plan(n, batch, -1)
     desc = plan.describe()
     log(f"[bench] headline plan {desc}")
+    clocks_before = read_clocks()
     # settle clocks: about half a second of the same kernel before timing
     t_end = time.perf_counter() + 0.5
     while time.perf_counter() < t_end:
@@ -313,6 +421,7 @@ def main():
             plan.execute(x, y)
         torch.cuda.synchronize()
     ms = time_launches(lambda: plan.execute(x, y), args.steps, args.warmup, torch)
+    clocks_after = read_clocks()
     bytes_alg = 16.0 * total
     gbps = bytes_alg / (ms * 1e-3) / 1e9
     gflops = 5.0 * n * math.log2(n) * batch / (ms * 1e-3) / 1e9
@@ -328,74 +437,45 @@ def main():
                    "variant": desc["variant"], "grid": desc["grid"],
                    "radices": desc["radices"], "seed": synth.SEED_PLAIN},
     }
+    # measured HBM traffic, when profiles/ holds counters taken for this very
+    # kernel instance, these sources and this variant table
     traffic = None
-    khash = kernel_hash()
+    khash, kname, table = kernel_hash(), kernel_name(desc), tune_table_id()
+    traffic_note = "no counter record"
     if os.path.exists(TRAFFIC_FILE):
         with open(TRAFFIC_FILE) as f:
             tr = json.load(f)
-        if tr.get("kernel_hash") == khash:
+        key = (tr.get("kernel_instance"), tr.get("kernel_hash"), tr.get("tune_table"))
+        if key == (kname, khash, table):
             traffic = tr.get("bytes_per_launch")
+            traffic_note = "counters of this kernel instance, sources and variant table"
+        else:
+            traffic_note = f"counter record is for {key}, not ({kname}, {khash}, {table})"
     out["roofline"] = {"bound": "hbm", "achieved": round(gbps, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                        "frac": round(gbps / HBM_PEAK_GBPS, 4), "traffic": traffic,
-                       "kernel": kernel_name(desc), "kernel_hash": khash,
-                       "algorithmic_bytes_per_launch": bytes_alg}
+                       "kernel": kname, "kernel_hash": khash, "tune_table": table,
+                       "traffic_note": traffic_note, "algorithmic_bytes_per_launch": bytes_alg}
     out["headline_distribution"] = per_call_distribution(lambda: plan.execute(x, y), 50, torch)
     out["gflops_fwd_2048"] = round(gflops, 1)
     out["gbps_fwd_2048"] = round(gbps, 1)
+    out["clocks"] = {"before_headline": clocks_before, "after_headline": clocks_after}
+    out["host"] = {"cpu_model": cpu_model(), "cpus": os.cpu_count(), "gpu": props.name,
+                   "arch": getattr(props, "gcnArchName", ""), "cus": props.multi_processor_count}
 
-    if args.only_headline and args.with_copy:
-        for _ in range(args.steps):
-            torch.mul(x_all, 1.0, out=y_all)
-        torch.cuda.synchronize()
+    if only == "headline" and args.with_copy:
+        bench_copy(torch, x_all, y_all, args.steps, args.warmup)
+    half_samples = {}
 
-    if not args.only_headline:
+    if only is None:
         # ------------------------------------------------------------ copy ceiling
-        ms_copy = time_launches(lambda: torch.mul(x_all, 1.0, out=y_all), args.steps, args.warmup, torch)
-        out["copy_ceiling_GBps"] = round(bytes_alg / (ms_copy * 1e-3) / 1e9, 1)
-        log(f"[bench] copy 512 MiB: {out['copy_ceiling_GBps']} GB/s")
+        copy = bench_copy(torch, x_all, y_all, args.steps, args.warmup)
+        out["copy_ceiling_GBps"] = copy["GBps"]
+        out["copy_ceiling"] = copy
+        log(f"[bench] copy 512 MiB: {copy}")
 
         # ------------------------------------------------------------ fwd + adjoint
-        nb = 16384
-        xa = x_all[: nb * n].view(nb, n)
-        ya = y_all[: nb * n].view(nb, n)
-        za = torch.empty_like(xa)
-        pa = api.Plan(n, nb, -1)
-        ms_f = time_launches(lambda: pa.execute(xa, ya), args.steps, args.warmup, torch)
-
-        def fa():
-            pa.execute(xa, ya)
-            pa.adjoint(ya, za)
-        ms_fa = time_launches(fa, args.steps, args.warmup, torch)
-        b1 = 16.0 * nb * n
-        w = torch.from_numpy(synth.uniform_weights(synth.SEED_AUTOGRAD, (nb, n))).to(dev)
-        xg = xa.clone().requires_grad_(True)
-
-        def step():
-            xg.grad = None
-            yy = api.fft_differentiable(xg)
-            loss = (w * (yy.real ** 2 + yy.imag ** 2)).sum()
-            loss.backward()
-        ms_step = time_launches(step, max(20, args.steps // 5), 3, torch)
-        lossv = torch.empty(nb, dtype=torch.float32, device=dev)
-        ms_fused = time_launches(lambda: pa.loss_grad(xa, w, za, lossv), args.steps, args.warmup, torch)
-
-        def fused_step():
-            xg.grad = None
-            api.weighted_power_loss(xg, w).backward()
-        ms_fused_step = time_launches(fused_step, max(20, args.steps // 5), 3, torch)
-        out["fwd_adjoint"] = {
-            "workload": "N=2048 batch 16384 (256 MiB per pass)",
-            "fwd_ms": round(ms_f, 5), "fwd_GBps": round(b1 / (ms_f * 1e-3) / 1e9, 1),
-            "fwd_adj_ms": round(ms_fa, 5), "fwd_adj_GBps": round(2 * b1 / (ms_fa * 1e-3) / 1e9, 1),
-            "ratio_fwd_adj_over_fwd": round(ms_fa / ms_f, 3),
-            "autograd_step_ms": round(ms_step, 5),
-            "fused_loss_grad_ms": round(ms_fused, 5),
-            "fused_loss_grad_GBps": round((20.0 * nb * n + 4.0 * nb) / (ms_fused * 1e-3) / 1e9, 1),
-            "fused_autograd_step_ms": round(ms_fused_step, 5),
-            "note": "fused: loss[b] = sum w|Fx|^2 and grad = F^H(2w Fx) in one kernel, 20 B per element",
-        }
+        out["fwd_adjoint"] = bench_fwd_adjoint(api, synth, torch, dev, args, x_all, y_all)
         log(f"[bench] fwd+adj {out['fwd_adjoint']}")
-        del xg, w
 
         # ------------------------------------------------------------ sweep
         if not args.no_sweep:
@@ -419,23 +499,11 @@ def main():
             out["sweep"] = sweep
 
         # ------------------------------------------------------------ lengths above 2048
-        large = []
-        for L in (12, 16, 20):
-            nn = 1 << L
-            bb = total // nn
-            p = api.Plan(nn, bb, -1)
-            m = time_launches(lambda: p.execute(x_all.view(bb, nn), y_all.view(bb, nn)),
-                              max(20, args.steps // 4), 5, torch)
-            large.append({"n": nn, "batch": bb, "us": round(m * 1e3, 2),
-                          "GFLOPs": round(5.0 * nn * L * bb / (m * 1e-3) / 1e9, 1),
-                          "GBps_algorithmic": round(bytes_alg / (m * 1e-3) / 1e9, 1),
-                          "passes_over_hbm": 2 if p.describe()["variant"] == 9 else 1})
-            p.close()
-        out["large_n"] = large
-        log(f"[bench] large {large}")
+        out["large_n"] = bench_large(api, torch, args, x_all, y_all)
+        log(f"[bench] large {out['large_n']}")
 
         # ------------------------------------------------------------ FP16 / BF16
-        out["half"] = bench_half(api, synth, torch, dev, args.steps, ms, x_all)
+        out["half"] = bench_half(api, synth, torch, dev, args.steps, ms, x_all, half_samples)
         log(f"[bench] half {out['half']}")
 
         # ------------------------------------------------------------ real input
@@ -451,11 +519,97 @@ def main():
         log(f"[bench] ragged {out['ragged']}")
 
     # ---------------------------------------------------------------- cpu baseline
+    # the FP64 oracle on the host: its throughput on a bounded sample of the
+    # headline workload, and the accuracy of the sampled FP16/BF16 results
     if not args.no_cpu:
         log("[bench] timing the FP64 CPU oracle")
         out["cpu_baseline"] = cpu_baseline(n, batch)
         log(f"[bench] cpu {out['cpu_baseline']}")
+        if half_samples:
+            out["half"]["accuracy_vs_fp64_oracle"] = half_accuracy(half_samples)
+            log(f"[bench] half accuracy {out['half']['accuracy_vs_fp64_oracle']}")
     print(json.dumps(out), flush=True)
+
+
+def bench_fwd_adjoint(api, synth, torch, dev, args, x_all, y_all):
+    """The differentiable FFT at N = 2048, batch 16384: forward, forward +
+    adjoint, the autograd step, and the fused loss-gradient kernel."""
+    n, nb = 2048, 16384
+    xa = x_all[: nb * n].view(nb, n)
+    ya = y_all[: nb * n].view(nb, n)
+    za = torch.empty_like(xa)
+    pa = api.Plan(n, nb, -1)
+    ms_f = time_launches(lambda: pa.execute(xa, ya), args.steps, args.warmup, torch)
+
+    def fa():
+        pa.execute(xa, ya)
+        pa.adjoint(ya, za)
+    ms_fa = time_launches(fa, args.steps, args.warmup, torch)
+    b1 = 16.0 * nb * n
+    w = torch.from_numpy(synth.uniform_weights(synth.SEED_AUTOGRAD, (nb, n))).to(dev)
+    xg = xa.clone().requires_grad_(True)
+
+    def step():
+        xg.grad = None
+        yy = api.fft_differentiable(xg)
+        loss = (w * (yy.real ** 2 + yy.imag ** 2)).sum()
+        loss.backward()
+    ms_step = time_launches(step, max(20, args.steps // 5), 3, torch)
+    lossv = torch.empty(nb, dtype=torch.float32, device=dev)
+    ms_fused = time_launches(lambda: pa.loss_grad(xa, w, za, lossv), args.steps, args.warmup, torch)
+
+    def fused_step():
+        xg.grad = None
+        api.weighted_power_loss(xg, w).backward()
+    ms_fused_step = time_launches(fused_step, max(20, args.steps // 5), 3, torch)
+    return {
+        "workload": "N=2048 batch 16384 (256 MiB per pass)",
+        "fwd_ms": round(ms_f, 5), "fwd_GBps": round(b1 / (ms_f * 1e-3) / 1e9, 1),
+        "fwd_adj_ms": round(ms_fa, 5), "fwd_adj_GBps": round(2 * b1 / (ms_fa * 1e-3) / 1e9, 1),
+        "ratio_fwd_adj_over_fwd": round(ms_fa / ms_f, 3),
+        "autograd_step_ms": round(ms_step, 5),
+        "fused_loss_grad_ms": round(ms_fused, 5),
+        "fused_loss_grad_GBps": round((20.0 * nb * n + 4.0 * nb) / (ms_fused * 1e-3) / 1e9, 1),
+        "fused_autograd_step_ms": round(ms_fused_step, 5),
+        "note": "fused: loss[b] = sum w|Fx|^2 and grad = F^H(2w Fx) in one kernel, 20 B per element",
+    }
+
+
+def bench_large(api, torch, args, x_all, y_all):
+    """Lengths above 2048 at 2^26 elements: one pass up to 2^14, the
+    two-pass four-step above."""
+    total = x_all.numel()
+    large = []
+    for L in (12, 14, 16, 20):
+        nn = 1 << L
+        bb = total // nn
+        p = api.Plan(nn, bb, -1)
+        m = time_launches(lambda: p.execute(x_all.view(bb, nn), y_all.view(bb, nn)),
+                          max(20, args.steps // 4), 5, torch)
+        passes = 2 if p.describe()["variant"] == 9 else 1
+        large.append({"n": nn, "batch": bb, "us": round(m * 1e3, 2),
+                      "GFLOPs": round(5.0 * nn * L * bb / (m * 1e-3) / 1e9, 1),
+                      "GBps_algorithmic": round(16.0 * total / (m * 1e-3) / 1e9, 1),
+                      "GBps_actual_passes": round(16.0 * passes * total / (m * 1e-3) / 1e9, 1),
+                      "passes_over_hbm": passes})
+        p.close()
+    return large
+
+
+def run_section(only, args, api, synth, torch, dev, x_all, y_all):
+    """One section alone, for profiler runs; prints its JSON."""
+    res = {"section": only}
+    if only == "half":
+        res["half"] = bench_half(api, synth, torch, dev, args.steps, float("nan"), x_all)
+    elif only == "loss":
+        res["fwd_adjoint"] = bench_fwd_adjoint(api, synth, torch, dev, args, x_all, y_all)
+    elif only == "copy":
+        res["copy"] = bench_copy(torch, x_all, y_all, args.steps, args.warmup)
+    elif only == "large":
+        res["large_n"] = bench_large(api, torch, args, x_all, y_all)
+    elif only == "nd":
+        res["nd"] = bench_nd(api, torch, args.steps, x_all, y_all)
+    print(json.dumps(res), flush=True)
 
 
 if __name__ == "__main__":

@@ -16,6 +16,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmifft.so")
+# measurement support for the benchmark: a plain streaming copy (HBM ceiling)
+COPY_LIB = os.path.join(HERE, "libstreamcopy.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # Packed FP32 instructions are disabled for every device compile.
@@ -70,6 +72,13 @@ def build(jobs: int | None = None, verbose: bool = False) -> str:
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")
     os.replace(tmp, LIB)
+    _compile("stream_copy.hip", "stream_copy.o", [])
+    tmp = COPY_LIB + ".tmp"
+    r = subprocess.run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp,
+                        os.path.join(BUILD, "stream_copy.o")], capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link of the copy library failed:\n{r.stderr}")
+    os.replace(tmp, COPY_LIB)
     return LIB
 
 

@@ -75,6 +75,13 @@ int ilog2(int64_t v)
 size_t elem_bytes(int dtype) { return (dtype == FFT_C32 || dtype == FFT_R32) ? 8 : 4; }
 }  // namespace
 
+// Status reporting for the entry points defined in other translation units.
+namespace mifft {
+int record_error(int code, const char* msg) { return set_err(code, "%s", msg); }
+int record_hip_error(hipError_t e, const char* what) { return hip_err(e, what); }
+int record_ok() { return ok(); }
+}  // namespace mifft
+
 // ------------------------------------------------------------------ registry
 namespace mifft {
 static std::vector<KernelC32>& c32_reg()
