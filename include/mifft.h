@@ -232,6 +232,32 @@ fft_plan fft_plan_create_nd(int rank, const int64_t *dims, int64_t batch, int si
  */
 int fft_execute(fft_plan p, const void *in, void *out, void *stream);
 
+/* Bytes of the library's static scratch array on each GPU (64 MiB). */
+#define MIFFT_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+
+/*
+ * For callers that cannot allocate device memory or call hipMalloc/hipFree
+ * while they execute (code under stream capture, tight serving loops,
+ * harnesses that forbid allocation): fft_execute with every intermediate in
+ * memory the library already holds.  Allocates nothing and frees nothing.
+ *   FFT_R32 plans above 2^15 (the half-length four-step transform plus the
+ *   split pass): the intermediate spectrum of n/2 complex values per
+ *   transform goes to a static scratch array of MIFFT_STATIC_SCRATCH_BYTES
+ *   per GPU instead of the plan's workspace, so (n/2) * batch * 8 bytes must
+ *   fit: FFT_EINVAL_BATCH otherwise, with the largest batch for that length
+ *   in the message (e.g. 256 transforms of 2^16 reals, 8 of 2^21).
+ *   Every other plan: exactly fft_execute (those executes use no workspace).
+ * Arguments, layouts, sizes and error codes otherwise as fft_execute.
+ * The scratch array's device address is looked up on the first call on each
+ * device.  All calls on one GPU share that GPU's array, and it keeps the
+ * last call's contents (nothing in it needs to start at zero): two calls
+ * that overlap in time on one GPU (on different streams, or from different
+ * threads without ordering) race on it and give wrong results.  Calls on
+ * one stream are ordered and safe.  Plans must still be created beforehand
+ * (plan creation allocates).
+ */
+int fft_execute_static_scratch(fft_plan p, const void *in, void *out, void *stream);
+
 /*
  * Apply the adjoint (conjugate transpose) of the plan's transform: the
  * opposite sign at the SAME scale.  For a forward plan that is the

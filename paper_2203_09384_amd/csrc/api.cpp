@@ -1123,25 +1123,29 @@ int check_exec(fft_plan p, const void* in, const void* out, bool to_bins = false
 int exec_c32(fft_plan p, const void* in, void* out, int sign, float scale, hipStream_t st);
 
 // FFT_R32: to_bins selects the real -> bins kernel; we / wi weight the
-// edge and interior bins (see real.hip).
-int exec_real(fft_plan p, const void* in, void* out, bool to_bins, float we, float wi, hipStream_t st)
+// edge and interior bins (see real.hip).  ws: the workspace of a plan above
+// 2^15 (n/2 complex values per transform), NULL for the plan's own.
+int exec_real(fft_plan p, const void* in, void* out, bool to_bins, float we, float wi, hipStream_t st,
+              void* ws = nullptr)
 {
     if (p->real_sub) {
         // Z = DFT_{n/2}(z) into the workspace, then the split (or the
         // reverse); the complex transform runs unscaled, the weights carry
         // the plan's scale
         const float2* tw = static_cast<const float2*>(p->real_tw);
+        if (!ws)
+            ws = p->real_ws;
         if (to_bins) {
-            int rc = exec_c32(p->real_sub, in, p->real_ws, -1, 1.0f, st);
+            int rc = exec_c32(p->real_sub, in, ws, -1, 1.0f, st);
             if (rc != FFT_OK)
                 return rc;
-            hipError_t e = launch_real_split(0, p->real_ws, out, tw, tw + 1024, p->log2n, p->batch, we, wi, st);
+            hipError_t e = launch_real_split(0, ws, out, tw, tw + 1024, p->log2n, p->batch, we, wi, st);
             return e == hipSuccess ? ok() : hip_err(e, "real-input split launch");
         }
-        hipError_t e = launch_real_split(1, in, p->real_ws, tw, tw + 1024, p->log2n, p->batch, we, wi, st);
+        hipError_t e = launch_real_split(1, in, ws, tw, tw + 1024, p->log2n, p->batch, we, wi, st);
         if (e != hipSuccess)
             return hip_err(e, "real-input split launch");
-        return exec_c32(p->real_sub, p->real_ws, out, +1, 1.0f, st);
+        return exec_c32(p->real_sub, ws, out, +1, 1.0f, st);
     }
     const KernelReal* k = to_bins ? p->r2c : p->c2r;
     hipError_t e = k->fn(in, out, p->rows, p->wn, p->batch, we, wi, p->grid_limit, st);
@@ -1196,6 +1200,43 @@ int exec_c32(fft_plan p, const void* in, void* out, int sign, float scale, hipSt
 }  // namespace
 
 // ------------------------------------------------------------------ C ABI
+// ------------------------------------------------------------------ static scratch
+// Device memory for fft_execute_static_scratch: the intermediate half-length
+// spectrum of real-input plans above 2^15, for callers that cannot allocate.
+// Every GPU the library runs on holds its own copy until the process ends.
+// Host code never passes the array's name to a kernel or a copy (on the host
+// it is only a stand-in for the symbol): it uses the device address that
+// hipGetSymbolAddress returns, looked up once per device with that device
+// current, and kept below.
+namespace {
+constexpr size_t kScratchBytes = MIFFT_STATIC_SCRATCH_BYTES;
+static __device__ __align__(256) float2 scratch[kScratchBytes / sizeof(float2)];
+
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxScratchDevices] = {};
+
+// Device address of `scratch` on device `dev` (the current device).
+int scratch_address(int dev, void** ptr)
+{
+    if (dev < 0 || dev >= kMaxScratchDevices)
+        return set_err(FFT_EDEVICE, "device %d: the static scratch is tracked for devices 0..%d", dev,
+                       kMaxScratchDevices - 1);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* a = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&a, HIP_SYMBOL(scratch));
+        if (e != hipSuccess)
+            return hip_err(e, "hipGetSymbolAddress(scratch)");
+        if (!a)
+            return set_err(FFT_EHIP, "hipGetSymbolAddress(scratch) returned a null address");
+        g_scratch_ptr[dev] = a;
+    }
+    *ptr = g_scratch_ptr[dev];
+    return FFT_OK;
+}
+}  // namespace
+
 extern "C" {
 
 fft_plan fft_plan_create(int64_t n, int64_t batch, int sign, int dtype)
@@ -1330,6 +1371,28 @@ int fft_execute(fft_plan p, const void* in, void* out, void* stream)
     if (p->dtype != FFT_C32)
         return fft_execute_scaled(p, in, nullptr, out, nullptr, stream);
     return exec_c32(p, in, out, p->sign, p->scale, static_cast<hipStream_t>(stream));
+}
+
+int fft_execute_static_scratch(fft_plan p, const void* in, void* out, void* stream)
+{
+    int rc = check_exec(p, in, out, p && p->sign < 0);
+    if (rc != FFT_OK)
+        return rc;
+    if (!(p->dtype == FFT_R32 && p->real_sub))
+        return fft_execute(p, in, out, stream);  // no workspace: the plain execute allocates nothing either
+    const size_t need = (size_t)(p->n / 2) * (size_t)p->batch * sizeof(float2);
+    if (need > kScratchBytes)
+        return set_err(FFT_EINVAL_BATCH,
+                       "n=%lld batch=%lld needs %zu bytes of scratch; the static scratch holds %zu "
+                       "(at most %lld transforms of this length)",
+                       (long long)p->n, (long long)p->batch, need, kScratchBytes,
+                       (long long)(kScratchBytes / ((size_t)(p->n / 2) * sizeof(float2))));
+    void* ws = nullptr;
+    rc = scratch_address(p->device, &ws);
+    if (rc != FFT_OK)
+        return rc;
+    const float s = p->scale;
+    return exec_real(p, in, out, p->sign < 0, s, s, static_cast<hipStream_t>(stream), ws);
 }
 
 int fft_execute_adjoint(fft_plan p, const void* in, void* out, void* stream)

@@ -27,7 +27,9 @@ EXPORTS = [
     "fft_execute_scaled", "fft_plan_destroy", "fft_plan_describe", "fft_plan_query",
     "fft_plan_twiddles", "fft_last_error", "fft_last_error_string", "fft_version",
     "fft_execute_loss_grad", "fft_plan_create_nd", "fft_c32_variants",
+    "fft_execute_static_scratch",
 ]
+STATIC_SCRATCH_BYTES = 64 << 20  # MIFFT_STATIC_SCRATCH_BYTES
 
 
 class PlanDesc(ctypes.Structure):
@@ -84,6 +86,8 @@ def _declare(L):
     L.fft_plan_create_ragged_config.restype = vp
     L.fft_execute.argtypes = [vp, vp, vp, vp]
     L.fft_execute.restype = i32
+    L.fft_execute_static_scratch.argtypes = [vp, vp, vp, vp]
+    L.fft_execute_static_scratch.restype = i32
     L.fft_execute_adjoint.argtypes = [vp, vp, vp, vp]
     L.fft_execute_adjoint.restype = i32
     L.fft_execute_scaled.argtypes = [vp, vp, vp, vp, vp, vp]
