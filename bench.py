@@ -376,7 +376,7 @@ def main():
                          "the streaming copy (counter calibration)")
     ap.add_argument("--only-headline", action="store_true", help="same as --only headline")
     ap.add_argument("--with-copy", action="store_true",
-                    help="with --only headline: also run the 512 MiB streaming copy (counter calibration)")
+                    help="with --only SECTION: also run the 512 MiB streaming copy (counter calibration)")
     args = ap.parse_args()
     if args.only_headline:
         args.only = "headline"
@@ -609,6 +609,8 @@ def run_section(only, args, api, synth, torch, dev, x_all, y_all):
         res["large_n"] = bench_large(api, torch, args, x_all, y_all)
     elif only == "nd":
         res["nd"] = bench_nd(api, torch, args.steps, x_all, y_all)
+    if args.with_copy and only != "copy":  # counter calibration in the same run
+        res["copy"] = bench_copy(torch, x_all, y_all, args.steps, args.warmup)
     print(json.dumps(res), flush=True)
 
 

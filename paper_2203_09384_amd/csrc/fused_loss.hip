@@ -47,34 +47,16 @@ __device__ __forceinline__ void load_weights(float (&wv)[1 << E], const float* _
     }
 }
 
-// Sum of `part` over the TPT threads of each transform; the total is valid
-// in thread t == 0 of the transform.  `red` holds TPB * (TPT / 64) floats.
-template <int TPT, int TPB>
-__device__ __forceinline__ float transform_sum(float part, int tb, int t, float* red)
+// Sum of `part` over the TPT <= 64 threads of each transform (one
+// wavefront); the total is valid in thread t == 0 of the transform.
+template <int TPT>
+__device__ __forceinline__ float transform_sum(float part)
 {
-    if constexpr (TPT == 1) {
-        return part;
-    } else if constexpr (TPT <= 64) {
+    static_assert(TPT <= 64, "transforms spanning wavefronts sum through LDS in loss_grad_group");
 #pragma unroll
-        for (int off = TPT / 2; off > 0; off >>= 1)
-            part += __shfl_xor(part, off);
-        return part;
-    } else {
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1)
-            part += __shfl_xor(part, off);
-        constexpr int W = TPT / 64;
-        if ((t & 63) == 0)
-            red[tb * W + (t >> 6)] = part;
-        __syncthreads();
-        float s = 0.f;
-        if (t == 0) {
-#pragma unroll
-            for (int i = 0; i < W; i++)
-                s += red[tb * W + i];
-        }
-        return s;
-    }
+    for (int off = TPT / 2; off > 0; off >>= 1)
+        part += __shfl_xor(part, off);
+    return part;
 }
 
 template <int L, int E, int S>
@@ -140,11 +122,33 @@ __device__ __forceinline__ void loss_grad_group(cf (&v)[1 << E], cf (&nx)[1 << E
         part += wv[m] * (y.x * y.x + y.y * y.y);
         v[m] = cscale(y, 2.f * wv[m]);
     }
-    const float total = transform_sum<TPT, TPB>(part, tb, t, red);
-    if (t == 0 && g * TPB + tb < batch)
-        loss[g * TPB + tb] = total;
-    if constexpr (TPT > 1)
-        lds_sync<WAVE>();  // the forward's last exchange is fully read
+    if constexpr (TPT > 64) {
+        // Per-wave sums go to `red`; one workgroup barrier both publishes
+        // them and orders the forward's last exchange reads before the
+        // adjoint's first writes (a separate barrier for the sum is not
+        // needed).  `red` is next written after this group's adjoint
+        // exchanges, long after thread 0 has read it.
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1)
+            part += __shfl_xor(part, off);
+        constexpr int W = TPT / 64;
+        if ((t & 63) == 0)
+            red[tb * W + (t >> 6)] = part;
+        __syncthreads();
+        if (t == 0 && g * TPB + tb < batch) {
+            float s = 0.f;
+#pragma unroll
+            for (int i = 0; i < W; i++)
+                s += red[tb * W + i];
+            loss[g * TPB + tb] = s;
+        }
+    } else {
+        const float total = transform_sum<TPT>(part);
+        if (t == 0 && g * TPB + tb < batch)
+            loss[g * TPB + tb] = total;
+        if constexpr (TPT > 1)
+            lds_sync<WAVE>();  // the forward's last exchange is fully read
+    }
     transform_passes<L, E, -S>(v, t, rows, lds);  // A^H g (before its scale)
     store_group<L, E, TPB>(v, grad, g, batch, tb, toff8, scale);
     if constexpr (TPT > 1)

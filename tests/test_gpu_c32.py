@@ -163,7 +163,10 @@ def test_rejects_overlap_misalignment_null():
     base = buf.data_ptr()
     s = ctypes.c_void_p(0)
     assert L.fft_execute(p._h, ctypes.c_void_p(base), ctypes.c_void_p(base + 8 * 16), s) == 6  # overlap
-    assert L.fft_execute(p._h, ctypes.c_void_p(base + 8), ctypes.c_void_p(base + 8 * n * batch + 16), s) == 11
+    # complex64 buffers need 8-byte (element) alignment; both calls are refused
+    # before any launch
+    assert L.fft_execute(p._h, ctypes.c_void_p(base + 4), ctypes.c_void_p(base + 8 * n * batch), s) == 11
+    assert L.fft_execute(p._h, ctypes.c_void_p(base), ctypes.c_void_p(base + 8 * n * batch + 4), s) == 11
     assert L.fft_execute(p._h, None, ctypes.c_void_p(base), s) == 5
     assert L.fft_execute(None, ctypes.c_void_p(base), ctypes.c_void_p(base + 8 * n * batch), s) == 5
     # exactly adjacent buffers do not overlap
