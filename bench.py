@@ -413,7 +413,9 @@ def main():
     plan = api.Plan(n, batch, -1)
     desc = plan.describe()
     log(f"[bench] headline plan {desc}")
-    clocks_before = read_clocks()
+    # rocm-smi is a separate program; under a profiler (the --only runs) its
+    # interpreter would start inside the profiled process tree, so skip it
+    clocks_before = read_clocks() if only is None else {"skipped": "single-section run"}
     # settle clocks: about half a second of the same kernel before timing
     t_end = time.perf_counter() + 0.5
     while time.perf_counter() < t_end:
@@ -421,7 +423,7 @@ def main():
             plan.execute(x, y)
         torch.cuda.synchronize()
     ms = time_launches(lambda: plan.execute(x, y), args.steps, args.warmup, torch)
-    clocks_after = read_clocks()
+    clocks_after = read_clocks() if only is None else {"skipped": "single-section run"}
     bytes_alg = 16.0 * total
     gbps = bytes_alg / (ms * 1e-3) / 1e9
     gflops = 5.0 * n * math.log2(n) * batch / (ms * 1e-3) / 1e9
