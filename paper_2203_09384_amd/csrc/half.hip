@@ -1,30 +1,25 @@
-// FP16 / BF16 storage path, N = 2048: block floating point, every pass as
-// dense DFT-matrix products on MFMA.
+// FP16 / BF16 storage path, N = 2048: block floating point, radix-16 stages
+// as dense 16 x 16 complex DFT-matrix products on MFMA.
 //
 // The paper's library is FP32-only (section "Implementation"); this path
 // stores data as half-precision (re, im) pairs and computes the same DFT of
 // Eq. (dft) with the Cooley-Tukey split 2048 = 8 * 16 * 16:
-//   pass A  radix 8 (NS = 1, no twiddles)
-//   pass B  radix 16 (NS = 8)
-//   pass C  radix 16 (NS = 128)
-// Each pass is Y = F X for 16 butterflies at a time, F the DFT matrix of the
-// radix, complex products written in real form with FP32 accumulation:
-//   pass A  one v_mfma_f32_16x16x16_f16 per 16 butterflies: (re, im)
-//           interleaved along both dimensions, so the stored (re, im) word
-//           pairs are the data operand as they are;
-//   passes B, C  two v_mfma_f32_16x16x32_f16 per 16 butterflies,
-//           Re Y = [Re F | -Im F] [Re X; Im X],  Im Y = [Im F | Re F] [Re X; Im X].
-// The inter-pass twiddles (FP32, from the plan's table) are folded into
-// pass B's DFT operands or applied when pass B writes its outputs to LDS,
-// so every data operand is a plain gather.
+//   pass A  radix-8 butterflies on the VALU in FP32 (no twiddles, NS = 1)
+//   pass B  radix-16 (NS = 8)   } Y = F16 X for 16 butterflies at a time,
+//   pass C  radix-16 (NS = 128) } F16 the 16-point DFT matrix,
+// where each complex product is two real MFMAs over K = 32:
+//   Re Y = [Re F | -Im F] [Re X; Im X],   Im Y = [Im F | Re F] [Re X; Im X]
+// on v_mfma_f32_16x16x32_f16 with FP32 accumulation.  The
+// inter-pass twiddles (FP32, from the plan's table) are applied when a pass
+// writes its outputs to LDS, so every MFMA operand is a plain gather.
 //
 // Block floating point: logical value = stored * 2^exp[b] per transform.
-// The input is scaled by a power of two so its largest component lies in
-// [8, 16); with the at most 8 * 16 * 16 = 2^11 growth of the three passes
-// no operand can exceed 2^15 < 65504, and the output is stored at that
-// scale with exponent in_exp + e_max - 4 (- 11 for the inverse's 1/N,
-// exact).  Scaling is by powers of two only, so it adds no rounding beyond
-// the operands' own.
+// On load the transform is scaled by a power of two so its largest
+// component lies in [8, 16); with the at most 8 * 16 * 16 = 2^11 growth of
+// the three passes no operand can exceed 2^15 < 65504, and the output is
+// stored at that scale with exponent in_exp + e_max - 4 (- 11 for the
+// inverse's 1/N, exact).  Scaling is by powers of two only, so it adds no
+// rounding.
 //
 // MFMA operands are FP16 for both storage types.  After the block scaling
 // every operand lies in FP16's range, FP16 carries three more significand
@@ -46,11 +41,8 @@ namespace mifft {
 namespace {
 
 typedef _Float16 v8h __attribute__((ext_vector_type(8)));
-typedef _Float16 v4h __attribute__((ext_vector_type(4)));
-typedef _Float16 v2h __attribute__((ext_vector_type(2)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef uint32_t v4u __attribute__((ext_vector_type(4)));
-typedef uint32_t v2u __attribute__((ext_vector_type(2)));
 
 constexpr int HN = 2048;
 constexpr int HWG = 256;
@@ -58,19 +50,17 @@ constexpr int HWG = 256;
 // LDS layouts, one per exchange, each conflict-free for both its writer and
 // its reader (modelled on the 64 banks) and affine in the per-instruction
 // indices, so every access is a per-thread base plus an immediate offset.
-// Element d is one 32-bit word holding its (re, im) as two FP16 halves (the
-// MFMA operand type, so rounding there is the operands' own rounding).
+// Element d is one 32-bit word holding its (re, im) as two 16-bit halves:
+// FP16 for the A -> B and B -> C exchanges (the MFMA operand type, so
+// rounding there is the operands' own rounding), the storage format for
+// C -> store (output scale applied first, so the value is rounded once).
 //   A -> B      : d + (d >> 3) + 16 (d >> 10)
 //   B -> C      : d + (d >> 6)
-// Pass C's results go out through a wavefront-private part of the A -> B
-// buffer (see half_transform).
+//   C -> store  : d + (d >> 6) + 4 (d >> 8)
 __device__ __forceinline__ int fA(int d) { return d + (d >> 3) + 16 * (d >> 10); }
 __device__ __forceinline__ int fB(int d) { return d + (d >> 6); }
-constexpr int BUFA = 2336;  // words of the A -> B buffer (fA(2047) + 1 = 2319, rounded up)
-constexpr int BUFB = 2080;  // words of the B -> C buffer (fB(2047) + 1 = 2079, rounded up)
-// store staging: wave w's 16 rows of 32 words at 584 w + 36 row, inside the
-// words its own pass-A writes use plus padding no wave writes
-constexpr int STAGE_WAVE = 584, STAGE_ROW = 36;
+__device__ __forceinline__ int fC(int d) { return d + (d >> 6) + 4 * (d >> 8); }
+constexpr int BUF = 2336;  // words per buffer (largest layout: fA)
 
 // ---- conversions (round to nearest even)
 template <bool BF>
@@ -80,6 +70,14 @@ __device__ __forceinline__ float to_f32(uint16_t h)
         return __builtin_bit_cast(float, (uint32_t)h << 16);
     else
         return (float)__builtin_bit_cast(_Float16, h);
+}
+template <bool BF>
+__device__ __forceinline__ uint16_t from_f32(float f)
+{
+    if constexpr (BF)
+        return __builtin_bit_cast(uint16_t, (__bf16)f);
+    else
+        return __builtin_bit_cast(uint16_t, (_Float16)f);
 }
 
 // MFMA operand: 8 FP16 values.
@@ -91,15 +89,6 @@ struct Op8 {
 __device__ __forceinline__ v4f mfma(const Op8& a, const Op8& b, v4f c)
 {
     return __builtin_amdgcn_mfma_f32_16x16x32_f16(a.hi, b.hi, c, 0, 0, 0);
-}
-
-template <int S>
-__device__ __forceinline__ cf tw_at(const cf* __restrict__ tw, int idx)
-{
-    cf w = tw[idx];
-    if constexpr (S > 0)
-        w.y = -w.y;
-    return w;
 }
 
 // This lane's rows of the A operands of the 16-point DFT with the twiddles
@@ -128,42 +117,29 @@ __device__ __forceinline__ void dft16_operands(Op8& are, Op8& aim, int lane, int
     }
 }
 
-// This lane's part of pass A's operand: the 8-point DFT F[m][r] =
-// exp(S 2 pi i m r / 8) in real form with (re, im) interleaved along both
-// dimensions, a 16 x 16 matrix over row 2m + c' (c' = 0: Re y_m, 1: Im y_m)
-// and column 2r + c (c = 0: Re x_r, 1: Im x_r):
-//   [Re F, -Im F]
-//   [Im F,  Re F]   at rows 2m, 2m + 1 and columns 2r, 2r + 1.
-// For v_mfma_f32_16x16x16_f16 lane l holds row l % 16, columns 4 (l / 16) + i.
-// Entries are lookups of the FP32 table (w_2048^{256 e} = w_8^e), rounded
-// once to FP16 (0, +-1 exact; +-sqrt(2)/2 to 2^-12 relative).
 template <int S>
-__device__ __forceinline__ v4h dft8_operand(int lane, const cf* __restrict__ tw)
+__device__ __forceinline__ cf tw_at(const cf* __restrict__ tw, int idx)
 {
-    const int row = lane & 15, m = row >> 1, cp = row & 1, kq = lane >> 4;
-    v4h a;
-#pragma unroll
-    for (int i = 0; i < 4; i++) {
-        const int k = 4 * kq + i, r = k >> 1, cc = k & 1;
-        const cf z = tw_at<S>(tw, 256 * ((m * r) & 7));
-        const float v = cp == 0 ? (cc == 0 ? z.x : -z.y) : (cc == 0 ? z.y : z.x);
-        a[i] = (_Float16)v;
-    }
-    return a;
+    cf w = tw[idx];
+    if constexpr (S > 0)
+        w.y = -w.y;
+    return w;
 }
 
-// Per-thread constants of the kernel: MFMA operands, twiddles, offsets.
+template <bool BF>
+__device__ __forceinline__ void unpack8(const uint32_t (&u)[8], cf (&v)[8])
+{
+#pragma unroll
+    for (int m = 0; m < 8; m++)
+        v[m] = cf{to_f32<BF>((uint16_t)(u[m] & 0xffffu)), to_f32<BF>((uint16_t)(u[m] >> 16))};
+}
+
+// Per-thread constants of the kernel: MFMA operands, twiddles, LDS bases.
 struct HalfCtx {
-    v4h f8;                // pass A, the 8-point DFT
     Op8 a_re[2], a_im[2];  // pass B, group g = 2 wave + gg, twiddles folded
     Op8 f_re, f_im;        // pass C, plain DFT
-    cf twBase[2], twStep;  // pass C twiddles of pass B output (gg, i): twBase[gg] twStep^i
-    int oLd;               // word of this lane's first input load
-    // LDS offsets: pass A writes (q = 0, first word; q adds 144, the second
-    // word is the next), pass B reads / writes and pass C reads of gg = 0
-    // (gg = 1 is 1, 1 and 16 words further: the layouts are affine there)
-    int oWA, oRB, oWB, oRC;
-    int oStW, oStR, oSt;   // store staging: write and read offsets, output element
+    cf twB[2][4];          // pass C twiddle of pass B output (gg, i)
+    int oWA, oRB[2], oWB[2], oRC[2], oWC[2], oRS0, oRS1;
     uint32_t sel;          // byte selector of this lane's halves (re: low, im: high)
     int tid, lane, wave;
 };
@@ -171,12 +147,13 @@ struct HalfCtx {
 // Two floats to one word of two halves (a low, b high), each rounded to
 // nearest even: one packed convert (v_cvt_pk_f16_f32 / v_cvt_pk_bf16_f32).
 typedef float v2f32 __attribute__((ext_vector_type(2)));
+typedef _Float16 v2f16 __attribute__((ext_vector_type(2)));
 typedef __bf16 v2bf16 __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ uint32_t pack_f16(float a, float b)
 {
     const v2f32 f = {a, b};
-    return __builtin_bit_cast(uint32_t, __builtin_convertvector(f, v2h));
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(f, v2f16));
 }
 
 template <bool BF>
@@ -186,7 +163,7 @@ __device__ __forceinline__ uint32_t pack_store(float a, float b)
     if constexpr (BF)
         return __builtin_bit_cast(uint32_t, __builtin_convertvector(f, v2bf16));
     else
-        return __builtin_bit_cast(uint32_t, __builtin_convertvector(f, v2h));
+        return __builtin_bit_cast(uint32_t, __builtin_convertvector(f, v2f16));
 }
 
 // An MFMA operand from 8 packed words: this lane's half (re or im) of each.
@@ -218,149 +195,64 @@ __device__ __forceinline__ float wave_max_nonneg(float x)
     return __builtin_bit_cast(float, __builtin_amdgcn_readlane(v, 63));
 }
 
-// This lane's pass-A input words of transform b: for group q (butterflies
-// j = 64 wave + 16 q + n, n = lane % 16) the inputs r = 2 kq and 2 kq + 1
-// (kq = lane / 16) of butterfly j, x[j + 256 r], as u[2 q] and u[2 q + 1].
-// Plain loads: for this pattern (runs of 64 bytes per instruction, the rest
-// of each line read by the same wave's next instructions) nontemporal loads
-// measured 15% slower, as did a plain copy of it (92 against 79 us at 512 MiB).
-__device__ __forceinline__ void load_raw(uint32_t (&u)[8], const uint32_t* __restrict__ in, int64_t b, int off)
+__device__ __forceinline__ void load_raw(uint32_t (&u)[8], const uint32_t* __restrict__ in, int64_t b, int tid)
 {
-    const uint32_t* src = in + b * HN + off;
+    const uint32_t* src = in + b * HN;
 #pragma unroll
-    for (int q = 0; q < 4; q++) {
-        u[2 * q] = src[16 * q];
-        u[2 * q + 1] = src[16 * q + 256];
-    }
+    for (int m = 0; m < 8; m++)
+        u[m] = __builtin_nontemporal_load(src + tid + 256 * m);
 }
 
-// Largest magnitude among the 16 half-precision components held in 8 raw
-// words, as a float.  Magnitudes of one 16-bit float format order like their
-// bit patterns with the sign cleared, so this is an unsigned 16-bit maximum
-// of the stored bits (two components per v_pk_max_u16); inf and NaN compare
-// above every finite value.
-typedef uint16_t v2u16 __attribute__((ext_vector_type(2)));
-template <bool BF>
-__device__ __forceinline__ float raw_absmax(const uint32_t (&u)[8])
-{
-    v2u16 m = __builtin_bit_cast(v2u16, u[0] & 0x7fff7fffu);
-#pragma unroll
-    for (int k = 1; k < 8; k++)
-        m = __builtin_elementwise_max(m, __builtin_bit_cast(v2u16, u[k] & 0x7fff7fffu));
-    return to_f32<BF>(m[0] > m[1] ? m[0] : m[1]);
-}
-
-// The wave's largest input magnitude of the transform in `u`, published in
-// red[wave] for the block maximum.
-template <bool BF>
-__device__ __forceinline__ void publish_max(const HalfCtx& c, const uint32_t (&u)[8], float* red)
-{
-    const float mx = wave_max_nonneg(raw_absmax<BF>(u));
-    if (c.lane == 0)
-        red[c.wave] = mx;
-}
-
-// Block maximum (over the four waves' maxima) -> the power-of-two exponent
-// e_max with max < 2^e_max (0 for an all-zero or non-finite transform).
-__device__ __forceinline__ int block_exponent(const float* red)
-{
-    const float mx = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
-    int e_max = 0;
-    if (mx > 0.f && mx <= 3.4e38f)
-        (void)frexpf(mx, &e_max);
-    return e_max;
-}
-
-// The raw words scaled by 2^sh (largest component into [8, 16)) as FP16
-// (re, im) pairs: pass A's data operand.  Exact, or one rounding to nearest
-// even where a value lands below FP16's normal range.  FP16 storage: packed
-// FP16 multiplies by 2^sh (sh is uniform; two steps above 2^15, where the
-// scale itself is not an FP16 value and every value grows, exactly).  BF16
-// storage: widened to FP32, ldexp (exact, and no 2^sh factor that could
-// overflow), one packed convert.
-template <bool BF>
-__device__ __forceinline__ void scale_operands(const uint32_t (&u)[8], uint32_t (&o)[8], int sh)
-{
-    if constexpr (BF) {
-#pragma unroll
-        for (int k = 0; k < 8; k++)
-            o[k] = pack_f16(ldexpf(__builtin_bit_cast(float, u[k] << 16), sh),
-                            ldexpf(__builtin_bit_cast(float, u[k] & 0xffff0000u), sh));
-    } else {
-        const int s1 = sh > 15 ? 15 : sh;
-        const _Float16 f1 = (_Float16)ldexpf(1.0f, s1);
-        const v2h m1 = {f1, f1};
-#pragma unroll
-        for (int k = 0; k < 8; k++)
-            o[k] = __builtin_bit_cast(uint32_t, __builtin_bit_cast(v2h, u[k]) * m1);
-        if (sh > 15) {
-            const _Float16 f2 = (_Float16)ldexpf(1.0f, sh - 15);
-            const v2h m2 = {f2, f2};
-#pragma unroll
-            for (int k = 0; k < 8; k++)
-                o[k] = __builtin_bit_cast(uint32_t, __builtin_bit_cast(v2h, o[k]) * m2);
-        }
-    }
-}
-
-// An empty asm that takes `o` as read and rewritten: the values are
-// computed where it stands and later code sees new values (nothing that
-// produced them is moved past it, and their loads carry no later wait).
-__device__ __forceinline__ void pin(uint32_t (&o)[8])
-{
-#pragma unroll
-    for (int k = 0; k < 8; k++)
-        asm volatile("" : "+v"(o[k]));
-}
-
-// One transform.  `op` holds its pass-A operand words (scaled, FP16; made
-// by the previous transform, or before the loop) and e_max its block
-// exponent; its raw words in `cur` are dead, so `cur` is refilled with
-// transform `refill` right away and two transforms' loads stay in flight.
-// `nxt` holds the next transform's raw words: after pass B its per-wave
-// maxima go to `red`, and after the second barrier (when every wave's are
-// there) its exponent and operand words are made for the next call.  Made at
-// the start of a transform instead, the compiler's loop-wide count of
-// outstanding memory operations waited there for the loads of the
-// transform after it, issued only one transform earlier.
-// X holds the A -> B exchange (and pass C's store staging), Y the B -> C
-// exchange.  Two barriers per transform:
-//  - X is written after the barrier that follows the previous transform's
-//    reads of X (its second: pass B reads, and staging reads are the same
-//    wave's own words), Y after the barrier that follows the previous
-//    transform's reads of Y (this transform's first), so one buffer of each
-//    serves every transform;
-//  - `red` is written before this transform's second barrier and read
-//    after it; the next write is in the next transform, after its first
-//    barrier, which every wave reaches only after its read.
+// One transform: raw input `cur` (thread t holds x[t + 256 m]) -> stored
+// output and exponent.  Once unpacked, `cur` is refilled with transform
+// `refill` (if < batch), so two transforms' loads stay in flight.  X holds
+// the A->B and C->store exchanges, Y the B->C exchange; `red` the per-wave
+// maxima.  Four barriers: the block maximum (needed before pass A's
+// outputs are scaled to FP16), then one per exchange.
 template <int S, bool BF>
-__device__ __forceinline__ void half_transform(const HalfCtx& c, uint32_t (&op)[8], int& e_max, uint32_t (&cur)[8],
-                                               const uint32_t (&nxt)[8], uint32_t* X, uint32_t* Y, float* red,
-                                               const uint32_t* __restrict__ in, const int32_t* __restrict__ in_exp,
-                                               uint32_t* __restrict__ out, int32_t* __restrict__ out_exp,
-                                               int64_t b, int64_t refill, int64_t batch, int scale_log2)
+__device__ __forceinline__ void half_transform(const HalfCtx& c, uint32_t (&cur)[8], uint32_t* X, uint32_t* Y,
+                                               float* red, const uint32_t* __restrict__ in,
+                                               const int32_t* __restrict__ in_exp, uint32_t* __restrict__ out,
+                                               int32_t* __restrict__ out_exp, int64_t b, int64_t refill,
+                                               int64_t batch, int scale_log2)
 {
+    constexpr int dWC[4] = {0, 130, 264, 394};  // fC(d0 + 128 i) - fC(d0)
+    // ---- pass A: radix 8 on the VALU in FP32 over x[tid + 256 m]
+    cf v[8];
+    unpack8<BF>(cur, v);
     // This transform's input exponent is read before the refill is issued,
     // and the refill itself is unconditional (past the end of the batch it
     // re-reads the last transform, which every workgroup shares through
     // the cache): a load issued after the refill, or a refill under a
-    // condition, would make the wait for `nxt` below cover the refill too.
+    // condition, would make the first wait below cover the refill as well.
     const int e_in = in_exp ? in_exp[b] : 0;
-    load_raw(cur, in, refill < batch ? refill : batch - 1, c.oLd);
-    const int e_out = e_in + e_max - 4 + scale_log2;
-
-    // ---- pass A: radix 8 on MFMA, 16 butterflies j = 64 wave + 16 q + n per
-    // product; outputs y_{2 kq}, y_{2 kq + 1} of butterfly j (this lane's
-    // accumulators) to the Stockham positions d = 8 j + 2 kq, + 1
+    load_raw(cur, in, refill < batch ? refill : batch - 1, c.tid);
+    float mx = 0.f;
 #pragma unroll
-    for (int q = 0; q < 4; q++) {
-        const v2u w = {op[2 * q], op[2 * q + 1]};
-        const v4f z = {0.f, 0.f, 0.f, 0.f};
-        const v4f y = __builtin_amdgcn_mfma_f32_16x16x16f16(c.f8, __builtin_bit_cast(v4h, w), z, 0, 0, 0);
-        uint32_t* wa = X + c.oWA + 144 * q;
-        wa[0] = pack_f16(y[0], y[1]);
-        wa[1] = pack_f16(y[2], y[3]);
-    }
+    for (int m = 0; m < 8; m++)
+        mx = fmaxf(mx, fmaxf(fabsf(v[m].x), fabsf(v[m].y)));
+    mx = wave_max_nonneg(mx);
+    if (c.lane == 0)
+        red[c.wave] = mx;
+    dft8<S>(v);
+    __syncthreads();
+
+    // ---- block maximum -> power-of-two scale (largest input component in [8, 16))
+    mx = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+    int e_max = 0;
+    if (mx > 0.f && mx <= 3.4e38f)
+        (void)frexpf(mx, &e_max);  // mx < 2^e_max
+    // applied as an exponent shift of each value (v_ldexp_f32): exact, and
+    // unlike a multiply by 2^(4 - e_max) it cannot overflow when the
+    // transform's largest component is near the bottom of the format's range
+    const int sh = 4 - e_max;
+    const int e_out = e_in + e_max - 4 + scale_log2;
+    // outputs to the Stockham position d = 8 tid + r, scaled, as FP16 pairs
+    // (pass B's twiddles are in its operands)
+    uint32_t* wa = X + c.oWA;
+#pragma unroll
+    for (int r = 0; r < 8; r++)
+        wa[r] = pack_f16(ldexpf(v[r].x, sh), ldexpf(v[r].y, sh));
     __syncthreads();
 
     // ---- pass B: radix 16 (NS = 8) on MFMA.  Group g holds the 16 butterflies
@@ -369,7 +261,7 @@ __device__ __forceinline__ void half_transform(const HalfCtx& c, uint32_t (&op)[
     v4f yre[2], yim[2];
 #pragma unroll
     for (int gg = 0; gg < 2; gg++) {
-        const uint32_t* rb = X + c.oRB + gg;
+        const uint32_t* rb = X + c.oRB[gg];
         uint32_t w[8];
 #pragma unroll
         for (int i = 0; i < 8; i++)
@@ -382,97 +274,76 @@ __device__ __forceinline__ void half_transform(const HalfCtx& c, uint32_t (&op)[
     // outputs Y[m] of butterfly j = g + 8 n to d = 128 n + g + 8 m, times pass C's twiddle
 #pragma unroll
     for (int gg = 0; gg < 2; gg++) {
-        uint32_t* wb = Y + c.oWB + gg;
-        cf t = c.twBase[gg];  // w_2048^{n (g + 8 m)}, m = 4 kq + i: twBase w_256^{n i}
-        // opaque per transform, so the products below are not hoisted out of
-        // the transform loop (that would hold all eight in registers again)
-        asm volatile("" : "+v"(t.x), "+v"(t.y));
+        uint32_t* wb = Y + c.oWB[gg];
 #pragma unroll
         for (int i = 0; i < 4; i++) {
-            const cf y = cmul(cf{yre[gg][i], yim[gg][i]}, t);
+            const cf y = cmul(cf{yre[gg][i], yim[gg][i]}, c.twB[gg][i]);
             wb[8 * i] = pack_f16(y.x, y.y);
-            if (i < 3)
-                t = cmul(t, c.twStep);
         }
     }
-    // the next transform's maximum, from its raw words (loaded a transform
-    // and a half ago, so the wait for them is short)
-    publish_max<BF>(c, nxt, red);
     __syncthreads();
 
-    // the next transform's exponent and pass-A operand words
-    e_max = block_exponent(red);
-    scale_operands<BF>(nxt, op, 4 - e_max);
-    pin(op);
-
-    // ---- pass C: radix 16 (NS = 128) on MFMA over butterflies j = 16 g + n,
-    // natural-order outputs d = j + 128 m.  The product is taken transposed,
-    // Y^T = X^T F^T (the data as the A operand, the DFT matrix as B: the same
-    // registers as Y = F X with the operands swapped), so a lane's four
-    // accumulators are outputs m = lane % 16 of the consecutive butterflies
-    // n = 4 (lane / 16) + i: four consecutive elements.
+    // ---- pass C: radix 16 (NS = 128) on MFMA over butterflies j = 16 g + n;
+    // natural-order outputs d = j + 128 m, stored in the output format
 #pragma unroll
     for (int gg = 0; gg < 2; gg++) {
-        const uint32_t* rc = Y + c.oRC + 16 * gg;
+        const uint32_t* rc = Y + c.oRC[gg];
         uint32_t w[8];
 #pragma unroll
         for (int i = 0; i < 8; i++)
             w[i] = rc[130 * i];
         const Op8 bo = gather_op(w, c.sel);
         const v4f z = {0.f, 0.f, 0.f, 0.f};
-        yre[gg] = mfma(bo, c.f_re, z);
-        yim[gg] = mfma(bo, c.f_im, z);
+        yre[gg] = mfma(c.f_re, bo, z);
+        yim[gg] = mfma(c.f_im, bo, z);
     }
-    // Lane (m, q) of wave w holds elements 128 m + 32 w + 16 gg + 4 q + i:
-    // the wave owns rows m = 0..15 of a 32-element (128-byte) column strip.
-    // Stored as they are, consecutive lanes would write different lines.
-    // The strip goes through a wavefront-private LDS area instead (rows of
-    // 36 words, conflict-free for the writes), and is read back so that
-    // lanes 8 r' .. 8 r' + 7 hold row r' in order: each group of 8 lanes then
-    // stores one whole line.  The area lies in this wave's own part of the
-    // A -> B buffer (plus padding no wave uses): no other wave touches it
-    // before the next transform's first barrier, which this wave reaches
-    // only after its reads.
-    uint32_t* sw = X + STAGE_WAVE * c.wave;
+    if (out_exp) {  // block floating point: the exponent carries the scale
 #pragma unroll
-    for (int gg = 0; gg < 2; gg++) {
-        v4u o;
-        if (out_exp) {  // block floating point: the exponent carries the scale
+        for (int gg = 0; gg < 2; gg++) {
+            uint32_t* wc = X + c.oWC[gg];
 #pragma unroll
             for (int i = 0; i < 4; i++)
-                o[i] = pack_store<BF>(yre[gg][i], yim[gg][i]);
-        } else {  // unit scale: the exponent applied to each value
-#pragma unroll
-            for (int i = 0; i < 4; i++)
-                o[i] = pack_store<BF>(ldexpf(yre[gg][i], e_out), ldexpf(yim[gg][i], e_out));
+                wc[dWC[i]] = pack_store<BF>(yre[gg][i], yim[gg][i]);
         }
-        *reinterpret_cast<v4u*>(sw + c.oStW + 16 * gg) = o;
-    }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    gu4* dst = reinterpret_cast<gu4*>(out + b * HN + c.oSt);
+    } else {  // unit scale: the exponent applied to each value
 #pragma unroll
-    for (int h = 0; h < 2; h++)
-        __builtin_nontemporal_store(*reinterpret_cast<const v4u*>(sw + c.oStR + STAGE_ROW * 8 * h), dst + 256 * h);
+        for (int gg = 0; gg < 2; gg++) {
+            uint32_t* wc = X + c.oWC[gg];
+#pragma unroll
+            for (int i = 0; i < 4; i++)
+                wc[dWC[i]] = pack_store<BF>(ldexpf(yre[gg][i], e_out), ldexpf(yim[gg][i], e_out));
+        }
+    }
+    __syncthreads();
+
+    // ---- store: 4 consecutive elements (16 bytes) per lane and instruction
+    gu4* dst = reinterpret_cast<gu4*>(out + b * HN);
+#pragma unroll
+    for (int h = 0; h < 2; h++) {
+        const uint32_t* rs = X + (h ? c.oRS1 : c.oRS0);
+        v4u o;
+#pragma unroll
+        for (int i = 0; i < 4; i++)
+            o[i] = rs[i];
+        __builtin_nontemporal_store(o, dst + c.tid + HWG * h);
+    }
     if (out_exp && c.tid == 0)
         out_exp[b] = e_out;
 }
 
 // Persistent: a workgroup walks transforms blockIdx.x, + gridDim.x, ...,
-// with the inputs of the next two transforms loaded ahead while one is
-// computed: two raw register buffers, the loop unrolled twice so each
-// body's buffer roles are fixed.  One set of LDS exchange buffers and
-// per-wave maxima serves every transform.
+// with the inputs of the next two transforms in flight while one is
+// computed.  Two LDS buffers (and two raw register buffers) alternate
+// between consecutive transforms (loop unrolled twice so each body's
+// buffer roles are fixed), so three barriers suffice.
 template <int S, bool BF>
 __global__ __launch_bounds__(HWG, 4) void k_fft_half_2048(const uint32_t* __restrict__ in,
                                                        const int32_t* __restrict__ in_exp,
                                                        uint32_t* __restrict__ out, int32_t* __restrict__ out_exp,
                                                        const cf* __restrict__ tw, int64_t batch, int scale_log2)
 {
-    __shared__ __align__(16) uint32_t ldsX[BUFA];
-    __shared__ __align__(16) uint32_t ldsY[BUFB];
-    __shared__ float s_red[HWG / 64];
+    __shared__ uint32_t lds[2 * BUF];
+    __shared__ float s_red[2][HWG / 64];
     int64_t b = blockIdx.x;
     if (b >= batch)
         return;
@@ -481,47 +352,43 @@ __global__ __launch_bounds__(HWG, 4) void k_fft_half_2048(const uint32_t* __rest
     c.lane = c.tid & 63;
     c.wave = c.tid >> 6;
     const int n = c.lane & 15, kq = c.lane >> 4, r0 = (kq & 1) * 8;
-    c.f8 = dft8_operand<S>(c.lane, tw);
     dft16_operands<S>(c.f_re, c.f_im, c.lane, 0, tw);
 #pragma unroll
     for (int gg = 0; gg < 2; gg++) {
         const int g = 2 * c.wave + gg;
         dft16_operands<S>(c.a_re[gg], c.a_im[gg], c.lane, g, tw);
-        c.twBase[gg] = tw_at<S>(tw, n * (g + 32 * kq));  // w_2048^{n (g + 8 m)} at m = 4 kq
+#pragma unroll
+        for (int i = 0; i < 4; i++)  // w_2048^{n (g + 8 m)}, m = 4 kq + i
+            c.twB[gg][i] = tw_at<S>(tw, n * (g + 8 * (4 * kq + i)));
+        c.oRB[gg] = fA(g + 8 * n + 128 * r0);
+        c.oWB[gg] = fB(128 * n + g + 32 * kq);
+        const int j = 16 * g + n;
+        c.oRC[gg] = fB(j + 128 * r0);
+        c.oWC[gg] = fC(j + 512 * kq);
     }
-    c.twStep = tw_at<S>(tw, 8 * n);  // w_2048^{8 n}: one step of m
-    c.oLd = 64 * c.wave + n + 512 * kq;
-    c.oWA = fA(8 * (64 * c.wave + n) + 2 * kq);
-    c.oRB = fA(2 * c.wave + 8 * n + 128 * r0);
-    c.oWB = fB(128 * n + 2 * c.wave + 32 * kq);
-    c.oRC = fB(32 * c.wave + n + 128 * r0);
     c.sel = (kq >> 1) ? 0x07060302u : 0x05040100u;  // rows k >= 16 take the imaginary halves
-    c.oStW = STAGE_ROW * n + 4 * kq;                                // row m = lane % 16, quad lane / 16
-    c.oStR = STAGE_ROW * (c.lane >> 3) + 4 * (c.lane & 7);         // row lane / 8, quad lane % 8
-    c.oSt = 128 * (c.lane >> 3) + 32 * c.wave + 4 * (c.lane & 7);  // its element of the output
+    c.oWA = fA(8 * c.tid);
+    c.oRS0 = fC(4 * c.tid);
+    c.oRS1 = fC(4 * (c.tid + HWG));
 
-    // two raw buffers: loading three or four transforms ahead measured no
-    // faster (MI355X, 32768 transforms: 93-95 us for each depth)
-    constexpr int D = 2;
-    uint32_t u[D][8], op[8];
+    uint32_t* const buf0 = lds;
+    uint32_t* const buf1 = lds + BUF;
+    uint32_t ua[8], ub[8];
     const int64_t stride = gridDim.x;
-#pragma unroll
-    for (int r = 0; r < D; r++)
-        load_raw(u[r], in, b + r * stride < batch ? b + r * stride : batch - 1, c.oLd);
-    publish_max<BF>(c, u[0], s_red);
-    __syncthreads();
-    int e_max = block_exponent(s_red);
-    scale_operands<BF>(u[0], op, 4 - e_max);
-    pin(op);
+    load_raw(ua, in, b, c.tid);
+    load_raw(ub, in, b + stride < batch ? b + stride : batch - 1, c.tid);
+    __builtin_amdgcn_sched_barrier(0);  // the first transform's loads are issued before the second's
     while (true) {
-#pragma unroll
-        for (int r = 0; r < D; r++) {
-            half_transform<S, BF>(c, op, e_max, u[r], u[(r + 1) % D], ldsX, ldsY, s_red, in, in_exp, out, out_exp,
-                                  b, b + D * stride, batch, scale_log2);
-            b += stride;
-            if (b >= batch)
-                return;
-        }
+        half_transform<S, BF>(c, ua, buf0, buf1, s_red[0], in, in_exp, out, out_exp, b, b + 2 * stride, batch,
+                              scale_log2);
+        b += stride;
+        if (b >= batch)
+            break;
+        half_transform<S, BF>(c, ub, buf1, buf0, s_red[1], in, in_exp, out, out_exp, b, b + 2 * stride, batch,
+                              scale_log2);
+        b += stride;
+        if (b >= batch)
+            break;
     }
 }
 
@@ -713,7 +580,7 @@ void half_query(int64_t n, int64_t batch, fft_plan_desc* d)
     d->radices[0] = 8;
     d->radices[1] = 16;
     d->radices[2] = 16;
-    d->lds_bytes = (int)((BUFA + BUFB) * sizeof(uint32_t) + 2 * HWG / 64 * sizeof(float));
+    d->lds_bytes = (int)(2 * BUF * sizeof(uint32_t) + 2 * HWG / 64 * sizeof(float));
     d->kind = 0;
     d->variant = 0;
 }

@@ -2,12 +2,11 @@
 budget independently of the GPU kernel.
 
 The emulated pipeline (N = 2048 = 8 * 16 * 16): stored half-precision input
-scaled by a power of two to max component in [8, 16); a radix-8 pass and
-two radix-16 passes whose operands (data and DFT matrix) are rounded to the
-operand type (the kernel uses FP16 for both storage types; BF16 operands
-split into hi + lo are modelled for comparison), with products accumulated
-in FP32 and FP32 twiddles between passes; output rounded to the storage
-type.  The reference is
+scaled by a power of two to max component in [8, 16); radix-8 pass in FP32;
+FP32 twiddles; two radix-16 passes whose operands (data and DFT matrix) are
+rounded to the operand type (the kernel uses FP16 for both storage types;
+BF16 operands split into hi + lo are modelled for comparison), with products
+accumulated in FP32; output rounded to the storage type.  The reference is
 numpy's FP64 FFT of the stored input (the method's own error), and the raw
 FP64 draw is the second column.  Bar: 3e-3 relative L2 per transform.
 """
@@ -40,22 +39,11 @@ def quant_parts(x, kind, split):
     return [hi, q(x - hi, kind)]
 
 
-def emulate(xs, kind, split, op_kind=None, pass_a="mfma"):
+def emulate(xs, kind, split, op_kind=None):
     """xs: (batch, N) complex, already the stored input (as float64); kind
-    is the storage type, op_kind the MFMA operand type (default: kind).
-    pass_a: "mfma" (the kernel: scaled inputs rounded to the operand type,
-    the 8-point DFT matrix rounded to it, products accumulated in FP32) or
-    "fp32" (the radix-8 pass in FP32 arithmetic)."""
+    is the storage type, op_kind the MFMA operand type (default: kind)."""
     op_kind = op_kind or kind
     out = np.empty_like(xs)
-
-    def prod(A, B):  # hi*hi + hi*lo + lo*hi, accumulated in fp64 then fp32
-        s = A[0].astype(np.float64) @ B[0].astype(np.float64)
-        if split:
-            s = s + A[0].astype(np.float64) @ B[1].astype(np.float64)
-            s = s + A[1].astype(np.float64) @ B[0].astype(np.float64)
-        return s.astype(np.float32)
-
     n = np.arange(16)
     F = np.exp(-2j * np.pi * np.outer(n, n) / 16)
     Fr = quant_parts(F.real, op_kind, split)
@@ -68,12 +56,7 @@ def emulate(xs, kind, split, op_kind=None, pass_a="mfma"):
         v = (x * 2.0 ** (4 - e)).astype(np.complex64)
         # pass A: radix 8 over x[j + 256 r]
         a = v.reshape(8, 256)
-        if pass_a == "mfma":
-            Ar, Ai = quant_parts(a.real, op_kind, split), quant_parts(a.imag, op_kind, split)
-            Gr, Gi = quant_parts(F8.real, op_kind, split), quant_parts(F8.imag, op_kind, split)
-            y = ((prod(Gr, Ar) - prod(Gi, Ai)) + 1j * (prod(Gi, Ar) + prod(Gr, Ai))).astype(np.complex64)
-        else:
-            y = (F8.astype(np.complex64) @ a).astype(np.complex64)  # y[m, j]
+        y = (F8.astype(np.complex64) @ a).astype(np.complex64)  # y[m, j]
         # Stockham layout after pass A: d = 8 j + m
         z = y.T.reshape(-1)
         # pass B input z[j + 128 r], twiddle w_128^{r (j mod 8)}
@@ -86,6 +69,12 @@ def emulate(xs, kind, split, op_kind=None, pass_a="mfma"):
             Xr = quant_parts(zz.real, op_kind, split)
             Xi = quant_parts(zz.imag, op_kind, split)
 
+            def prod(A, B):  # hi*hi + hi*lo + lo*hi, accumulated in fp64 then fp32
+                s = A[0].astype(np.float64) @ B[0].astype(np.float64)
+                if split:
+                    s = s + A[0].astype(np.float64) @ B[1].astype(np.float64)
+                    s = s + A[1].astype(np.float64) @ B[0].astype(np.float64)
+                return s.astype(np.float32)
             Yr = prod(Fr, Xr) - prod(Fi, Xi)
             Yi = prod(Fi, Xr) + prod(Fr, Xi)
             Y = (Yr + 1j * Yi).astype(np.complex64)  # [m, j]
