@@ -214,7 +214,7 @@ __device__ __forceinline__ void half_transform(const HalfCtx& c, uint32_t (&cur)
                                                float* red, const uint32_t* __restrict__ in,
                                                const int32_t* __restrict__ in_exp, uint32_t* __restrict__ out,
                                                int32_t* __restrict__ out_exp, int64_t b, int64_t refill,
-                                               int64_t batch, int scale_log2)
+                                               int scale_log2)
 {
     constexpr int dWC[4] = {0, 130, 264, 394};  // fC(d0 + 128 i) - fC(d0)
     // ---- pass A: radix 8 on the VALU in FP32 over x[tid + 256 m]
@@ -226,7 +226,7 @@ __device__ __forceinline__ void half_transform(const HalfCtx& c, uint32_t (&cur)
     // the cache): a load issued after the refill, or a refill under a
     // condition, would make the first wait below cover the refill as well.
     const int e_in = in_exp ? in_exp[b] : 0;
-    load_raw(cur, in, refill < batch ? refill : batch - 1, c.tid);
+    load_raw(cur, in, refill, c.tid);
     float mx = 0.f;
 #pragma unroll
     for (int m = 0; m < 8; m++)
@@ -331,35 +331,16 @@ __device__ __forceinline__ void half_transform(const HalfCtx& c, uint32_t (&cur)
         out_exp[b] = e_out;
 }
 
-// Persistent: a workgroup walks transforms blockIdx.x, + gridDim.x, ...,
-// with the inputs of the next two transforms in flight while one is
-// computed.  Two LDS buffers (and two raw register buffers) alternate
-// between consecutive transforms (loop unrolled twice so each body's
-// buffer roles are fixed), so three barriers suffice.
-template <int S, bool BF>
-__global__ __launch_bounds__(HWG, 4) void k_fft_half_2048(const uint32_t* __restrict__ in,
-                                                       const int32_t* __restrict__ in_exp,
-                                                       uint32_t* __restrict__ out, int32_t* __restrict__ out_exp,
-                                                       const cf* __restrict__ tw, int64_t batch, int scale_log2)
+// This thread's LDS bases and byte selector.
+__device__ __forceinline__ void init_offsets(HalfCtx& c)
 {
-    __shared__ uint32_t lds[2 * BUF];
-    __shared__ float s_red[2][HWG / 64];
-    int64_t b = blockIdx.x;
-    if (b >= batch)
-        return;
-    HalfCtx c;
     c.tid = threadIdx.x;
     c.lane = c.tid & 63;
     c.wave = c.tid >> 6;
     const int n = c.lane & 15, kq = c.lane >> 4, r0 = (kq & 1) * 8;
-    dft16_operands<S>(c.f_re, c.f_im, c.lane, 0, tw);
 #pragma unroll
     for (int gg = 0; gg < 2; gg++) {
         const int g = 2 * c.wave + gg;
-        dft16_operands<S>(c.a_re[gg], c.a_im[gg], c.lane, g, tw);
-#pragma unroll
-        for (int i = 0; i < 4; i++)  // w_2048^{n (g + 8 m)}, m = 4 kq + i
-            c.twB[gg][i] = tw_at<S>(tw, n * (g + 8 * (4 * kq + i)));
         c.oRB[gg] = fA(g + 8 * n + 128 * r0);
         c.oWB[gg] = fB(128 * n + g + 32 * kq);
         const int j = 16 * g + n;
@@ -370,45 +351,151 @@ __global__ __launch_bounds__(HWG, 4) void k_fft_half_2048(const uint32_t* __rest
     c.oWA = fA(8 * c.tid);
     c.oRS0 = fC(4 * c.tid);
     c.oRS1 = fC(4 * (c.tid + HWG));
+}
 
+// The per-thread constants: MFMA operands and twiddles gathered from the
+// FP32 twiddle table, LDS bases.
+template <int S>
+__device__ __forceinline__ void init_ctx(HalfCtx& c, const cf* __restrict__ tw)
+{
+    init_offsets(c);
+    const int n = c.lane & 15, kq = c.lane >> 4;
+    dft16_operands<S>(c.f_re, c.f_im, c.lane, 0, tw);
+#pragma unroll
+    for (int gg = 0; gg < 2; gg++) {
+        const int g = 2 * c.wave + gg;
+        dft16_operands<S>(c.a_re[gg], c.a_im[gg], c.lane, g, tw);
+#pragma unroll
+        for (int i = 0; i < 4; i++)  // w_2048^{n (g + 8 m)}, m = 4 kq + i
+            c.twB[gg][i] = tw_at<S>(tw, n * (g + 8 * (4 * kq + i)));
+    }
+}
+
+// The same constants as a table of CTX_VEC 16-byte words per thread, word k
+// of thread t at tab[k HWG + t] (coalesced loads): the operands f_re, f_im,
+// a_re[0], a_im[0], a_re[1], a_im[1], then twB[gg][2h], twB[gg][2h + 1] for
+// (gg, h) = (0, 0), (0, 1), (1, 0), (1, 1).  Built once per plan by
+// k_half_ctx_table from the gathers above, so both routes hold the same bits.
+constexpr int CTX_VEC = 10;
+
+__device__ __forceinline__ v4u cf2_word(cf a, cf b)
+{
+    return v4u{__builtin_bit_cast(uint32_t, a.x), __builtin_bit_cast(uint32_t, a.y), __builtin_bit_cast(uint32_t, b.x),
+               __builtin_bit_cast(uint32_t, b.y)};
+}
+
+template <int S>
+__global__ __launch_bounds__(HWG) void k_half_ctx_table(const cf* __restrict__ tw, v4u* __restrict__ tab)
+{
+    HalfCtx c;
+    init_ctx<S>(c, tw);
+    v4u* t = tab + c.tid;
+    t[0 * HWG] = __builtin_bit_cast(v4u, c.f_re.hi);
+    t[1 * HWG] = __builtin_bit_cast(v4u, c.f_im.hi);
+#pragma unroll
+    for (int gg = 0; gg < 2; gg++) {
+        t[(2 + 2 * gg) * HWG] = __builtin_bit_cast(v4u, c.a_re[gg].hi);
+        t[(3 + 2 * gg) * HWG] = __builtin_bit_cast(v4u, c.a_im[gg].hi);
+#pragma unroll
+        for (int h = 0; h < 2; h++)
+            t[(6 + 2 * gg + h) * HWG] = cf2_word(c.twB[gg][2 * h], c.twB[gg][2 * h + 1]);
+    }
+}
+
+// (Elements are copied out before the bit casts: a bit cast applied to a
+// vector element expression directly has been seen to read element 0.)
+__device__ __forceinline__ cf word_cf(const v4u& w, int h)
+{
+    const uint32_t re = w[2 * h], im = w[2 * h + 1];
+    return cf{__builtin_bit_cast(float, re), __builtin_bit_cast(float, im)};
+}
+
+__device__ __forceinline__ void load_ctx(HalfCtx& c, const v4u* __restrict__ tab)
+{
+    init_offsets(c);
+    v4u q[CTX_VEC];
+#pragma unroll
+    for (int k = 0; k < CTX_VEC; k++)
+        q[k] = tab[k * HWG + c.tid];
+    c.f_re.hi = __builtin_bit_cast(v8h, q[0]);
+    c.f_im.hi = __builtin_bit_cast(v8h, q[1]);
+#pragma unroll
+    for (int gg = 0; gg < 2; gg++) {
+        c.a_re[gg].hi = __builtin_bit_cast(v8h, q[2 + 2 * gg]);
+        c.a_im[gg].hi = __builtin_bit_cast(v8h, q[3 + 2 * gg]);
+#pragma unroll
+        for (int h = 0; h < 2; h++) {
+            c.twB[gg][2 * h] = word_cf(q[6 + 2 * gg + h], 0);
+            c.twB[gg][2 * h + 1] = word_cf(q[6 + 2 * gg + h], 1);
+        }
+    }
+}
+
+// Transforms per workgroup.  Measured at N = 2048, batch 32768 with the
+// input streamed from HBM: 4 (and 8) beat both shorter runs (1, 2: too
+// little in flight per workgroup) and a persistent grid of CUs x 4
+// workgroups looping over the batch (about 10% slower: the same copy
+// pattern without any arithmetic loses as much against a one-shot grid).
+constexpr int64_t kRun = 4;
+
+// A workgroup takes `per_wg` consecutive transforms (the last workgroup
+// fewer), with the inputs of the next two in flight while one is computed.
+// Past the end of its run the refill re-reads the batch's last transform,
+// which every workgroup shares through the cache, so the refill stays
+// unconditional.  Two LDS buffers (and two raw register buffers) alternate
+// between consecutive transforms (loop unrolled twice so each body's
+// buffer roles are fixed), so three barriers suffice.
+template <int S, bool BF>
+__global__ __launch_bounds__(HWG, 4) void k_fft_half_2048(const uint32_t* __restrict__ in,
+                                                       const int32_t* __restrict__ in_exp,
+                                                       uint32_t* __restrict__ out, int32_t* __restrict__ out_exp,
+                                                       const v4u* __restrict__ ctab, int64_t batch, int64_t per_wg,
+                                                       int scale_log2)
+{
+    __shared__ uint32_t lds[2 * BUF];
+    __shared__ float s_red[2][HWG / 64];
+    int64_t b = (int64_t)blockIdx.x * per_wg;
+    const int64_t end = b + per_wg < batch ? b + per_wg : batch;
+    const int64_t last = batch - 1;
+    uint32_t ua[8], ub[8];
+    load_raw(ua, in, b, threadIdx.x);
+    load_raw(ub, in, b + 1 < end ? b + 1 : last, threadIdx.x);
+    __builtin_amdgcn_sched_barrier(0);  // the first transform's loads are issued before the second's
+    HalfCtx c;
+    load_ctx(c, ctab);
     uint32_t* const buf0 = lds;
     uint32_t* const buf1 = lds + BUF;
-    uint32_t ua[8], ub[8];
-    const int64_t stride = gridDim.x;
-    load_raw(ua, in, b, c.tid);
-    load_raw(ub, in, b + stride < batch ? b + stride : batch - 1, c.tid);
-    __builtin_amdgcn_sched_barrier(0);  // the first transform's loads are issued before the second's
     while (true) {
-        half_transform<S, BF>(c, ua, buf0, buf1, s_red[0], in, in_exp, out, out_exp, b, b + 2 * stride, batch,
+        half_transform<S, BF>(c, ua, buf0, buf1, s_red[0], in, in_exp, out, out_exp, b, b + 2 < end ? b + 2 : last,
                               scale_log2);
-        b += stride;
-        if (b >= batch)
+        if (++b >= end)
             break;
-        half_transform<S, BF>(c, ub, buf1, buf0, s_red[1], in, in_exp, out, out_exp, b, b + 2 * stride, batch,
+        half_transform<S, BF>(c, ub, buf1, buf0, s_red[1], in, in_exp, out, out_exp, b, b + 2 < end ? b + 2 : last,
                               scale_log2);
-        b += stride;
-        if (b >= batch)
+        if (++b >= end)
             break;
     }
 }
 
-template <int S, bool BF>
-hipError_t launch_half(const void* in, const int32_t* in_exp, void* out, int32_t* out_exp, const void* tw,
-                       int64_t batch, int scale_log2, int64_t grid_limit, hipStream_t stream)
+// Largest grid of one launch: 2^32 - 1 work-items of HWG threads.
+constexpr int64_t kMaxGrid = (((int64_t)1 << 32) - 1) / HWG;
+
+// Transforms per workgroup: kRun, more only when the batch would need a
+// grid beyond one launch's limit.
+int64_t half_run_length(int64_t batch)
 {
-    const int64_t grid = grid_limit > 0 && batch > grid_limit ? grid_limit : batch;
-    return launch_kernel((k_fft_half_2048<S, BF>), dim3((unsigned)grid), dim3(HWG), 0, stream,
-                       static_cast<const uint32_t*>(in), in_exp, static_cast<uint32_t*>(out), out_exp,
-                       static_cast<const cf*>(tw), batch, scale_log2);
+    return (batch + kRun - 1) / kRun > kMaxGrid ? (batch + kMaxGrid - 1) / kMaxGrid : kRun;
 }
 
 template <int S, bool BF>
-int occupancy_half()
+hipError_t launch_half(const void* in, const int32_t* in_exp, void* out, int32_t* out_exp, const void* ctab,
+                       int64_t batch, int scale_log2, hipStream_t stream)
 {
-    int blocks = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_fft_half_2048<S, BF>, HWG, 0) != hipSuccess)
-        return 0;
-    return blocks;
+    const int64_t per_wg = half_run_length(batch);
+    const int64_t grid = (batch + per_wg - 1) / per_wg;
+    return launch_kernel((k_fft_half_2048<S, BF>), dim3((unsigned)grid), dim3(HWG), 0, stream,
+                         static_cast<const uint32_t*>(in), in_exp, static_cast<uint32_t*>(out), out_exp,
+                         static_cast<const v4u*>(ctab), batch, per_wg, scale_log2);
 }
 
 thread_local char g_hmsg[256] = "";
@@ -444,9 +531,9 @@ void register_half_small(const KernelHalfSmall& k) { small_reg().push_back(k); }
 struct HalfPlan {
     int64_t n = 0, batch = 0;
     int dtype = FFT_C16;
-    int64_t grid_limit[2] = {0, 0};  // CUs x resident workgroups, forward / inverse kernel
     const KernelHalfSmall* small[2] = {nullptr, nullptr};  // n < 2048: forward / inverse kernel
     void* rows = nullptr;                                  // their twiddle rows
+    void* ctx = nullptr;  // n = 2048: per-thread constant tables, forward then inverse
 };
 
 bool half_supported(int64_t n) { return n >= 2 && n <= HN && (n & (n - 1)) == 0; }
@@ -494,17 +581,21 @@ int half_create(HalfPlan** out, int64_t n, int64_t batch, int dtype, const void*
         *out = hp;
         return FFT_OK;
     }
-    int dev = 0, cus = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
-        snprintf(g_hmsg, sizeof g_hmsg, "cannot query the device's compute units");
-        delete hp;
-        return FFT_EHIP;
+    const size_t tab = (size_t)CTX_VEC * HWG * sizeof(v4u);
+    hipError_t e = hipMalloc(&hp->ctx, 2 * tab);
+    if (e == hipSuccess)
+        e = launch_kernel(k_half_ctx_table<-1>, dim3(1), dim3(HWG), 0, nullptr, static_cast<const cf*>(tw),
+                          static_cast<v4u*>(hp->ctx));
+    if (e == hipSuccess)
+        e = launch_kernel(k_half_ctx_table<1>, dim3(1), dim3(HWG), 0, nullptr, static_cast<const cf*>(tw),
+                          static_cast<v4u*>(hp->ctx) + CTX_VEC * HWG);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(nullptr);
+    if (e != hipSuccess) {
+        snprintf(g_hmsg, sizeof g_hmsg, "half-precision constant tables: %s", hipGetErrorString(e));
+        half_destroy(hp);
+        return e == hipErrorOutOfMemory ? FFT_ENOMEM : FFT_EHIP;
     }
-    const int occ_f = dtype == FFT_CBF16 ? occupancy_half<-1, true>() : occupancy_half<-1, false>();
-    const int occ_i = dtype == FFT_CBF16 ? occupancy_half<1, true>() : occupancy_half<1, false>();
-    hp->grid_limit[0] = (int64_t)cus * std::max(occ_f, 1);
-    hp->grid_limit[1] = (int64_t)cus * std::max(occ_i, 1);
     *out = hp;
     return FFT_OK;
 }
@@ -524,12 +615,13 @@ int half_execute(HalfPlan* hp, const void* in, const int32_t* in_exp, void* out,
         return FFT_OK;
     }
     const bool bf = hp->dtype == FFT_CBF16;
+    const v4u* ctab = static_cast<const v4u*>(hp->ctx) + (sign > 0 ? CTX_VEC * HWG : 0);
     if (sign < 0)
-        e = bf ? launch_half<-1, true>(in, in_exp, out, out_exp, tw, hp->batch, sl, hp->grid_limit[0], stream)
-               : launch_half<-1, false>(in, in_exp, out, out_exp, tw, hp->batch, sl, hp->grid_limit[0], stream);
+        e = bf ? launch_half<-1, true>(in, in_exp, out, out_exp, ctab, hp->batch, sl, stream)
+               : launch_half<-1, false>(in, in_exp, out, out_exp, ctab, hp->batch, sl, stream);
     else
-        e = bf ? launch_half<+1, true>(in, in_exp, out, out_exp, tw, hp->batch, sl, hp->grid_limit[1], stream)
-               : launch_half<+1, false>(in, in_exp, out, out_exp, tw, hp->batch, sl, hp->grid_limit[1], stream);
+        e = bf ? launch_half<+1, true>(in, in_exp, out, out_exp, ctab, hp->batch, sl, stream)
+               : launch_half<+1, false>(in, in_exp, out, out_exp, ctab, hp->batch, sl, stream);
     if (e != hipSuccess) {
         snprintf(g_hmsg, sizeof g_hmsg, "half-precision kernel launch: %s", hipGetErrorString(e));
         return FFT_EHIP;
@@ -541,6 +633,8 @@ void half_destroy(HalfPlan* hp)
 {
     if (hp && hp->rows)
         (void)hipFree(hp->rows);
+    if (hp && hp->ctx)
+        (void)hipFree(hp->ctx);
     delete hp;
 }
 
@@ -574,8 +668,8 @@ void half_query(int64_t n, int64_t batch, fft_plan_desc* d)
     d->batch = batch;
     d->ept = 8;
     d->wg = HWG;
-    d->transforms_per_wg = 1;
-    d->grid = batch;
+    d->transforms_per_wg = (int)half_run_length(batch);
+    d->grid = (batch + d->transforms_per_wg - 1) / d->transforms_per_wg;
     d->npasses = 3;
     d->radices[0] = 8;
     d->radices[1] = 16;
@@ -585,14 +679,6 @@ void half_query(int64_t n, int64_t batch, fft_plan_desc* d)
     d->variant = 0;
 }
 
-void half_describe(const HalfPlan* hp, fft_plan_desc* d)
-{
-    half_query(hp->n, hp->batch, d);
-    if (hp->small[0])
-        return;
-    const int64_t lim = hp->grid_limit[d->sign > 0 ? 1 : 0];
-    if (lim > 0 && d->grid > lim)
-        d->grid = lim;
-}
+void half_describe(const HalfPlan* hp, fft_plan_desc* d) { half_query(hp->n, hp->batch, d); }
 
 }  // namespace mifft

@@ -120,6 +120,14 @@ def test_half_precision_queries():
         assert rc == 0 and int(np.prod(list(d.radices)[: d.npasses])) == 1 << L
         assert d.scale == np.float32(1.0 / (1 << L))
     assert q(4096, 4, -1, 1)[0] == 1     # half precision stops at 2048
+    # N = 2048: runs of 4 consecutive transforms per workgroup, longer runs
+    # only when the grid would pass one launch's 2^32 - 1 work-items
+    max_grid = ((1 << 32) - 1) // 256
+    for batch in (1, 3, 4, 5, 32768, 4 * max_grid, 4 * max_grid + 1, 1 << 29):  # 2^40 elements
+        rc, d = q(2048, batch, -1, 2)
+        t = d.transforms_per_wg
+        assert rc == 0 and d.grid == -(-batch // t) and d.grid <= max_grid, batch
+        assert t == 4 if batch <= 4 * max_grid else (t - 1) * max_grid < batch <= t * max_grid, batch
     L = native.lib()
     assert L.fft_execute_scaled(None, None, None, None, None, None) == 5
 

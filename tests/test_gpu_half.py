@@ -98,9 +98,10 @@ def test_full_size_sampled(dtype, cls):
 
 
 def grid_limit(n, sign, dtype):
-    """Workgroups a plan of this length launches at most (CUs x resident
-    workgroups at N = 2048, the looping cap below), from describe()."""
-    p = api.Plan(n, 1 << 22 if n < N else 1 << 16, sign, dtype=dtype)
+    """Workgroups a plan of length n < 2048 launches at most (the looping
+    cap), and transforms per workgroup, from describe()."""
+    assert n < N
+    p = api.Plan(n, 1 << 22, sign, dtype=dtype)
     d = p.describe()
     p.close()
     return d["grid"], d["transforms_per_wg"]
@@ -122,35 +123,45 @@ def check_every_transform(yh, ex, xh, sign, n, tol, chunk_elems=1 << 22):
     return worst
 
 
+def run_length(sign, dtype, batch=1 << 16):
+    """Consecutive transforms per workgroup at N = 2048 (describe())."""
+    p = api.Plan(N, batch, sign, dtype=dtype)
+    d = p.describe()
+    p.close()
+    return d["transforms_per_wg"]
+
+
 @pytest.mark.parametrize("dtype", ["c16", "cbf16"])
 @pytest.mark.parametrize("cls", ["uniform", "loguniform"])
 @pytest.mark.parametrize("sign", [-1, 1])
-def test_persistent_loop_every_transform(dtype, cls, sign):
-    """A batch of 2.5 x the grid plus a ragged tail, so every workgroup runs
-    both bodies of the alternating-buffer loop (and some a third, partial
-    trip): every transform, forward and inverse, against the oracle."""
-    grid, _ = grid_limit(N, sign, dtype)
-    batch = (5 * grid) // 2 + 7
+def test_runs_every_transform(dtype, cls, sign):
+    """Workgroups take runs of consecutive transforms with the next two
+    prefetched, alternating two buffers: a batch of many runs and a partial
+    last run, so every workgroup runs both bodies of the loop and the last
+    one ends early.  Every transform, forward and inverse, against the oracle."""
+    t = run_length(sign, dtype)
+    batch = 1025 * t + t - 1
     x = draw(cls, batch, key=7)
     xh = to_half(x, dtype)
     del x
     p = api.Plan(N, batch, sign, dtype=dtype)
     d = p.describe()
-    print(f"[case] half loop {dtype} {cls} sign={sign} batch={batch} grid={d['grid']}", flush=True)
-    assert d["grid"] == grid and 2 * grid < batch
+    print(f"[case] half runs {dtype} {cls} sign={sign} batch={batch} {d}", flush=True)
+    assert t >= 2 and d["transforms_per_wg"] == t and d["grid"] == -(-batch // t)
     yh, ex = p.execute_scaled(xh)
     torch.cuda.synchronize()
     e = check_every_transform(yh, ex, xh, sign, N, TOL)
-    print(f"loop {dtype} {cls} sign={sign}: max rel L2 over {batch} transforms {e:.3e}")
+    print(f"runs {dtype} {cls} sign={sign}: max rel L2 over {batch} transforms {e:.3e}")
 
 
-def edge_batch(dtype, batch, grid):
+def edge_batch(dtype, batch, t):
     """Uniform transforms with special ones planted at both ends of the batch
-    and around the first loop trip.  Returns the stored input and the kinds."""
+    and around the first run boundaries (t transforms per workgroup).
+    Returns the stored input and the kinds."""
     rng = np.random.default_rng(11)
     x = draw("uniform", batch, key=8)
     kinds = {}
-    pos = [0, 1, grid - 1, grid, grid + 1, 2 * grid + 2, batch - 2, batch - 1]
+    pos = [0, 1, t - 1, t, t + 1, 2 * t + 2, batch - 2, batch - 1]
     specials = ["zero", "big", "tiny", "bottom", "inf", "bottom", "zero", "big"]
     for b, kind in zip(pos, specials):
         kinds[b] = kind
@@ -173,16 +184,16 @@ def edge_batch(dtype, batch, grid):
 @pytest.mark.parametrize("dtype", ["c16", "cbf16"])
 @pytest.mark.parametrize("sign", [-1, 1])
 def test_block_fp_edge_cases(dtype, sign):
-    """Block-floating-point edge cases inside a batch that runs the
-    persistent loop.  Documented results: an all-zero transform gives stored
+    """Block-floating-point edge cases inside a batch of many workgroups'
+    runs of transforms.  Documented results: an all-zero transform gives stored
     zeros (logical value 0); one with a component near FP16's maximum, one in
     FP16's subnormal range and one at the bottom of the storage format's
     range (BF16 subnormals) are each scaled into range and meet the 3e-3
     bar; a transform holding an inf gives non-finite values in that
     transform only.  Every other transform still meets the bar."""
-    grid, _ = grid_limit(N, sign, dtype)
-    batch = 2 * grid + 5
-    x, kinds = edge_batch(dtype, batch, grid)
+    t = run_length(sign, dtype)
+    batch = 64 * t + 5
+    x, kinds = edge_batch(dtype, batch, t)
     xh = to_half(x, dtype)
     p = api.Plan(N, batch, sign, dtype=dtype)
     print(f"[case] half edge {dtype} sign={sign} batch={batch} kinds={kinds}", flush=True)
