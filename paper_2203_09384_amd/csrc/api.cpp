@@ -365,6 +365,7 @@ struct mifft_plan_s {
     const KernelNd2* nd2_same = nullptr;
     const KernelNd2* nd2_opp = nullptr;
     void* nd2_rows[2] = {nullptr, nullptr};  // column, row transforms
+    int64_t nd2_grid_cap = 0;                // persistent single-pass 2D kernel: the device's CUs
 };
 
 namespace {
@@ -930,6 +931,11 @@ fft_plan create_nd2(const int64_t* dims, int64_t batch, int sign)
     p->dims[1] = dims[1];
     p->nd2_same = k;
     p->nd2_opp = find_nd2(L0, L1, -sign);
+    if (k->persistent) {
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess)
+            p->nd2_grid_cap = cus;
+    }
     if (make_twiddles(p) != FFT_OK) {
         free_plan(p);
         return nullptr;
@@ -1480,6 +1486,8 @@ int fft_plan_describe(fft_plan p, fft_plan_desc* d)
         d->wg = k->wg;
         d->transforms_per_wg = k->arrays_per_wg;
         d->grid = (p->batch + k->arrays_per_wg - 1) / k->arrays_per_wg;
+        if (p->nd2_grid_cap > 0 && d->grid > p->nd2_grid_cap)
+            d->grid = p->nd2_grid_cap;  // workgroups walk the batch
         int r0[8], r1[8];
         const int n0 = schedule(k->log2n0, k->log2ept, r0), n1 = schedule(k->log2n1, k->log2ept, r1);
         d->npasses = std::min(8, n0 + n1);

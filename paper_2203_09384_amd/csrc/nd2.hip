@@ -61,6 +61,29 @@ constexpr bool nd2_valid()
     return L0 >= 1 && L1 >= 1 && L0 + L1 <= 14 && Z::TPA <= 1024 && Z::TPT1 <= 64 && Z::LDS <= 160 * 1024;
 }
 
+// Twiddle-row entries (float2) of the column and row transforms.
+template <int L0, int L1>
+struct Nd2Rows {
+    using Z = Nd2Shape<L0, L1>;
+    static constexpr int R0 = Z::TPT0 > 1 ? Layout2<L0, Z::E>::rows_total() : 0;
+    static constexpr int R1 = Z::TPT1 > 1 ? Layout2<L1, Z::E>::rows_total() : 0;
+};
+
+// Arrays whose exchanges take more than half of a CU's 160 KiB of LDS run
+// one workgroup per CU, which then has nothing to overlap its loads and
+// stores with.  Those run persistent (k_nd2p) when the twiddle rows fit in
+// the LDS left over.
+template <int L0, int L1>
+constexpr bool nd2_persistent()
+{
+    using Z = Nd2Shape<L0, L1>;
+    using RW = Nd2Rows<L0, L1>;
+    // 1024-point rows excluded: at 1024 threads their registers spill
+    // (16 x 1024 measured 280 -> 348 us)
+    return Z::AP == 1 && 2 * Z::LDS > 160 * 1024 && Z::LDS + (RW::R0 + RW::R1) * 8 <= 160 * 1024 &&
+           Z::EPT % Sched<L0, Z::E>::NP == 0 && L1 < 10;
+}
+
 template <int L0, int L1, int S>
 __global__ __launch_bounds__((Nd2Shape<L0, L1>::WG)) void k_nd2(const cf* __restrict__ in, cf* __restrict__ out,
                                                              const cf* __restrict__ rows0,
@@ -117,11 +140,148 @@ __global__ __launch_bounds__((Nd2Shape<L0, L1>::WG)) void k_nd2(const cf* __rest
     }
 }
 
+// run2 (twiddle rows from `rows`) over workgroup-wide exchanges that calls
+// slice(P) before pass P, after that pass's twiddle row is read: the
+// caller's loads for the next array, spread over the passes.  The rows are
+// in LDS, so no wait for them covers the slices' global loads.
+template <int L, int E, int S, int P, class F>
+__device__ __forceinline__ void run2_slices(cf (&v)[1 << E], int t, const cf* rows, cf* lds, F& slice)
+{
+    using SC = Sched<L, E>;
+    cf w[SC::EPT];
+    if constexpr (SC::log2ns(P) > 0)
+        load_row<L, E, S, P>(w, rows, t);
+    slice(std::integral_constant<int, P>{});
+    pass_compute2<L, E, S, P>(v, w);
+    if constexpr (P + 1 < SC::NP) {
+        if constexpr (P > 0)
+            lds_sync<false>();  // all reads of the previous exchange are done
+        exchange2<L, E, P, false>(v, t, lds);
+        run2_slices<L, E, S, P + 1>(v, t, rows, lds, slice);
+    }
+}
+
+// Persistent form of k_nd2 for one array per workgroup (nd2_persistent):
+// a workgroup walks arrays g = blockIdx.x, + gridDim.x, ... .  While an
+// array's column passes run, the next array's row inputs are loaded into the
+// row registers (dead after the turn), a slice before each column pass; the
+// twiddle rows sit in LDS for the workgroup's life, so the only global
+// loads in the loop are the arrays themselves.  The loop body always
+// prefetches; the last array runs after it without (a prefetch under a
+// condition would make the wait for the next rows cover the stores too).
+template <int L0, int L1, int S>
+__global__ __launch_bounds__((Nd2Shape<L0, L1>::WG)) void k_nd2p(const cf* __restrict__ in, cf* __restrict__ out,
+                                                              const cf* __restrict__ rows0,
+                                                              const cf* __restrict__ rows1, int64_t batch, float scale)
+{
+    using Z = Nd2Shape<L0, L1>;
+    using RW = Nd2Rows<L0, L1>;
+    constexpr int E = Z::E, EPT = Z::EPT, N1 = Z::N1, N = Z::N, NP0 = Sched<L0, E>::NP;
+    static_assert(Z::AP == 1 && EPT % NP0 == 0, "one array per workgroup, whole slices");
+    __shared__ cf lds[Z::ASZ];
+    __shared__ cf trow[RW::R0 + RW::R1 > 0 ? RW::R0 + RW::R1 : 1];
+    const int tid = threadIdx.x;
+    int64_t g = blockIdx.x;
+    if (g >= batch)
+        return;
+    for (int i = tid; i < RW::R0 + RW::R1; i += Z::WG)
+        trow[i] = i < RW::R0 ? rows0[i] : rows1[i - RW::R0];
+    const cf* tr0 = trow;
+    const cf* tr1 = trow + RW::R0;
+    TwRegs<L1, E> tw1;
+#pragma unroll
+    for (int p = 0; p < Sched<L1, E>::NP; p++)
+#pragma unroll
+        for (int i = 0; i < EPT; i++)
+            tw1[p][i] = cf{1.f, 0.f};
+    TwRegs<L0, E> tw0;
+#pragma unroll
+    for (int p = 0; p < NP0; p++)
+#pragma unroll
+        for (int i = 0; i < EPT; i++)
+            tw0[p][i] = cf{1.f, 0.f};
+    const int r = tid / Z::TPT1, t = tid % Z::TPT1;  // rows: thread t of row r
+    const int c = tid % N1, t0 = tid / N1;           // columns: thread t0 of column c
+    const cf* src = in + r * N1 + t;                 // + g N + m TPT1: point t + m TPT1 of row r
+    cf* myrow = lds + r * Z::RS1;
+    cf* col = lds + c * Z::RS0;
+    cf a[EPT], v[EPT];
+#pragma unroll
+    for (int m = 0; m < EPT; m++)
+        a[m] = src[g * N + m * Z::TPT1];
+    __syncthreads();  // twiddle rows in place
+    // rows, the turn, and the column's points into v
+    auto rows_and_turn = [&]() {
+        run2<L1, E, S, 1, true>(a, t, tr1, tw1, myrow);
+        __syncthreads();  // every row's exchanges are read
+#pragma unroll
+        for (int m = 0; m < EPT; m++)
+            lds[(t + m * Z::TPT1) * Z::RS0 + r] = a[m];
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < EPT; m++)
+            v[m] = col[t0 + m * Z::TPT0];
+        if constexpr (Z::TPT0 > 1)
+            __syncthreads();  // the column is read before its exchanges overwrite it
+    };
+    auto store = [&]() {
+        cf* dst = out + g * N + c;
+#pragma unroll
+        for (int m = 0; m < EPT; m++)
+            dst[(t0 + m * Z::TPT0) * N1] = cscale(v[m], scale);
+    };
+    // The loop is rotated (rows of the next array at the end of the body), so
+    // the prefetched rows are used in the body that loaded them and the wait
+    // for them leaves the stores issued in between in flight.
+    const int64_t stride = gridDim.x;
+    int64_t left = (batch - 1 - g) / stride;
+    rows_and_turn();
+    while (left > 0) {
+        const cf* nsrc = src + (g + stride) * N;
+        auto slice = [&](auto pc) {
+            constexpr int P = decltype(pc)::value;
+#pragma unroll
+            for (int m = P * EPT / NP0; m < (P + 1) * EPT / NP0; m++)
+                a[m] = nsrc[m * Z::TPT1];
+        };
+        run2_slices<L0, E, S, 0>(v, t0, tr0, col, slice);
+        store();
+        g += stride;
+        --left;
+        __syncthreads();  // the column exchanges are read before the next rows use LDS
+        rows_and_turn();
+    }
+    run2<L0, E, S, 1, false>(v, t0, tr0, tw0, col);
+    store();
+}
+
+int nd2_cus()
+{
+    static int cached[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64)
+        return 0;
+    if (cached[dev] == 0) {
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            return 0;
+        cached[dev] = cus;
+    }
+    return cached[dev];
+}
+
 template <int L0, int L1, int S>
 hipError_t launch_nd2(const void* in, void* out, const void* rows0, const void* rows1, int64_t batch, float scale,
                       hipStream_t stream)
 {
     using Z = Nd2Shape<L0, L1>;
+    if constexpr (nd2_persistent<L0, L1>()) {
+        const int cus = nd2_cus();
+        const int64_t grid = cus > 0 && batch > cus ? cus : batch;  // one workgroup fills a CU's LDS
+        return launch_kernel((k_nd2p<L0, L1, S>), dim3((unsigned)grid), dim3(Z::WG), 0, stream,
+                             static_cast<const cf*>(in), static_cast<cf*>(out), static_cast<const cf*>(rows0),
+                             static_cast<const cf*>(rows1), batch, scale);
+    }
     const int64_t grid = (batch + Z::AP - 1) / Z::AP;
     return launch_kernel((k_nd2<L0, L1, S>), dim3((unsigned)grid), dim3(Z::WG), 0, stream,
                        static_cast<const cf*>(in), static_cast<cf*>(out), static_cast<const cf*>(rows0),
@@ -135,8 +295,9 @@ void add_nd2()
         using Z = Nd2Shape<L0, L1>;
         const int r0 = Z::TPT0 > 1 ? Layout2<L0, Z::E>::rows_total() : 0;
         const int r1 = Z::TPT1 > 1 ? Layout2<L1, Z::E>::rows_total() : 0;
-        register_nd2(KernelNd2{L0, L1, Z::E, -1, Z::AP, Z::WG, &launch_nd2<L0, L1, -1>, r0, r1, Z::LDS});
-        register_nd2(KernelNd2{L0, L1, Z::E, +1, Z::AP, Z::WG, &launch_nd2<L0, L1, +1>, r0, r1, Z::LDS});
+        constexpr bool P = nd2_persistent<L0, L1>();
+        register_nd2(KernelNd2{L0, L1, Z::E, -1, Z::AP, Z::WG, &launch_nd2<L0, L1, -1>, r0, r1, Z::LDS, P});
+        register_nd2(KernelNd2{L0, L1, Z::E, +1, Z::AP, Z::WG, &launch_nd2<L0, L1, +1>, r0, r1, Z::LDS, P});
     }
 }
 

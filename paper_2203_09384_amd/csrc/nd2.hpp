@@ -20,6 +20,7 @@ struct KernelNd2 {
     LaunchNd2 fn;
     int rows0, rows1;  // twiddle-row entries (float2)
     int lds_bytes;
+    bool persistent;   // one workgroup per CU walking the batch (grid: min(batch, CUs))
 };
 
 void register_nd2(const KernelNd2& k);

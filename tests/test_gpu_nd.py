@@ -113,6 +113,30 @@ def test_single_pass_full_size():
     assert per_array_relerr(to_cpu(back), x, 2) <= 2 * TOL
 
 
+@pytest.mark.parametrize("shape", [(128, 128), (64, 128), (256, 32), (32, 256)], ids=lambda s: "x".join(map(str, s)))
+def test_single_pass_persistent_every_array(shape):
+    """Arrays that fill more than half of a CU's LDS run one persistent
+    workgroup per CU (describe()'s grid is then below the batch): a batch of
+    2.5x that grid plus 3, so workgroups take two or three arrays through
+    the prefetching loop body and the last one after it.  Every array
+    against the oracle, both signs."""
+    big = 1 << 14
+    grid = api.PlanND(shape, big, -1).describe()["grid"]
+    assert grid < big
+    batch = grid * 5 // 2 + 3
+    n = int(np.prod(shape))
+    x = synth.uniform_complex(SEED_ND, (batch,) + shape, key=shape + (40,))
+    xg = to_gpu(x)
+    x64 = x.astype(np.complex128)
+    for sign in (-1, 1):
+        p = api.PlanND(shape, batch, sign)
+        print(f"[case] nd2 persistent {shape} batch={batch} sign={sign} {p.describe()}", flush=True)
+        assert p.describe()["grid"] == grid
+        y = to_cpu(p.execute(xg))
+        ref = oracle.fftn(x64, 2, sign, 1.0 if sign < 0 else 1.0 / n)
+        assert per_array_relerr(y, ref, 2) <= TOL
+
+
 @pytest.mark.parametrize("shape", [(128, 128), (2048, 64), (4, 64, 64)], ids=lambda s: "x".join(map(str, s)))
 def test_nd_run_to_run_bitwise_and_scaled_adjoint(shape):
     """Repeated executes give identical bits, and the inverse equals the
