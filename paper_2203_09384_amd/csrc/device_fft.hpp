@@ -505,7 +505,12 @@ __device__ __forceinline__ void store_group(const cf (&v)[1 << E], cf* __restric
     constexpr bool NT = stream_nt<N, TPT>();
     const int64_t first = g * TPB;
     char* gb = reinterpret_cast<char*>(out + first * N);
-    if (first + TPB <= batch || first + tb < batch) {
+    // One transform per group: every group a kernel stores (g < batch) is
+    // whole, and the stores carry no branch.  A branch around them would make
+    // the wait counter's bookkeeping after it allow for the stores not having
+    // been issued, so a later wait for a load issued before them would wait
+    // for the stores as well.
+    if (TPB == 1 || first + TPB <= batch || first + tb < batch) {
 #pragma unroll
         for (int m = 0; m < EPT; m++)
             st_data<NT>(gb + (toff8 + (unsigned)(m * TPT * 8)), cscale(v[m], scale));

@@ -151,18 +151,32 @@ __global__ __launch_bounds__(WG) void k_fft_c32_v2(const cf* __restrict__ in, cf
     // would let the path without it meet the path with it before the
     // current group is used, and the wait placed there would then cover
     // most of the prefetched loads.
+    //
+    // The loop is rotated so that its head is the b body: both edges into it
+    // come from an a body that has just issued b's loads and then a's
+    // stores, so the wait for b leaves those stores in flight.  (With the a
+    // body at the head, the edge from before the loop, where no stores are
+    // outstanding, would make that wait cover the stores on every trip.)
     const int64_t stride = gridDim.x;
     int64_t left = (ngroups - 1 - g) / stride;
-    while (left >= 2) {
+    if (left >= 2) {
         run2_prefetch<L, E, S, TW, WAVE, TPB>(a, t, rows, tws, my, b, in, g + stride, batch, tb, toff8);
         store_group<L, E, TPB>(a, out, g, batch, tb, toff8, scale);
         g += stride;
         lds_sync<WAVE>();  // LDS is reused by the next group
-        run2_prefetch<L, E, S, TW, WAVE, TPB>(b, t, rows, tws, my, a, in, g + stride, batch, tb, toff8);
-        store_group<L, E, TPB>(b, out, g, batch, tb, toff8, scale);
-        g += stride;
-        lds_sync<WAVE>();
-        left -= 2;
+        while (true) {
+            run2_prefetch<L, E, S, TW, WAVE, TPB>(b, t, rows, tws, my, a, in, g + stride, batch, tb, toff8);
+            store_group<L, E, TPB>(b, out, g, batch, tb, toff8, scale);
+            g += stride;
+            lds_sync<WAVE>();
+            left -= 2;
+            if (left < 2)
+                break;
+            run2_prefetch<L, E, S, TW, WAVE, TPB>(a, t, rows, tws, my, b, in, g + stride, batch, tb, toff8);
+            store_group<L, E, TPB>(a, out, g, batch, tb, toff8, scale);
+            g += stride;
+            lds_sync<WAVE>();
+        }
     }
     if (left == 1) {
         run2_prefetch<L, E, S, TW, WAVE, TPB>(a, t, rows, tws, my, b, in, g + stride, batch, tb, toff8);

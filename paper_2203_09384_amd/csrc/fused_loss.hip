@@ -127,7 +127,7 @@ __device__ __forceinline__ void loss_grad_group(cf (&v)[1 << E], cf (&nx)[1 << E
         // them and orders the forward's last exchange reads before the
         // adjoint's first writes (a separate barrier for the sum is not
         // needed).  `red` is next written after this group's adjoint
-        // exchanges, long after thread 0 has read it.
+        // exchanges, long after every reader has read it.
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1)
             part += __shfl_xor(part, off);
@@ -135,7 +135,16 @@ __device__ __forceinline__ void loss_grad_group(cf (&v)[1 << E], cf (&nx)[1 << E
         if ((t & 63) == 0)
             red[tb * W + (t >> 6)] = part;
         __syncthreads();
-        if (t == 0 && g * TPB + tb < batch) {
+        if constexpr (TPB == 1) {
+            // every thread stores the same sum to the same word: no branch
+            // around the store (one would make later waits allow for it
+            // not having been issued, and so cover the stores before it)
+            float s = 0.f;
+#pragma unroll
+            for (int i = 0; i < W; i++)
+                s += red[i];
+            loss[g] = s;
+        } else if (t == 0 && g * TPB + tb < batch) {
             float s = 0.f;
 #pragma unroll
             for (int i = 0; i < W; i++)
