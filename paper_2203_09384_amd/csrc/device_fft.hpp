@@ -324,19 +324,40 @@ struct Layout2 {
 };
 
 // Twiddles of pass P for thread t, read as EPT/2 16-byte loads of one row.
-template <int L, int E, int S, int P>
+// PAD > 0: the table is a copy whose rows of EPT values are padded to
+// EPT + PAD (copy_rows_padded), for LDS: with PAD = 2 the 16-byte reads of
+// 16 consecutive rows cover the 64 banks once (rows 144 bytes apart).
+template <int L, int E, int S, int P, int PAD = 0>
 __device__ __forceinline__ void load_row(cf (&w)[1 << E], const cf* __restrict__ rows, int t)
 {
     using SC = Sched<L, E>;
-    constexpr int EPT = SC::EPT, NS = 1 << SC::log2ns(P);
+    constexpr int EPT = SC::EPT, NS = 1 << SC::log2ns(P), RS = EPT + PAD;
     static_assert(SC::log2r(P) == E, "twiddled passes have radix EPT");
-    const float4* r4 = reinterpret_cast<const float4*>(rows + Layout2<L, E>::rows_offset(P) + (t & (NS - 1)) * EPT);
+    static_assert(PAD % 2 == 0, "rows stay 16-byte aligned");
+    const float4* r4 =
+        reinterpret_cast<const float4*>(rows + Layout2<L, E>::rows_offset(P) / EPT * RS + (t & (NS - 1)) * RS);
 #pragma unroll
     for (int i = 0; i < EPT / 2; i++) {
         const float4 q = r4[i];
         w[2 * i] = cf{q.x, S > 0 ? -q.y : q.y};
         w[2 * i + 1] = cf{q.z, S > 0 ? -q.w : q.w};
     }
+}
+
+// Copies the twiddle-row table `src` (rows of EPT values) to `dst` with each
+// row padded to EPT + PAD values, threads tid, tid + nthreads, ... .
+template <int L, int E, int PAD>
+__device__ __forceinline__ void copy_rows_padded(cf* dst, const cf* __restrict__ src, int tid, int nthreads)
+{
+    constexpr int EPT = 1 << E, TOT = Layout2<L, E>::rows_total();
+    for (int i = tid; i < TOT; i += nthreads)
+        dst[i / EPT * (EPT + PAD) + i % EPT] = src[i];
+}
+
+template <int L, int E, int PAD>
+__host__ __device__ constexpr int padded_rows_total()
+{
+    return Layout2<L, E>::rows_total() / (1 << E) * ((1 << E) + PAD);
 }
 
 // Twiddle + butterflies of pass P given the row values w (ignored if NS = 1).
@@ -531,7 +552,7 @@ __device__ __forceinline__ void load_all_rows(TwRegs<L, E>& tws, const cf* __res
     }
 }
 
-template <int L, int E, int S, int TW, bool WAVE, int P = 0>
+template <int L, int E, int S, int TW, bool WAVE, int P = 0, int PAD = 0>
 __device__ __forceinline__ void run2(cf (&v)[1 << E], int t, const cf* __restrict__ rows,
                                      const TwRegs<L, E>& tws, cf* lds)
 {
@@ -542,7 +563,7 @@ __device__ __forceinline__ void run2(cf (&v)[1 << E], int t, const cf* __restric
             pass_compute2<L, E, S, P>(v, tws[P]);
         } else {
             cf w[EPT];
-            load_row<L, E, S, P>(w, rows, t);
+            load_row<L, E, S, P, PAD>(w, rows, t);
             pass_compute2<L, E, S, P>(v, w);
         }
     } else {
@@ -552,14 +573,14 @@ __device__ __forceinline__ void run2(cf (&v)[1 << E], int t, const cf* __restric
         if constexpr (P > 0)
             lds_sync<WAVE>();  // all reads of the previous exchange are done
         exchange2<L, E, P, WAVE>(v, t, lds);
-        run2<L, E, S, TW, WAVE, P + 1>(v, t, rows, tws, lds);
+        run2<L, E, S, TW, WAVE, P + 1, PAD>(v, t, rows, tws, lds);
     }
 }
 
 // run2 that also loads the next group (transform group `gn` of `in`) into
 // `nx`, one slice before each pass, so a workgroup's loads reach HBM spread
 // over its passes rather than in one burst per group.
-template <int L, int E, int S, int TW, bool WAVE, int TPB, int P = 0>
+template <int L, int E, int S, int TW, bool WAVE, int TPB, int P = 0, int PAD = 0>
 __device__ __forceinline__ void run2_prefetch(cf (&v)[1 << E], int t, const cf* __restrict__ rows,
                                               const TwRegs<L, E>& tws, cf* lds, cf (&nx)[1 << E],
                                               const cf* __restrict__ in, int64_t gn, int64_t batch, int tb,
@@ -576,7 +597,7 @@ __device__ __forceinline__ void run2_prefetch(cf (&v)[1 << E], int t, const cf* 
             // it, its wait would cover the slice as well), and the
             // scheduling barrier keeps both ahead of the pass's arithmetic.
             cf w[EPT];
-            load_row<L, E, S, P>(w, rows, t);
+            load_row<L, E, S, P, PAD>(w, rows, t);
             load_group_part<L, E, TPB, P, SC::NP>(nx, in, gn, batch, tb, toff8);
             __builtin_amdgcn_sched_barrier(0);
             pass_compute2<L, E, S, P>(v, w);
@@ -591,7 +612,7 @@ __device__ __forceinline__ void run2_prefetch(cf (&v)[1 << E], int t, const cf* 
         if constexpr (P > 0)
             lds_sync<WAVE>();  // all reads of the previous exchange are done
         exchange2<L, E, P, WAVE>(v, t, lds);
-        run2_prefetch<L, E, S, TW, WAVE, TPB, P + 1>(v, t, rows, tws, lds, nx, in, gn, batch, tb, toff8);
+        run2_prefetch<L, E, S, TW, WAVE, TPB, P + 1, PAD>(v, t, rows, tws, lds, nx, in, gn, batch, tb, toff8);
     }
 }
 

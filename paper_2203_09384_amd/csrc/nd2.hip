@@ -61,12 +61,16 @@ constexpr bool nd2_valid()
     return L0 >= 1 && L1 >= 1 && L0 + L1 <= 14 && Z::TPA <= 1024 && Z::TPT1 <= 64 && Z::LDS <= 160 * 1024;
 }
 
-// Twiddle-row entries (float2) of the column and row transforms.
+// Twiddle-row entries (float2) of the column and row transforms as the
+// persistent kernel keeps them in LDS: rows padded by ROW_PAD values (see
+// load_row).
+constexpr int ROW_PAD = 2;
+
 template <int L0, int L1>
 struct Nd2Rows {
     using Z = Nd2Shape<L0, L1>;
-    static constexpr int R0 = Z::TPT0 > 1 ? Layout2<L0, Z::E>::rows_total() : 0;
-    static constexpr int R1 = Z::TPT1 > 1 ? Layout2<L1, Z::E>::rows_total() : 0;
+    static constexpr int R0 = Z::TPT0 > 1 ? padded_rows_total<L0, Z::E, ROW_PAD>() : 0;
+    static constexpr int R1 = Z::TPT1 > 1 ? padded_rows_total<L1, Z::E, ROW_PAD>() : 0;
 };
 
 // Arrays whose exchanges take more than half of a CU's 160 KiB of LDS run
@@ -150,7 +154,7 @@ __device__ __forceinline__ void run2_slices(cf (&v)[1 << E], int t, const cf* ro
     using SC = Sched<L, E>;
     cf w[SC::EPT];
     if constexpr (SC::log2ns(P) > 0)
-        load_row<L, E, S, P>(w, rows, t);
+        load_row<L, E, S, P, ROW_PAD>(w, rows, t);
     slice(std::integral_constant<int, P>{});
     pass_compute2<L, E, S, P>(v, w);
     if constexpr (P + 1 < SC::NP) {
@@ -165,7 +169,7 @@ __device__ __forceinline__ void run2_slices(cf (&v)[1 << E], int t, const cf* ro
 // a workgroup walks arrays g = blockIdx.x, + gridDim.x, ... .  While an
 // array's column passes run, the next array's row inputs are loaded into the
 // row registers (dead after the turn), a slice before each column pass; the
-// twiddle rows sit in LDS for the workgroup's life, so the only global
+// twiddle rows sit in LDS (padded) for the workgroup's life, so the only global
 // loads in the loop are the arrays themselves.  The loop body always
 // prefetches; the last array runs after it without (a prefetch under a
 // condition would make the wait for the next rows cover the stores too).
@@ -184,8 +188,10 @@ __global__ __launch_bounds__((Nd2Shape<L0, L1>::WG)) void k_nd2p(const cf* __res
     int64_t g = blockIdx.x;
     if (g >= batch)
         return;
-    for (int i = tid; i < RW::R0 + RW::R1; i += Z::WG)
-        trow[i] = i < RW::R0 ? rows0[i] : rows1[i - RW::R0];
+    if constexpr (RW::R0 > 0)
+        copy_rows_padded<L0, E, ROW_PAD>(trow, rows0, tid, Z::WG);
+    if constexpr (RW::R1 > 0)
+        copy_rows_padded<L1, E, ROW_PAD>(trow + RW::R0, rows1, tid, Z::WG);
     const cf* tr0 = trow;
     const cf* tr1 = trow + RW::R0;
     TwRegs<L1, E> tw1;
@@ -212,7 +218,7 @@ __global__ __launch_bounds__((Nd2Shape<L0, L1>::WG)) void k_nd2p(const cf* __res
     __syncthreads();  // twiddle rows in place
     // rows, the turn, and the column's points into v
     auto rows_and_turn = [&]() {
-        run2<L1, E, S, 1, true>(a, t, tr1, tw1, myrow);
+        run2<L1, E, S, 1, true, 0, ROW_PAD>(a, t, tr1, tw1, myrow);
         __syncthreads();  // every row's exchanges are read
 #pragma unroll
         for (int m = 0; m < EPT; m++)
@@ -251,7 +257,7 @@ __global__ __launch_bounds__((Nd2Shape<L0, L1>::WG)) void k_nd2p(const cf* __res
         __syncthreads();  // the column exchanges are read before the next rows use LDS
         rows_and_turn();
     }
-    run2<L0, E, S, 1, false>(v, t0, tr0, tw0, col);
+    run2<L0, E, S, 1, false, 0, ROW_PAD>(v, t0, tr0, tw0, col);
     store();
 }
 
