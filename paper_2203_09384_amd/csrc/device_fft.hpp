@@ -19,6 +19,8 @@
 // With this, thread t always holds elements t + m N/EPT (m < EPT) at the
 // start of every pass: a contiguous, coalesced pattern in HBM and in LDS.
 #pragma once
+
+#include <utility>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -613,6 +615,28 @@ __device__ __forceinline__ void run2_prefetch(cf (&v)[1 << E], int t, const cf* 
             lds_sync<WAVE>();  // all reads of the previous exchange are done
         exchange2<L, E, P, WAVE>(v, t, lds);
         run2_prefetch<L, E, S, TW, WAVE, TPB, P + 1, PAD>(v, t, rows, tws, lds, nx, in, gn, batch, tb, toff8);
+    }
+}
+
+// run2 over workgroup-wide exchanges (twiddle rows from `rows`, read with
+// the row padding PAD) that calls slice(P) before pass P, after that pass's
+// twiddle row is read: a caller's loads for its next tile, spread over the
+// passes.  With the rows in LDS no wait for a row covers the slices' global
+// loads.
+template <int L, int E, int S, int PAD, int P = 0, class F>
+__device__ __forceinline__ void run2_slices(cf (&v)[1 << E], int t, const cf* rows, cf* lds, F& slice)
+{
+    using SC = Sched<L, E>;
+    cf w[SC::EPT];
+    if constexpr (SC::log2ns(P) > 0)
+        load_row<L, E, S, P, PAD>(w, rows, t);
+    slice(std::integral_constant<int, P>{});
+    pass_compute2<L, E, S, P>(v, w);
+    if constexpr (P + 1 < SC::NP) {
+        if constexpr (P > 0)
+            lds_sync<false>();  // all reads of the previous exchange are done
+        exchange2<L, E, P, false>(v, t, lds);
+        run2_slices<L, E, S, PAD, P + 1>(v, t, rows, lds, slice);
     }
 }
 

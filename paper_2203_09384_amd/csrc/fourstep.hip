@@ -152,6 +152,11 @@ hipError_t launch_fourstep(const void* in, void* out, const void* rows1, const v
                                        static_cast<const cf*>(thi), t1);
     if (e != hipSuccess)
         return e;
+    // pass 2 is the axis pass of stride N1 over batch N1 transforms: the
+    // persistent form where it applies (1024-point rows)
+    hipError_t e2;
+    if (launch_axis_persistent<L2, S>(out, rows2, batch << L1, L1, scale, stream, &e2))
+        return e2;
     return launch_kernel((k_fourstep2<L1, L2, S>), dim3((unsigned)g2), dim3(WG2), 0, stream, static_cast<cf*>(out),
                        static_cast<const cf*>(rows2), batch << L1, scale);
 }

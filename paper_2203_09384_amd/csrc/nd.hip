@@ -46,6 +46,9 @@ template <int L, int S>
 hipError_t launch_axis(void* io, const void* rows, int64_t count, int log2s, float scale, hipStream_t stream)
 {
     constexpr int TILE = axis_tile(L);
+    hipError_t e;
+    if (launch_axis_persistent<L, S>(io, rows, count, log2s, scale, stream, &e))
+        return e;
     int64_t grid = (count + TILE - 1) / TILE;
     if (TILE < 16)
         grid = (grid + 127) & ~int64_t(127);  // whole chunks for the XCD grouping

@@ -144,27 +144,6 @@ __global__ __launch_bounds__((Nd2Shape<L0, L1>::WG)) void k_nd2(const cf* __rest
     }
 }
 
-// run2 (twiddle rows from `rows`) over workgroup-wide exchanges that calls
-// slice(P) before pass P, after that pass's twiddle row is read: the
-// caller's loads for the next array, spread over the passes.  The rows are
-// in LDS, so no wait for them covers the slices' global loads.
-template <int L, int E, int S, int P, class F>
-__device__ __forceinline__ void run2_slices(cf (&v)[1 << E], int t, const cf* rows, cf* lds, F& slice)
-{
-    using SC = Sched<L, E>;
-    cf w[SC::EPT];
-    if constexpr (SC::log2ns(P) > 0)
-        load_row<L, E, S, P, ROW_PAD>(w, rows, t);
-    slice(std::integral_constant<int, P>{});
-    pass_compute2<L, E, S, P>(v, w);
-    if constexpr (P + 1 < SC::NP) {
-        if constexpr (P > 0)
-            lds_sync<false>();  // all reads of the previous exchange are done
-        exchange2<L, E, P, false>(v, t, lds);
-        run2_slices<L, E, S, P + 1>(v, t, rows, lds, slice);
-    }
-}
-
 // Persistent form of k_nd2 for one array per workgroup (nd2_persistent):
 // a workgroup walks arrays g = blockIdx.x, + gridDim.x, ... .  While an
 // array's column passes run, the next array's row inputs are loaded into the
@@ -250,7 +229,7 @@ __global__ __launch_bounds__((Nd2Shape<L0, L1>::WG)) void k_nd2p(const cf* __res
             for (int m = P * EPT / NP0; m < (P + 1) * EPT / NP0; m++)
                 a[m] = nsrc[m * Z::TPT1];
         };
-        run2_slices<L0, E, S, 0>(v, t0, tr0, col, slice);
+        run2_slices<L0, E, S, ROW_PAD>(v, t0, tr0, col, slice);
         store();
         g += stride;
         --left;

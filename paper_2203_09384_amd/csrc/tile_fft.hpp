@@ -5,6 +5,7 @@
 #pragma once
 
 #include "device_fft.hpp"
+#include "launch.hpp"
 
 namespace mifft {
 
@@ -135,5 +136,154 @@ __device__ __forceinline__ void axis_tile_staged(cf* __restrict__ io, const cf* 
             st_c(io + addr(c, n), lds[c * ST + n]);
     }
 }
+
+// Kernels in this header are per translation unit (anonymous namespace),
+// like every kernel of the library.
+namespace {
+
+// Axis passes whose tile fills more than half of a CU's LDS (1024-point
+// axes: one 1024-thread workgroup per CU, which a workgroup per tile leaves
+// nothing to overlap with) run persistent when every tile is whole: a workgroup walks the tiles in the one-shot grid's order (rounds
+// of gridDim.x workgroups, so the XCD grouping of tiles sharing lines
+// holds), loading its next tile into a second register set a slice before
+// each pass.  The twiddle rows sit in LDS, padded, for the workgroup's
+// life.  The prefetched tile is waited for only after the current tile's
+// stores, which stay in flight.  With every tile whole no load or store is
+// conditional, and addresses are a uniform tile base plus a 32-bit
+// per-thread byte offset.
+constexpr int AX_ROW_PAD = 2;
+
+template <int L>
+constexpr int axis_lds_bytes()
+{
+    return axis_tile(L) * stage_stride<L, axis_e(L)>() * 8;
+}
+
+template <int L>
+constexpr bool axis_rows_in_lds()
+{
+    return axis_lds_bytes<L>() + padded_rows_total<L, axis_e(L), AX_ROW_PAD>() * 8 <= 160 * 1024;
+}
+
+// (At 2048 points the rows do not fit beside the tile, and reading them from
+// the cache before each pass costs registers: the second tile spills.)
+template <int L>
+constexpr bool axis_persistent()
+{
+    return axis_direct(L) && 2 * axis_lds_bytes<L>() > 160 * 1024 && axis_rows_in_lds<L>();
+}
+
+template <int L, int S>
+__global__ __launch_bounds__(axis_wg<L>()) void k_axis_p(cf* __restrict__ io, const cf* __restrict__ rows,
+                                                          int64_t ntiles, int log2s, float scale)
+{
+    constexpr int E = axis_e(L), TILE = axis_tile(L), LT = TILE == 16 ? 4 : 3, G = 16 / TILE;
+    constexpr int N = 1 << L, EPT = 1 << E, TPT = N / EPT, ST = stage_stride<L, E>(), WG = axis_wg<L>();
+    constexpr int NP = Sched<L, E>::NP;
+    constexpr bool RL = axis_rows_in_lds<L>();
+    constexpr int PAD = RL ? AX_ROW_PAD : 0;
+    __shared__ cf lds[TILE * ST];
+    __shared__ cf trow[RL ? padded_rows_total<L, E, AX_ROW_PAD>() : 1];
+    const int tid = threadIdx.x, c = tid & (TILE - 1), t = tid >> LT;
+    int64_t vb = blockIdx.x;
+    if (vb >= ntiles)
+        return;
+    if constexpr (RL)
+        copy_rows_padded<L, E, AX_ROW_PAD>(trow, rows, tid, WG);
+    const cf* rw = RL ? trow : rows;
+    cf* my = lds + c * ST;
+    const int64_t P = gridDim.x;
+    // Point t + m TPT of tile transform c lies c + ((t + m TPT) << log2s)
+    // elements past the tile's first element (the stride is at least TILE).
+    const unsigned loff = (unsigned)(c + (t << log2s)) * 8u;
+    const unsigned step8 = (unsigned)TPT << (log2s + 3);
+    auto tbase = [&](int64_t b) {
+        return reinterpret_cast<char*>(io + idx::axis_elem(idx::xcd_group_tile(b, G) * TILE, 0, L, log2s));
+    };
+    TwRegs<L, E> tws;
+    unit_rows<L, E>(tws);
+    cf a[EPT], bb[EPT];
+    {
+        const char* gb = tbase(vb);
+#pragma unroll
+        for (int m = 0; m < EPT; m++)
+            a[m] = ld_data<false>(gb + (loff + m * step8));
+    }
+    if constexpr (RL)
+        __syncthreads();  // twiddle rows in place
+    auto store = [&](const cf (&v)[EPT], int64_t b) {
+        char* gb = tbase(b);
+#pragma unroll
+        for (int m = 0; m < EPT; m++)
+            st_data<false>(gb + (loff + m * step8), cscale(v[m], scale));
+    };
+    // transform the tile at position b (in v) while loading position b + P into nx
+    auto run = [&](cf (&v)[EPT], cf (&nx)[EPT], int64_t b) {
+        const char* nb = tbase(b + P);
+        auto slice = [&](auto pc) {
+            constexpr int Q = decltype(pc)::value;
+#pragma unroll
+            for (int m = Q * EPT / NP; m < (Q + 1) * EPT / NP; m++)
+                nx[m] = ld_data<false>(nb + (loff + m * step8));
+        };
+        run2_slices<L, E, S, PAD>(v, t, rw, my, slice);
+        store(v, b);
+        __syncthreads();  // this tile's exchanges are read before the next tile's
+    };
+    // One body: the prefetched tile is copied into the working set at the
+    // body's end, after the stores, so the wait for it there leaves those
+    // stores in flight, and the body's code appears once.
+    for (int64_t left = (ntiles - 1 - vb) / P; left > 0; --left) {
+        run(a, bb, vb);
+#pragma unroll
+        for (int m = 0; m < EPT; m++)
+            a[m] = bb[m];
+        vb += P;
+    }
+    run2<L, E, S, 1, false, 0, PAD>(a, t, rw, tws, my);
+    store(a, vb);
+}
+
+inline int axis_cus()
+{
+    static int cached[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64)
+        return 0;
+    if (cached[dev] == 0) {
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            return 0;
+        cached[dev] = cus;
+    }
+    return cached[dev];
+}
+
+
+// Launches the persistent axis pass when it applies (axis_persistent, every
+// tile whole, every chunk of the XCD grouping full, rows of at least TILE
+// values so tiles are disjoint columns, and a transform's span addressable
+// with 32-bit byte offsets).  Returns false, launching nothing, otherwise.
+template <int L, int S>
+bool launch_axis_persistent(void* io, const void* rows, int64_t count, int log2s, float scale, hipStream_t stream,
+                            hipError_t* err)
+{
+    if constexpr (!axis_persistent<L>()) {
+        return false;
+    } else {
+        constexpr int TILE = axis_tile(L);
+        const int64_t ntiles = count / TILE;
+        const int cus = axis_cus();
+        const bool span32 = ((int64_t(1) << (L + log2s)) * 8) <= (int64_t(1) << 32);
+        if (count % TILE != 0 || ntiles % (128 / TILE) != 0 || log2s < (TILE == 16 ? 4 : 3) || !span32 || cus <= 0)
+            return false;
+        const int64_t g = ntiles < cus ? ntiles : cus;
+        *err = launch_kernel((k_axis_p<L, S>), dim3((unsigned)g), dim3(axis_wg<L>()), 0, stream, static_cast<cf*>(io),
+                             static_cast<const cf*>(rows), ntiles, log2s, scale);
+        return true;
+    }
+}
+
+}  // namespace
 
 }  // namespace mifft

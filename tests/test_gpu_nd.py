@@ -137,6 +137,22 @@ def test_single_pass_persistent_every_array(shape):
         assert per_array_relerr(y, ref, 2) <= TOL
 
 
+@pytest.mark.parametrize("sign", [-1, 1])
+def test_axis_pass_persistent_every_array(sign):
+    """1024-point axis passes whose tiles are all whole run one persistent
+    workgroup per CU: 1024 x 1024, batch 10, is 640 tiles of 16 columns, so
+    every workgroup takes two or three tiles (the prefetching body, then the
+    last tile).  Every array against the oracle."""
+    shape, batch = (1024, 1024), 10
+    n = int(np.prod(shape))
+    x = synth.uniform_complex(SEED_ND, (batch,) + shape, key=(41, sign + 1))
+    p = api.PlanND(shape, batch, sign)
+    print(f"[case] axis persistent {shape} batch={batch} sign={sign}", flush=True)
+    y = to_cpu(p.execute(to_gpu(x)))
+    ref = oracle.fftn(x.astype(np.complex128), 2, sign, 1.0 if sign < 0 else 1.0 / n)
+    assert per_array_relerr(y, ref, 2) <= TOL
+
+
 @pytest.mark.parametrize("shape", [(128, 128), (2048, 64), (4, 64, 64)], ids=lambda s: "x".join(map(str, s)))
 def test_nd_run_to_run_bitwise_and_scaled_adjoint(shape):
     """Repeated executes give identical bits, and the inverse equals the
