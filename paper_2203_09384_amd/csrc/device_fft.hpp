@@ -618,26 +618,59 @@ __device__ __forceinline__ void run2_prefetch(cf (&v)[1 << E], int t, const cf* 
     }
 }
 
-// run2 over workgroup-wide exchanges (twiddle rows from `rows`, read with
-// the row padding PAD) that calls slice(P) before pass P, after that pass's
-// twiddle row is read: a caller's loads for its next tile, spread over the
-// passes.  With the rows in LDS no wait for a row covers the slices' global
-// loads.
-template <int L, int E, int S, int PAD, int P = 0, class F>
-__device__ __forceinline__ void run2_slices(cf (&v)[1 << E], int t, const cf* rows, cf* lds, F& slice)
+// run2 over workgroup-wide exchanges that calls slice(P) before pass P,
+// after that pass's twiddle row is read: a caller's loads for its next tile,
+// spread over the passes.  Passes P < K read their rows from `lrows`, a copy
+// in LDS with the row padding PAD (copy_rows_padded, the first K passes'
+// rows); later passes from `grows`, the table itself.  A wait for an LDS
+// row covers none of the slices' global loads; a wait for a global row
+// covers the slices issued before it.
+template <int L, int E, int S, int PAD, int K, int P = 0, class F>
+__device__ __forceinline__ void run2_slices(cf (&v)[1 << E], int t, const cf* lrows, const cf* __restrict__ grows,
+                                            cf* lds, F& slice)
 {
     using SC = Sched<L, E>;
     cf w[SC::EPT];
-    if constexpr (SC::log2ns(P) > 0)
-        load_row<L, E, S, P, PAD>(w, rows, t);
+    if constexpr (SC::log2ns(P) > 0) {
+        if constexpr (P < K)
+            load_row<L, E, S, P, PAD>(w, lrows, t);
+        else
+            load_row<L, E, S, P, 0>(w, grows, t);
+    }
     slice(std::integral_constant<int, P>{});
     pass_compute2<L, E, S, P>(v, w);
     if constexpr (P + 1 < SC::NP) {
         if constexpr (P > 0)
             lds_sync<false>();  // all reads of the previous exchange are done
         exchange2<L, E, P, false>(v, t, lds);
-        run2_slices<L, E, S, PAD, P + 1>(v, t, rows, lds, slice);
+        run2_slices<L, E, S, PAD, K, P + 1>(v, t, lrows, grows, lds, slice);
     }
+}
+
+// Leading passes whose twiddle rows, padded by PAD, fit in `bytes` of LDS.
+template <int L, int E, int PAD>
+__host__ __device__ constexpr int rows_prefix_passes(int bytes)
+{
+    int k = 0;
+    while (k < Sched<L, E>::NP && Layout2<L, E>::rows_offset(k + 1) / (1 << E) * ((1 << E) + PAD) * 8 <= bytes)
+        k++;
+    return k;
+}
+
+// Entries (float2) of the padded LDS copy of the first K passes' rows.
+template <int L, int E, int PAD>
+__host__ __device__ constexpr int padded_rows_prefix(int K)
+{
+    return Layout2<L, E>::rows_offset(K) / (1 << E) * ((1 << E) + PAD);
+}
+
+// Copies the first K passes' rows of `src` to `dst`, padded as above.
+template <int L, int E, int PAD, int K>
+__device__ __forceinline__ void copy_rows_prefix_padded(cf* dst, const cf* __restrict__ src, int tid, int nthreads)
+{
+    constexpr int EPT = 1 << E, TOT = Layout2<L, E>::rows_offset(K);
+    for (int i = tid; i < TOT; i += nthreads)
+        dst[i / EPT * (EPT + PAD) + i % EPT] = src[i];
 }
 
 }  // namespace mifft

@@ -229,7 +229,7 @@ __global__ __launch_bounds__((Nd2Shape<L0, L1>::WG)) void k_nd2p(const cf* __res
             for (int m = P * EPT / NP0; m < (P + 1) * EPT / NP0; m++)
                 a[m] = nsrc[m * Z::TPT1];
         };
-        run2_slices<L0, E, S, ROW_PAD>(v, t0, tr0, col, slice);
+        run2_slices<L0, E, S, ROW_PAD, NP0>(v, t0, tr0, rows0, col, slice);
         store();
         g += stride;
         --left;

@@ -159,18 +159,21 @@ constexpr int axis_lds_bytes()
     return axis_tile(L) * stage_stride<L, axis_e(L)>() * 8;
 }
 
+// Passes whose twiddle rows sit in LDS beside the tile.
 template <int L>
-constexpr bool axis_rows_in_lds()
+constexpr int axis_lds_row_passes()
 {
-    return axis_lds_bytes<L>() + padded_rows_total<L, axis_e(L), AX_ROW_PAD>() * 8 <= 160 * 1024;
+    return rows_prefix_passes<L, axis_e(L), AX_ROW_PAD>(160 * 1024 - axis_lds_bytes<L>());
 }
 
-// (At 2048 points the rows do not fit beside the tile, and reading them from
-// the cache before each pass costs registers: the second tile spills.)
+// All rows must fit: at 2048 points only the first two passes' do, and
+// reading the last pass's row from the cache costs the registers the second
+// tile needs (128 bytes per lane spilled; 2D 2048 x 2048 459 -> 568 us).
 template <int L>
 constexpr bool axis_persistent()
 {
-    return axis_direct(L) && 2 * axis_lds_bytes<L>() > 160 * 1024 && axis_rows_in_lds<L>();
+    return axis_direct(L) && 2 * axis_lds_bytes<L>() > 160 * 1024 &&
+           axis_lds_row_passes<L>() == Sched<L, axis_e(L)>::NP;
 }
 
 template <int L, int S>
@@ -179,18 +182,14 @@ __global__ __launch_bounds__(axis_wg<L>()) void k_axis_p(cf* __restrict__ io, co
 {
     constexpr int E = axis_e(L), TILE = axis_tile(L), LT = TILE == 16 ? 4 : 3, G = 16 / TILE;
     constexpr int N = 1 << L, EPT = 1 << E, TPT = N / EPT, ST = stage_stride<L, E>(), WG = axis_wg<L>();
-    constexpr int NP = Sched<L, E>::NP;
-    constexpr bool RL = axis_rows_in_lds<L>();
-    constexpr int PAD = RL ? AX_ROW_PAD : 0;
+    constexpr int NP = Sched<L, E>::NP, K = axis_lds_row_passes<L>();
     __shared__ cf lds[TILE * ST];
-    __shared__ cf trow[RL ? padded_rows_total<L, E, AX_ROW_PAD>() : 1];
+    __shared__ cf trow[padded_rows_prefix<L, E, AX_ROW_PAD>(K) > 0 ? padded_rows_prefix<L, E, AX_ROW_PAD>(K) : 1];
     const int tid = threadIdx.x, c = tid & (TILE - 1), t = tid >> LT;
     int64_t vb = blockIdx.x;
     if (vb >= ntiles)
         return;
-    if constexpr (RL)
-        copy_rows_padded<L, E, AX_ROW_PAD>(trow, rows, tid, WG);
-    const cf* rw = RL ? trow : rows;
+    copy_rows_prefix_padded<L, E, AX_ROW_PAD, K>(trow, rows, tid, WG);
     cf* my = lds + c * ST;
     const int64_t P = gridDim.x;
     // Point t + m TPT of tile transform c lies c + ((t + m TPT) << log2s)
@@ -200,8 +199,6 @@ __global__ __launch_bounds__(axis_wg<L>()) void k_axis_p(cf* __restrict__ io, co
     auto tbase = [&](int64_t b) {
         return reinterpret_cast<char*>(io + idx::axis_elem(idx::xcd_group_tile(b, G) * TILE, 0, L, log2s));
     };
-    TwRegs<L, E> tws;
-    unit_rows<L, E>(tws);
     cf a[EPT], bb[EPT];
     {
         const char* gb = tbase(vb);
@@ -209,8 +206,7 @@ __global__ __launch_bounds__(axis_wg<L>()) void k_axis_p(cf* __restrict__ io, co
         for (int m = 0; m < EPT; m++)
             a[m] = ld_data<false>(gb + (loff + m * step8));
     }
-    if constexpr (RL)
-        __syncthreads();  // twiddle rows in place
+    __syncthreads();  // twiddle rows in place
     auto store = [&](const cf (&v)[EPT], int64_t b) {
         char* gb = tbase(b);
 #pragma unroll
@@ -226,7 +222,7 @@ __global__ __launch_bounds__(axis_wg<L>()) void k_axis_p(cf* __restrict__ io, co
             for (int m = Q * EPT / NP; m < (Q + 1) * EPT / NP; m++)
                 nx[m] = ld_data<false>(nb + (loff + m * step8));
         };
-        run2_slices<L, E, S, PAD>(v, t, rw, my, slice);
+        run2_slices<L, E, S, AX_ROW_PAD, K>(v, t, trow, rows, my, slice);
         store(v, b);
         __syncthreads();  // this tile's exchanges are read before the next tile's
     };
@@ -240,7 +236,8 @@ __global__ __launch_bounds__(axis_wg<L>()) void k_axis_p(cf* __restrict__ io, co
             a[m] = bb[m];
         vb += P;
     }
-    run2<L, E, S, 1, false, 0, PAD>(a, t, rw, tws, my);
+    auto none = [](auto) {};
+    run2_slices<L, E, S, AX_ROW_PAD, K>(a, t, trow, rows, my, none);
     store(a, vb);
 }
 

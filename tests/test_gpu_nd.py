@@ -137,15 +137,16 @@ def test_single_pass_persistent_every_array(shape):
         assert per_array_relerr(y, ref, 2) <= TOL
 
 
+@pytest.mark.parametrize("shape,batch", [((1024, 1024), 10), ((2048, 1024), 5)], ids=["1024x1024", "2048x1024"])
 @pytest.mark.parametrize("sign", [-1, 1])
-def test_axis_pass_persistent_every_array(sign):
+def test_axis_pass_persistent_every_array(shape, batch, sign):
     """1024-point axis passes whose tiles are all whole run one persistent
     workgroup per CU: 1024 x 1024, batch 10, is 640 tiles of 16 columns, so
     every workgroup takes two or three tiles (the prefetching body, then the
-    last tile).  Every array against the oracle."""
-    shape, batch = (1024, 1024), 10
+    last tile).  2048 x 1024, batch 5 (640 tiles of 8 columns) runs the
+    one-shot 2048-point pass next to it.  Every array against the oracle."""
     n = int(np.prod(shape))
-    x = synth.uniform_complex(SEED_ND, (batch,) + shape, key=(41, sign + 1))
+    x = synth.uniform_complex(SEED_ND, (batch,) + shape, key=(41, shape[0], sign + 1))
     p = api.PlanND(shape, batch, sign)
     print(f"[case] axis persistent {shape} batch={batch} sign={sign}", flush=True)
     y = to_cpu(p.execute(to_gpu(x)))
