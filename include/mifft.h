@@ -114,7 +114,9 @@ typedef struct {
                            transform per thread (n <= 16) with the block
                            staged through LDS in 16-byte vectors; 12 the
                            same staging for n = 32, 64 (several threads
-                           per transform, wavefront-local exchanges)   */
+                           per transform, wavefront-local exchanges);
+                           13 the single-pass 3D kernel (multidimensional
+                           plans)                                      */
     int ept_by_log2n[12]; /* ragged: elements per thread used for length 2^L */
     int rank;           /* multidimensional plans: number of axes (else 0)   */
     int64_t dims[3];    /* multidimensional plans: axis lengths, first to last */
@@ -211,8 +213,11 @@ fft_plan fft_plan_create_ragged_config(int64_t count, const int64_t *offsets, in
  * one workgroup's LDS (at most 16384 points, both axes >= 16 points per
  * thread group, e.g. 128 x 128) instead runs one kernel: rows, a
  * transpose through LDS and columns, one pass over HBM
- * (fft_plan_desc.variant 10); a 3D plan whose last two axes form such an
- * array runs that kernel over them, then one pass for its first axis.
+ * (fft_plan_desc.variant 10).  A 3D array that fits one workgroup's LDS
+ * (at most 16384 points, every axis at least 4) runs one kernel as well:
+ * the three axes with two transposes through LDS, one pass over HBM
+ * (variant 13).  Otherwise a 3D plan whose last two axes form a single-pass
+ * 2D array runs that kernel over them, then one pass for its first axis.
  *   rank   1, 2 or 3 (rank 1 is fft_plan_create).
  *   dims   host array of `rank` powers of two: the last in [2, 2^20], the
  *          others in [2, 2048].  Copied into the plan.

@@ -37,6 +37,7 @@ def _units():
     units.append(("fourstep.hip", "fourstep.o", []))
     units.append(("nd.hip", "nd.o", []))
     units.append(("nd2.hip", "nd2.o", []))
+    units.append(("nd3.hip", "nd3.o", []))
     for wg in (64, 128, 256):
         units.append(("ragged.hip", f"ragged_wg{wg}.o", [f"-DMIFFT_RAGGED_WG={wg}"]))
     units.append(("ragged_plan.cpp", "ragged_plan.o", ["-x", "hip"]))

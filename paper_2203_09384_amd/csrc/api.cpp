@@ -22,6 +22,7 @@
 #include "index_maps.hpp"
 #include "nd.hpp"
 #include "nd2.hpp"
+#include "nd3.hpp"
 #include "ragged.hpp"
 #include "real.hpp"
 #include "registry.hpp"
@@ -156,6 +157,19 @@ static std::vector<KernelNd2>& nd2_reg()
     return r;
 }
 void register_nd2(const KernelNd2& k) { nd2_reg().push_back(k); }
+static std::vector<KernelNd3>& nd3_reg()
+{
+    static std::vector<KernelNd3> r;
+    return r;
+}
+void register_nd3(const KernelNd3& k) { nd3_reg().push_back(k); }
+const KernelNd3* find_nd3(int log2n0, int log2n1, int log2n2, int sign)
+{
+    for (const auto& k : nd3_reg())
+        if (k.log2n[0] == log2n0 && k.log2n[1] == log2n1 && k.log2n[2] == log2n2 && k.sign == sign)
+            return &k;
+    return nullptr;
+}
 const KernelNd2* find_nd2(int log2n0, int log2n1, int sign)
 {
     for (const auto& k : nd2_reg())
@@ -366,6 +380,9 @@ struct mifft_plan_s {
     const KernelNd2* nd2_opp = nullptr;
     void* nd2_rows[2] = {nullptr, nullptr};  // column, row transforms
     int64_t nd2_grid_cap = 0;                // persistent single-pass 2D kernel: the device's CUs
+    const KernelNd3* nd3_same = nullptr;     // single-pass 3D kernel (this sign / the opposite one)
+    const KernelNd3* nd3_opp = nullptr;
+    void* nd3_rows = nullptr;                // its twiddle rows, axes 0, 1, 2 back to back
 };
 
 namespace {
@@ -675,7 +692,7 @@ void free_plan(mifft_plan_s* p)
     for (void* q : {p->real_ws, p->real_tw})
         if (q)
             (void)hipFree(q);
-    for (void* q : {p->ax_rows[0], p->ax_rows[1], p->nd2_rows[0], p->nd2_rows[1]})
+    for (void* q : {p->ax_rows[0], p->ax_rows[1], p->nd2_rows[0], p->nd2_rows[1], p->nd3_rows})
         if (q)
             (void)hipFree(q);
     if (p->ragged)
@@ -965,6 +982,70 @@ fft_plan create_nd2(const int64_t* dims, int64_t batch, int sign)
     return p;
 }
 
+// A 3D plan whose arrays fit one workgroup's LDS: one kernel, one HBM pass.
+fft_plan create_nd3(const int64_t* dims, int64_t batch, int sign)
+{
+    const int L[3] = {ilog2(dims[0]), ilog2(dims[1]), ilog2(dims[2])};
+    const KernelNd3* k = find_nd3(L[0], L[1], L[2], sign);
+    if ((batch + k->arrays_per_wg - 1) / k->arrays_per_wg > 0x7fffffffLL) {
+        set_err(FFT_EINVAL_BATCH, "batch=%lld needs more than 2^31-1 workgroups", (long long)batch);
+        return nullptr;
+    }
+    int dev = -1;
+    if (current_gfx950(&dev) != FFT_OK)
+        return nullptr;
+    auto* p = new (std::nothrow) mifft_plan_s();
+    if (!p) {
+        set_err(FFT_ENOMEM, "out of host memory");
+        return nullptr;
+    }
+    p->kind = 2;
+    p->n = dims[0] * dims[1] * dims[2];
+    p->batch = batch;
+    p->sign = sign;
+    p->dtype = FFT_C32;
+    p->scale = sign > 0 ? 1.0f / (float)p->n : 1.0f;
+    p->device = dev;
+    p->log2n = L[0] + L[1] + L[2];
+    p->total = p->n * batch;
+    p->rank = 3;
+    for (int a = 0; a < 3; a++)
+        p->dims[a] = dims[a];
+    p->nd3_same = k;
+    p->nd3_opp = find_nd3(L[0], L[1], L[2], -sign);
+    if (make_twiddles(p) != FFT_OK) {
+        free_plan(p);
+        return nullptr;
+    }
+    const int total = k->rows[0] + k->rows[1] + k->rows[2];
+    if (total > 0) {
+        hipError_t e = hipMalloc(&p->nd3_rows, (size_t)total * sizeof(float2));
+        if (e != hipSuccess) {
+            p->nd3_rows = nullptr;
+            e == hipErrorOutOfMemory ? set_err(FFT_ENOMEM, "hipMalloc(3D twiddle rows) failed")
+                                     : hip_err(e, "hipMalloc(3D twiddle rows)");
+            free_plan(p);
+            return nullptr;
+        }
+        int off = 0;
+        for (int a = 0; a < 3 && e == hipSuccess; a++) {
+            if (k->rows[a] > 0)
+                e = launch_twiddle_rows(p->tw, static_cast<float2*>(p->nd3_rows) + off, L[a], k->log2ept, k->rows[a],
+                                        nullptr);
+            off += k->rows[a];
+        }
+        if (e == hipSuccess)
+            e = hipStreamSynchronize(nullptr);
+        if (e != hipSuccess) {
+            hip_err(e, "3D twiddle rows");
+            free_plan(p);
+            return nullptr;
+        }
+    }
+    ok();
+    return p;
+}
+
 fft_plan create_nd(int rank, const int64_t* dims, int64_t batch, int sign, int dtype)
 {
     if (!dims) {
@@ -1023,6 +1104,9 @@ fft_plan create_nd(int rank, const int64_t* dims, int64_t batch, int sign, int d
     if (rank == 2 && find_nd2(ilog2(dims[0]), ilog2(dims[1]), sign) &&
         find_nd2(ilog2(dims[0]), ilog2(dims[1]), -sign))
         return create_nd2(dims, batch, sign);
+    if (rank == 3 && find_nd3(ilog2(dims[0]), ilog2(dims[1]), ilog2(dims[2]), sign) &&
+        find_nd3(ilog2(dims[0]), ilog2(dims[1]), ilog2(dims[2]), -sign))
+        return create_nd3(dims, batch, sign);
     // The trailing axes handled by the sub-plan: the last one (batched 1D),
     // or for 3D the last two when they fit the single-pass 2D kernel.
     const bool tail2 = rank == 3 && find_nd2(ilog2(dims[1]), ilog2(dims[2]), sign) &&
@@ -1163,6 +1247,13 @@ int exec_real(fft_plan p, const void* in, void* out, bool to_bins, float we, flo
 // direction: the sign of the exponent actually applied; scale as given.
 int exec_c32(fft_plan p, const void* in, void* out, int sign, float scale, hipStream_t st)
 {
+    if (p->kind == 2 && p->nd3_same) {
+        const KernelNd3* k = sign == p->sign ? p->nd3_same : p->nd3_opp;
+        hipError_t e = k->fn(in, out, p->nd3_rows, p->batch, p->scale, st);
+        if (e != hipSuccess)
+            return hip_err(e, "3D kernel launch");
+        return ok();
+    }
     if (p->kind == 2 && p->nd2_same) {
         const KernelNd2* k = sign == p->sign ? p->nd2_same : p->nd2_opp;
         hipError_t e = k->fn(in, out, p->nd2_rows[0], p->nd2_rows[1], p->batch, p->scale, st);
@@ -1474,6 +1565,34 @@ int fft_plan_describe(fft_plan p, fft_plan_desc* d)
 {
     if (!p || !d)
         return set_err(FFT_ENULL, "plan or desc is NULL");
+    if (p->kind == 2 && p->nd3_same) {
+        const KernelNd3* k = p->nd3_same;
+        memset(d, 0, sizeof *d);
+        d->n = p->n;
+        d->batch = p->batch;
+        d->sign = p->sign;
+        d->dtype = FFT_C32;
+        d->scale = p->scale;
+        d->ept = 1 << k->log2ept;
+        d->wg = k->wg;
+        d->transforms_per_wg = k->arrays_per_wg;
+        d->grid = (p->batch + k->arrays_per_wg - 1) / k->arrays_per_wg;
+        int np = 0;
+        for (int a = 2; a >= 0; a--) {  // passes in execution order: axis 2, 1, 0
+            int r[8];
+            const int na = schedule(k->log2n[a], k->log2ept, r);
+            for (int i = 0; i < na && np < 8; i++)
+                d->radices[np++] = r[i];
+        }
+        d->npasses = np;
+        d->lds_bytes = k->lds_bytes;
+        d->kind = 2;
+        d->variant = 13;
+        d->rank = 3;
+        for (int a = 0; a < 3; a++)
+            d->dims[a] = p->dims[a];
+        return ok();
+    }
     if (p->kind == 2 && p->nd2_same) {
         const KernelNd2* k = p->nd2_same;
         memset(d, 0, sizeof *d);

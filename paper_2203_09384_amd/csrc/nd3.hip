@@ -1,0 +1,209 @@
+// Single-pass 3D transforms of arrays that fit one workgroup's LDS
+// (N0 x N1 x N2 <= 16384 points, every axis at least 4): one HBM pass
+// instead of two or three.
+//
+// The 3D DFT factors into a DFT along each axis in turn (its kernel is a
+// product over the axes).  A workgroup holds AP whole arrays; all of an
+// array's points are in registers at once (N / EPT threads, EPT points
+// each), and two turns through LDS bring each axis's lines together:
+//   axis 2   thread (r, t) loads points t + m TPT2 of row r (r = i0 N1 + i1)
+//            straight from HBM and runs the Stockham passes in row r's own
+//            LDS region (a row's threads share a wavefront);
+//   turn     each result goes to LDS so that the axis-1 line (i0, i2) is
+//            contiguous at stride RS1 (odd, for the banks);
+//   axis 1   thread (l, t1), the line index l fastest, reads points
+//            t1 + m TPT1 of line l and runs the passes in that line's place
+//            (workgroup barriers: a line's threads span wavefronts);
+//   turn     the results go to LDS so that the axis-0 line (i1, i2) is
+//            contiguous at stride RS0;
+//   axis 0   thread (c, t0), c = i1 N2 + i2 fastest, transforms line c and
+//            stores X[n0][i1][i2] straight to HBM: consecutive lanes,
+//            consecutive addresses.
+#include "device_fft.hpp"
+#include "launch.hpp"
+#include "nd3.hpp"
+
+#include <utility>
+
+namespace mifft {
+namespace {
+
+constexpr int nd3_e(int L0, int L1, int L2)
+{
+    int m = L0 < L1 ? L0 : L1;
+    m = m < L2 ? m : L2;
+    return m < 4 ? m : 4;
+}
+
+// Line stride of a turned layout: the Stockham region, rounded up to an
+// odd number of complex values so that lanes reading consecutive lines
+// spread over the banks.
+template <int L, int E>
+constexpr int line_stride()
+{
+    const int r = Layout2<L, E>::region();
+    return (r & 1) ? r : r + 1;
+}
+
+template <int L0, int L1, int L2>
+struct Nd3Shape {
+    static constexpr int E = nd3_e(L0, L1, L2), EPT = 1 << E;
+    static constexpr int N0 = 1 << L0, N1 = 1 << L1, N2 = 1 << L2, N = N0 * N1 * N2;
+    static constexpr int TPA = N / EPT;                    // threads per array
+    static constexpr int AP = TPA >= 256 ? 1 : 256 / TPA;  // arrays per workgroup
+    static constexpr int WG = AP * TPA;
+    static constexpr int TPT0 = N0 / EPT, TPT1 = N1 / EPT, TPT2 = N2 / EPT;
+    static constexpr int RS2 = Layout2<L2, E>::region();  // row stride (axis-2 phase)
+    static constexpr int RS1 = line_stride<L1, E>();      // axis-1 line stride
+    static constexpr int RS0 = line_stride<L0, E>();      // axis-0 line stride
+    static constexpr int A2 = N0 * N1 * RS2, A1 = N0 * N2 * RS1, A0 = N1 * N2 * RS0;
+    static constexpr int ASZ = A2 > A1 ? (A2 > A0 ? A2 : A0) : (A1 > A0 ? A1 : A0);  // LDS per array
+    static constexpr int LDS = AP * ASZ * 8;
+    static constexpr int R0 = TPT0 > 1 ? Layout2<L0, E>::rows_total() : 0;
+    static constexpr int R1 = TPT1 > 1 ? Layout2<L1, E>::rows_total() : 0;
+    static constexpr int R2 = TPT2 > 1 ? Layout2<L2, E>::rows_total() : 0;
+};
+
+template <int L0, int L1, int L2>
+constexpr bool nd3_valid()
+{
+    if constexpr (L0 < 2 || L1 < 2 || L2 < 2 || L0 + L1 + L2 > 14) {
+        return false;
+    } else {
+        using Z = Nd3Shape<L0, L1, L2>;
+        return Z::TPA <= 1024 && Z::TPT2 <= 64 && Z::LDS <= 160 * 1024;
+    }
+}
+
+template <int L, int E>
+__device__ __forceinline__ void unit_tw(TwRegs<L, E>& tws)
+{
+#pragma unroll
+    for (int p = 0; p < Sched<L, E>::NP; p++)
+#pragma unroll
+        for (int i = 0; i < (1 << E); i++)
+            tws[p][i] = cf{1.f, 0.f};
+}
+
+template <int L0, int L1, int L2, int S>
+__global__ __launch_bounds__((Nd3Shape<L0, L1, L2>::WG)) void k_nd3(const cf* __restrict__ in, cf* __restrict__ out,
+                                                                 const cf* __restrict__ rows, int64_t batch,
+                                                                 float scale)
+{
+    using Z = Nd3Shape<L0, L1, L2>;
+    constexpr int E = Z::E, EPT = Z::EPT, N0 = Z::N0, N1 = Z::N1, N2 = Z::N2, N = Z::N;
+    __shared__ cf lds[Z::AP * Z::ASZ];
+    const cf* rows0 = rows;
+    const cf* rows1 = rows + Z::R0;
+    const cf* rows2 = rows + Z::R0 + Z::R1;
+    const int tid = threadIdx.x, a = tid / Z::TPA, u = tid % Z::TPA;
+    const int64_t arr = (int64_t)blockIdx.x * Z::AP + a;
+    const bool live = arr < batch;
+    cf* my = lds + a * Z::ASZ;
+    cf v[EPT];
+    // ---- axis 2 (rows r = i0 N1 + i1)
+    {
+        TwRegs<L2, E> tw;
+        unit_tw<L2, E>(tw);
+        const int r = u / Z::TPT2, t = u % Z::TPT2;
+        const cf* src = in + arr * N + r * N2;
+#pragma unroll
+        for (int m = 0; m < EPT; m++)
+            v[m] = live ? src[t + m * Z::TPT2] : cf{0.f, 0.f};
+        run2<L2, E, S, 1, true>(v, t, rows2, tw, my + r * Z::RS2);
+        __syncthreads();  // every row's exchanges are read
+        const int i0 = r / N1, i1 = r % N1;
+#pragma unroll
+        for (int m = 0; m < EPT; m++)
+            my[(i0 * N2 + t + m * Z::TPT2) * Z::RS1 + i1] = v[m];  // line (i0, i2), point i1
+        __syncthreads();
+    }
+    // ---- axis 1 (lines l = i0 N2 + i2)
+    {
+        TwRegs<L1, E> tw;
+        unit_tw<L1, E>(tw);
+        constexpr int NL = N0 * N2;
+        const int l = u % NL, t1 = u / NL;
+        cf* line = my + l * Z::RS1;
+#pragma unroll
+        for (int m = 0; m < EPT; m++)
+            v[m] = line[t1 + m * Z::TPT1];
+        if constexpr (Z::TPT1 > 1)
+            __syncthreads();  // the line is read before its exchanges overwrite it
+        run2<L1, E, S, 1, false>(v, t1, rows1, tw, line);
+        __syncthreads();  // every line's exchanges are read
+        const int i0 = l / N2, i2 = l % N2;
+#pragma unroll
+        for (int m = 0; m < EPT; m++)
+            my[((t1 + m * Z::TPT1) * N2 + i2) * Z::RS0 + i0] = v[m];  // line (i1, i2), point i0
+        __syncthreads();
+    }
+    // ---- axis 0 (lines c = i1 N2 + i2), stored straight to HBM
+    {
+        TwRegs<L0, E> tw;
+        unit_tw<L0, E>(tw);
+        constexpr int NC = N1 * N2;
+        const int c = u % NC, t0 = u / NC;
+        cf* line = my + c * Z::RS0;
+#pragma unroll
+        for (int m = 0; m < EPT; m++)
+            v[m] = line[t0 + m * Z::TPT0];
+        if constexpr (Z::TPT0 > 1)
+            __syncthreads();
+        run2<L0, E, S, 1, false>(v, t0, rows0, tw, line);
+        if (live) {
+            cf* dst = out + arr * N + c;
+#pragma unroll
+            for (int m = 0; m < EPT; m++)
+                dst[(t0 + m * Z::TPT0) * NC] = cscale(v[m], scale);
+        }
+    }
+}
+
+template <int L0, int L1, int L2, int S>
+hipError_t launch_nd3(const void* in, void* out, const void* rows, int64_t batch, float scale, hipStream_t stream)
+{
+    using Z = Nd3Shape<L0, L1, L2>;
+    const int64_t grid = (batch + Z::AP - 1) / Z::AP;
+    return launch_kernel((k_nd3<L0, L1, L2, S>), dim3((unsigned)grid), dim3(Z::WG), 0, stream,
+                         static_cast<const cf*>(in), static_cast<cf*>(out), static_cast<const cf*>(rows), batch, scale);
+}
+
+template <int L0, int L1, int L2>
+void add_nd3()
+{
+    if constexpr (nd3_valid<L0, L1, L2>()) {
+        using Z = Nd3Shape<L0, L1, L2>;
+        register_nd3(KernelNd3{{L0, L1, L2}, Z::E, -1, Z::AP, Z::WG, &launch_nd3<L0, L1, L2, -1>, {Z::R0, Z::R1, Z::R2},
+                               Z::LDS});
+        register_nd3(KernelNd3{{L0, L1, L2}, Z::E, +1, Z::AP, Z::WG, &launch_nd3<L0, L1, L2, +1>, {Z::R0, Z::R1, Z::R2},
+                               Z::LDS});
+    }
+}
+
+// every (L0, L1, L2) with each in [2, 10] and L0 + L1 + L2 <= 14
+template <int L0, int L1, int... L2s>
+void add_l2(std::integer_sequence<int, L2s...>)
+{
+    (add_nd3<L0, L1, L2s + 2>(), ...);
+}
+
+template <int L0, int... L1s>
+void add_l1(std::integer_sequence<int, L1s...>)
+{
+    (add_l2<L0, L1s + 2>(std::make_integer_sequence<int, 9>{}), ...);
+}
+
+template <int... L0s>
+void add_l0(std::integer_sequence<int, L0s...>)
+{
+    (add_l1<L0s + 2>(std::make_integer_sequence<int, 9>{}), ...);
+}
+
+struct Nd3Registrar {
+    Nd3Registrar() { add_l0(std::make_integer_sequence<int, 9>{}); }
+};
+Nd3Registrar nd3_registrar;
+
+}  // namespace
+}  // namespace mifft

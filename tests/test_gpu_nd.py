@@ -18,7 +18,9 @@ SHAPES = [(2, 2), (4, 8), (8, 2), (16, 2048), (2048, 16), (64, 64), (2, 4096), (
           # single-pass 2D (the array fits one workgroup's LDS)
           (128, 128), (64, 256), (256, 64), (16, 1024), (1024, 16), (2, 1024), (32, 32), (8, 512), (4, 4),
           # 3D: last two axes in one pass, or not
-          (2, 128, 128), (4, 64, 64), (2, 256, 256), (8, 2, 1024)]
+          (2, 128, 128), (4, 64, 64), (2, 256, 256), (8, 2, 1024),
+          # 3D single pass (every axis >= 4, at most 16384 points)
+          (4, 4, 4), (16, 32, 32), (32, 16, 8), (4, 256, 16), (64, 4, 4), (8, 8, 128)]
 
 
 @pytest.fixture(autouse=True)
@@ -96,6 +98,39 @@ def test_single_pass_choice(shape, single):
     d = api.PlanND(shape, 2, -1).describe()
     assert (d["variant"] == 10) == single, d
     assert d["dims"] == list(shape)
+
+
+@pytest.mark.parametrize("shape,single", [((16, 16, 16), True), ((4, 64, 64), False), ((16, 16, 32), True),
+                                          ((4, 4, 4), True), ((2, 64, 64), False), ((8, 4, 2), False),
+                                          ((4, 128, 128), False), ((4, 1024, 4), False), ((16, 32, 32), False)])
+def test_single_pass_3d_choice(shape, single):
+    """3D arrays of at most 16384 points with every axis at least 4 run the
+    single-pass 3D kernel (variant 13) when an array fits one workgroup
+    (N / EPT <= 1024 threads, EPT the smallest axis up to 16 points): every
+    axis's passes in one kernel.  4 x 64 x 64 (4 points per thread, 4096
+    threads) does not, nor does 16 x 32 x 32 (200 KiB of exchange regions)."""
+    d = api.PlanND(shape, 2, -1).describe()
+    assert (d["variant"] == 13) == single, d
+    assert d["dims"] == list(shape) and d["rank"] == 3
+    if single:
+        assert int(np.prod(d["radices"][:d["npasses"]])) == int(np.prod(shape))
+
+
+def test_single_pass_3d_full_size():
+    """16 x 16 x 32, batch 8192 (2^26 elements): sampled arrays against the
+    oracle, and the round trip over the whole batch."""
+    shape, batch = (16, 16, 32), 8192
+    x = synth.uniform_complex(SEED_ND, (batch,) + shape, key=(97,))
+    xg = to_gpu(x)
+    print(f"[case] nd3 full size {shape} batch={batch}", flush=True)
+    p = api.PlanND(shape, batch, -1)
+    assert p.describe()["variant"] == 13
+    y = p.execute(xg)
+    idx = [0, 1, batch // 2, batch - 1]
+    ys = to_cpu(y[idx])
+    assert per_array_relerr(ys, oracle.fftn(x[idx].astype(np.complex128), 3), 3) <= TOL
+    back = api.PlanND(shape, batch, +1).execute(y)
+    assert per_array_relerr(to_cpu(back), x, 3) <= 2 * TOL
 
 
 def test_single_pass_full_size():
