@@ -286,12 +286,14 @@ def bench_real(api, torch, dev, steps, x_all):
 
 def bench_nd(api, torch, steps, x_all, y_all):
     """2D 2048 x 2048 (batch 16), 128 x 128 and 64 x 64, and 3D 128^3
-    (batch 32) forward transforms, 2^26 complex64 elements each way; one HBM
-    pass per axis, or one in all for arrays that fit one workgroup's LDS."""
+    (batch 32) and 16^3 (batch 16384) forward transforms, 2^26 complex64
+    elements each way; one HBM pass per axis, or one in all for arrays that
+    fit one workgroup's LDS."""
     res = {"workload": "multidimensional C2C forward FFT, 2^26 complex64 elements (512 MiB in + 512 MiB out); "
                        "the last axis through the batched kernels, each other axis one in-place tiled pass"}
     for name, shape, batch in (("2d_2048x2048", (2048, 2048), 16), ("2d_128x128", (128, 128), 4096),
-                               ("2d_64x64", (64, 64), 16384), ("3d_128x128x128", (128, 128, 128), 32)):
+                               ("2d_64x64", (64, 64), 16384), ("3d_128x128x128", (128, 128, 128), 32),
+                               ("3d_16x16x16", (16, 16, 16), 16384)):
         p = api.PlanND(shape, batch, -1)
         xs = x_all.view((batch,) + shape)
         ys = y_all.view((batch,) + shape)
@@ -299,7 +301,8 @@ def bench_nd(api, torch, steps, x_all, y_all):
         elems = batch
         for d in shape:
             elems *= d
-        passes = len(shape) - 1 if p.describe()["variant"] == 10 else len(shape)
+        variant = p.describe()["variant"]
+        passes = 1 if variant == 13 else len(shape) - 1 if variant == 10 else len(shape)
         res[name] = {"us": round(m * 1e3, 2), "passes_over_hbm": passes,
                      "GBps_algorithmic": round(16.0 * elems / (m * 1e-3) / 1e9, 1),
                      "GBps_actual_passes": round(16.0 * passes * elems / (m * 1e-3) / 1e9, 1),
