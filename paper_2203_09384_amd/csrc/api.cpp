@@ -1577,6 +1577,11 @@ int fft_plan_describe(fft_plan p, fft_plan_desc* d)
         d->wg = k->wg;
         d->transforms_per_wg = k->arrays_per_wg;
         d->grid = (p->batch + k->arrays_per_wg - 1) / k->arrays_per_wg;
+        if (k->slots) {
+            const int64_t s = k->slots();
+            if (s > 0 && d->grid > s)
+                d->grid = s;  // workgroups walk the batch
+        }
         int np = 0;
         for (int a = 2; a >= 0; a--) {  // passes in execution order: axis 2, 1, 0
             int r[8];

@@ -20,6 +20,9 @@ struct KernelNd3 {
     LaunchNd3 fn;
     int rows[3];  // twiddle-row entries (float2) of each axis (0 for a one-thread axis)
     int lds_bytes;
+    // persistent form: the workgroups resident on the current device at once
+    // (its grid; 0 if the query fails), nullptr for one workgroup per group
+    int (*slots)();
 };
 
 void register_nd3(const KernelNd3& k);

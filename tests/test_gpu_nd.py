@@ -172,6 +172,42 @@ def test_single_pass_persistent_every_array(shape):
         assert per_array_relerr(y, ref, 2) <= TOL
 
 
+@pytest.mark.parametrize("shape", [(16, 16, 16), (16, 16, 32), (8, 8, 128)],
+                         ids=lambda s: "x".join(map(str, s)))
+def test_single_pass_3d_persistent_every_array(shape):
+    """3D arrays of one workgroup each whose first two axes are one thread
+    per line (N0 = N1 = points per thread) and whose LDS leaves a CU at most
+    16 wavefronts of the one-shot grid run persistent: as many
+    workgroups as fit the device at once walk the batch (describe()'s grid
+    is then below the batch), prefetching the next array during axes 1 and
+    0.  A batch of 2.5x that grid plus 3, so workgroups take two or three
+    arrays through the loop body and the last one after it.  Every array
+    against the oracle, both signs."""
+    big = 1 << 16
+    grid = api.PlanND(shape, big, -1).describe()["grid"]
+    assert grid < big
+    batch = grid * 5 // 2 + 3
+    n = int(np.prod(shape))
+    x = synth.uniform_complex(SEED_ND, (batch,) + shape, key=shape + (41,))
+    xg = to_gpu(x)
+    x64 = x.astype(np.complex128)
+    for sign in (-1, 1):
+        p = api.PlanND(shape, batch, sign)
+        print(f"[case] nd3 persistent {shape} batch={batch} sign={sign} {p.describe()}", flush=True)
+        assert p.describe()["variant"] == 13 and p.describe()["grid"] == grid
+        y = to_cpu(p.execute(xg))
+        ref = oracle.fftn(x64, 3, sign, 1.0 if sign < 0 else 1.0 / n)
+        assert per_array_relerr(y, ref, 3) <= TOL
+
+
+@pytest.mark.parametrize("shape", [(8, 8, 32), (4, 4, 64), (4, 4, 4)], ids=lambda s: "x".join(map(str, s)))
+def test_single_pass_3d_one_shot_grid(shape):
+    """Shapes whose one-shot grid already fills a CU with wavefronts keep a
+    workgroup per group of arrays."""
+    d = api.PlanND(shape, 1 << 16, -1).describe()
+    assert d["variant"] == 13 and d["grid"] == (1 << 16) // d["transforms_per_wg"]
+
+
 @pytest.mark.parametrize("shape,batch", [((1024, 1024), 10), ((2048, 1024), 5)], ids=["1024x1024", "2048x1024"])
 @pytest.mark.parametrize("sign", [-1, 1])
 def test_axis_pass_persistent_every_array(shape, batch, sign):
