@@ -97,7 +97,8 @@ typedef struct {
                            half-length transform, as npasses and radices)  */
     int wg;             /* threads per workgroup                              */
     int transforms_per_wg;
-    int64_t grid;       /* workgroups per execute                             */
+    int64_t grid;       /* workgroups per execute (persistent kernels: those
+                           resident at once, each walking the batch)     */
     int npasses;        /* Stockham passes                                    */
     int radices[8];     /* radix of each pass, first to last                  */
     int lds_bytes;      /* LDS per workgroup                                  */
