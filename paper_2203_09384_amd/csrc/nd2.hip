@@ -18,47 +18,32 @@
 #include "device_fft.hpp"
 #include "launch.hpp"
 #include "nd2.hpp"
+#include "nd_maps.hpp"
 
 #include <utility>
 
 namespace mifft {
 namespace {
 
-constexpr int nd2_e(int L0, int L1)
-{
-    const int m = L0 < L1 ? L0 : L1;
-    return m < 4 ? m : 4;
-}
-
-// Column stride in the transposed layout: the column's Stockham region,
-// rounded up to an odd number of complex values so that lanes reading
-// consecutive columns spread over the 64 banks.
-template <int L0, int E>
-constexpr int col_stride()
-{
-    const int r = Layout2<L0, E>::region();
-    return (r & 1) ? r : r + 1;
-}
-
 template <int L0, int L1>
 struct Nd2Shape {
-    static constexpr int E = nd2_e(L0, L1), EPT = 1 << E;
-    static constexpr int N0 = 1 << L0, N1 = 1 << L1, N = N0 * N1;
-    static constexpr int TPA = N / EPT;                  // threads per array
-    static constexpr int AP = TPA >= 256 ? 1 : 256 / TPA;  // arrays per workgroup
-    static constexpr int WG = AP * TPA;
-    static constexpr int TPT1 = N1 / EPT, TPT0 = N0 / EPT;
-    static constexpr int RS1 = Layout2<L1, E>::region();  // row stride (row phase)
-    static constexpr int RS0 = col_stride<L0, E>();       // column stride (column phase)
-    static constexpr int ASZ = N0 * RS1 > N1 * RS0 ? N0 * RS1 : N1 * RS0;  // LDS per array
-    static constexpr int LDS = AP * ASZ * 8;
+    static constexpr ndm::Nd2Geom G = ndm::nd2_geom(L0, L1);
+    static constexpr int E = G.E, EPT = 1 << E;
+    static constexpr int N0 = G.N0, N1 = G.N1, N = N0 * N1;
+    static constexpr int TPA = G.TPA;  // threads per array
+    static constexpr int AP = G.AP;    // arrays per workgroup
+    static constexpr int WG = G.WG;
+    static constexpr int TPT1 = G.TPT1, TPT0 = G.TPT0;
+    static constexpr int RS1 = G.RS1;  // row stride (row phase): the row's exchange region
+    static constexpr int RS0 = G.RS0;  // column stride (column phase): odd, for the banks
+    static constexpr int ASZ = G.ASZ;  // LDS per array
+    static constexpr int LDS = G.LDS;
 };
 
 template <int L0, int L1>
 constexpr bool nd2_valid()
 {
-    using Z = Nd2Shape<L0, L1>;
-    return L0 >= 1 && L1 >= 1 && L0 + L1 <= 14 && Z::TPA <= 1024 && Z::TPT1 <= 64 && Z::LDS <= 160 * 1024;
+    return ndm::nd2_fits(L0, L1);
 }
 
 // Twiddle-row entries (float2) of the column and row transforms as the
@@ -118,7 +103,7 @@ __global__ __launch_bounds__((Nd2Shape<L0, L1>::WG)) void k_nd2(const cf* __rest
         __syncthreads();  // every row's exchanges are read
 #pragma unroll
         for (int m = 0; m < EPT; m++)
-            my[(t + m * Z::TPT1) * Z::RS0 + r] = v[m];
+            my[ndm::nd2_turn(r, t + m * Z::TPT1, Z::RS0)] = v[m];
         __syncthreads();
     }
     // ---- columns
@@ -201,7 +186,7 @@ __global__ __launch_bounds__((Nd2Shape<L0, L1>::WG)) void k_nd2p(const cf* __res
         __syncthreads();  // every row's exchanges are read
 #pragma unroll
         for (int m = 0; m < EPT; m++)
-            lds[(t + m * Z::TPT1) * Z::RS0 + r] = a[m];
+            lds[ndm::nd2_turn(r, t + m * Z::TPT1, Z::RS0)] = a[m];
         __syncthreads();
 #pragma unroll
         for (int m = 0; m < EPT; m++)

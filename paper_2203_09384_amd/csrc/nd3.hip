@@ -22,43 +22,27 @@
 #include "device_fft.hpp"
 #include "launch.hpp"
 #include "nd3.hpp"
+#include "nd_maps.hpp"
 
 #include <utility>
 
 namespace mifft {
 namespace {
 
-constexpr int nd3_e(int L0, int L1, int L2)
-{
-    int m = L0 < L1 ? L0 : L1;
-    m = m < L2 ? m : L2;
-    return m < 4 ? m : 4;
-}
-
-// Line stride of a turned layout: the Stockham region, rounded up to an
-// odd number of complex values so that lanes reading consecutive lines
-// spread over the banks.
-template <int L, int E>
-constexpr int line_stride()
-{
-    const int r = Layout2<L, E>::region();
-    return (r & 1) ? r : r + 1;
-}
-
 template <int L0, int L1, int L2>
 struct Nd3Shape {
-    static constexpr int E = nd3_e(L0, L1, L2), EPT = 1 << E;
-    static constexpr int N0 = 1 << L0, N1 = 1 << L1, N2 = 1 << L2, N = N0 * N1 * N2;
-    static constexpr int TPA = N / EPT;                    // threads per array
-    static constexpr int AP = TPA >= 256 ? 1 : 256 / TPA;  // arrays per workgroup
-    static constexpr int WG = AP * TPA;
-    static constexpr int TPT0 = N0 / EPT, TPT1 = N1 / EPT, TPT2 = N2 / EPT;
-    static constexpr int RS2 = Layout2<L2, E>::region();  // row stride (axis-2 phase)
-    static constexpr int RS1 = line_stride<L1, E>();      // axis-1 line stride
-    static constexpr int RS0 = line_stride<L0, E>();      // axis-0 line stride
-    static constexpr int A2 = N0 * N1 * RS2, A1 = N0 * N2 * RS1, A0 = N1 * N2 * RS0;
-    static constexpr int ASZ = A2 > A1 ? (A2 > A0 ? A2 : A0) : (A1 > A0 ? A1 : A0);  // LDS per array
-    static constexpr int LDS = AP * ASZ * 8;
+    static constexpr ndm::Nd3Geom G = ndm::nd3_geom(L0, L1, L2);
+    static constexpr int E = G.E, EPT = 1 << E;
+    static constexpr int N0 = G.N0, N1 = G.N1, N2 = G.N2, N = N0 * N1 * N2;
+    static constexpr int TPA = G.TPA;  // threads per array
+    static constexpr int AP = G.AP;    // arrays per workgroup
+    static constexpr int WG = G.WG;
+    static constexpr int TPT0 = G.TPT0, TPT1 = G.TPT1, TPT2 = G.TPT2;
+    static constexpr int RS2 = G.RS2;  // row stride (axis-2 phase)
+    static constexpr int RS1 = G.RS1;  // axis-1 line stride
+    static constexpr int RS0 = G.RS0;  // axis-0 line stride
+    static constexpr int ASZ = G.ASZ;  // LDS per array
+    static constexpr int LDS = G.LDS;
     static constexpr int R0 = TPT0 > 1 ? Layout2<L0, E>::rows_total() : 0;
     static constexpr int R1 = TPT1 > 1 ? Layout2<L1, E>::rows_total() : 0;
     static constexpr int R2 = TPT2 > 1 ? Layout2<L2, E>::rows_total() : 0;
@@ -67,12 +51,7 @@ struct Nd3Shape {
 template <int L0, int L1, int L2>
 constexpr bool nd3_valid()
 {
-    if constexpr (L0 < 2 || L1 < 2 || L2 < 2 || L0 + L1 + L2 > 14) {
-        return false;
-    } else {
-        using Z = Nd3Shape<L0, L1, L2>;
-        return Z::TPA <= 1024 && Z::TPT2 <= 64 && Z::LDS <= 160 * 1024;
-    }
+    return ndm::nd3_fits(L0, L1, L2);
 }
 
 template <int L, int E>
@@ -115,7 +94,7 @@ __global__ __launch_bounds__((Nd3Shape<L0, L1, L2>::WG)) void k_nd3(const cf* __
         const int i0 = r / N1, i1 = r % N1;
 #pragma unroll
         for (int m = 0; m < EPT; m++)
-            my[(i0 * N2 + t + m * Z::TPT2) * Z::RS1 + i1] = v[m];  // line (i0, i2), point i1
+            my[ndm::nd3_turn21(i0, i1, t + m * Z::TPT2, N2, Z::RS1)] = v[m];  // line (i0, i2), point i1
         __syncthreads();
     }
     // ---- axis 1 (lines l = i0 N2 + i2)
@@ -135,7 +114,7 @@ __global__ __launch_bounds__((Nd3Shape<L0, L1, L2>::WG)) void k_nd3(const cf* __
         const int i0 = l / N2, i2 = l % N2;
 #pragma unroll
         for (int m = 0; m < EPT; m++)
-            my[((t1 + m * Z::TPT1) * N2 + i2) * Z::RS0 + i0] = v[m];  // line (i1, i2), point i0
+            my[ndm::nd3_turn10(i0, t1 + m * Z::TPT1, i2, N2, Z::RS0)] = v[m];  // line (i1, i2), point i0
         __syncthreads();
     }
     // ---- axis 0 (lines c = i1 N2 + i2), stored straight to HBM
@@ -226,7 +205,7 @@ __global__ __launch_bounds__((Nd3Shape<L0, L1, L2>::WG)) void k_nd3p(const cf* _
         __syncthreads();  // every row's exchanges are read
 #pragma unroll
         for (int m = 0; m < EPT; m++)
-            lds[(i0r * N2 + t + m * Z::TPT2) * Z::RS1 + i1r] = x[m];
+            lds[ndm::nd3_turn21(i0r, i1r, t + m * Z::TPT2, N2, Z::RS1)] = x[m];
         __syncthreads();
 #pragma unroll
         for (int m = 0; m < EPT; m++)
@@ -238,7 +217,7 @@ __global__ __launch_bounds__((Nd3Shape<L0, L1, L2>::WG)) void k_nd3p(const cf* _
         __syncthreads();  // every axis-1 line is read
 #pragma unroll
         for (int m = 0; m < EPT; m++)
-            lds[(m * N2 + i2l) * Z::RS0 + i0l] = v[m];
+            lds[ndm::nd3_turn10(i0l, m, i2l, N2, Z::RS0)] = v[m];
         __syncthreads();
 #pragma unroll
         for (int m = 0; m < EPT; m++)

@@ -4,6 +4,7 @@
 #include <stdint.h>
 
 #include "index_maps.hpp"
+#include "nd_maps.hpp"
 
 using namespace mifft::idx;
 
@@ -79,5 +80,49 @@ void im_fourstep_cols(int64_t ntiles, int L1, int L2, int T, int64_t* out_in, in
 }
 
 int im_real_partner(int M, int k) { return real_partner(M, k); }
+
+// single-pass 2D: out = fits, E, TPA, AP, WG, TPT0, TPT1, RS1, RS0, ASZ, LDS
+void im_nd2_geom(int L0, int L1, int* out)
+{
+    const mifft::ndm::Nd2Geom g = mifft::ndm::nd2_geom(L0, L1);
+    const int v[] = {mifft::ndm::nd2_fits(L0, L1) ? 1 : 0, g.E, g.TPA, g.AP, g.WG, g.TPT0, g.TPT1, g.RS1, g.RS0,
+                     g.ASZ, g.LDS};
+    for (int i = 0; i < 11; i++)
+        out[i] = v[i];
+}
+
+// out[r N1 + k1] = the turn's LDS index of point k1 of row r
+void im_nd2_turns(int L0, int L1, int* out)
+{
+    const mifft::ndm::Nd2Geom g = mifft::ndm::nd2_geom(L0, L1);
+    for (int r = 0; r < g.N0; r++)
+        for (int k = 0; k < g.N1; k++)
+            out[r * g.N1 + k] = mifft::ndm::nd2_turn(r, k, g.RS0);
+}
+
+// single-pass 3D: out = fits, E, TPA, AP, WG, TPT0, TPT1, TPT2, RS2, RS1,
+// RS0, A2, A1, A0, ASZ, LDS
+void im_nd3_geom(int L0, int L1, int L2, int* out)
+{
+    const mifft::ndm::Nd3Geom g = mifft::ndm::nd3_geom(L0, L1, L2);
+    const int v[] = {mifft::ndm::nd3_fits(L0, L1, L2) ? 1 : 0, g.E, g.TPA, g.AP, g.WG, g.TPT0, g.TPT1, g.TPT2, g.RS2,
+                     g.RS1, g.RS0, g.A2, g.A1, g.A0, g.ASZ, g.LDS};
+    for (int i = 0; i < 16; i++)
+        out[i] = v[i];
+}
+
+// t21[(i0 N1 + i1) N2 + k2]: the first turn's LDS index of point k2 of row
+// (i0, i1); t10[(i0 N1 + k1) N2 + k2]: the second turn's of point k1 of the
+// axis-1 line (i0, k2)
+void im_nd3_turns(int L0, int L1, int L2, int* t21, int* t10)
+{
+    const mifft::ndm::Nd3Geom g = mifft::ndm::nd3_geom(L0, L1, L2);
+    for (int i0 = 0; i0 < g.N0; i0++)
+        for (int j = 0; j < g.N1; j++)
+            for (int k2 = 0; k2 < g.N2; k2++) {
+                t21[(i0 * g.N1 + j) * g.N2 + k2] = mifft::ndm::nd3_turn21(i0, j, k2, g.N2, g.RS1);
+                t10[(i0 * g.N1 + j) * g.N2 + k2] = mifft::ndm::nd3_turn10(i0, j, k2, g.N2, g.RS0);
+            }
+}
 
 }  // extern "C"

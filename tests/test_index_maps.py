@@ -17,7 +17,12 @@ header is built for the host (g++) and enumerated:
 * the XCD tile grouping is a bijection that puts tiles sharing 128-byte
   lines on one XCD; axis and four-step maps touch every element exactly
   once, and the four-step maps reproduce the DFT;
-* the real-input partner map pairs bins as the even/odd split needs.
+* the real-input partner map pairs bins as the even/odd split needs;
+* the single-pass 2D / 3D kernels' geometry and turns through LDS
+  (paper_2203_09384_amd/csrc/nd_maps.hpp): every turn injective and in
+  bounds, every line's exchange region inside its stride, and the dataflow
+  rows -> turn -> lines (-> turn -> lines) reproducing the 2D / 3D DFT for
+  every shape the kernels are built for.
 """
 import ctypes
 import os
@@ -221,3 +226,94 @@ def test_real_partner_map_gives_the_split(im, M):
     k = np.arange(M)
     X = 0.5 * (Z + Zp) + np.exp(-2j * np.pi * k / (2 * M)) * (Z - Zp) / 2j
     assert np.allclose(X, np.fft.rfft(x)[:M], rtol=0, atol=1e-10 * np.abs(x).sum())
+
+
+# ---------------------------------------------------------------- single-pass 2D / 3D
+def nd2_shapes():
+    return [(a, b) for a in range(1, 14) for b in range(1, 14) if a + b <= 14]
+
+
+def nd3_shapes():
+    return [(a, b, c) for a in range(2, 11) for b in range(2, 11) for c in range(2, 11) if a + b + c <= 14]
+
+
+def test_single_pass_shape_counts(im):
+    """The shapes the kernels exist for (every axis from 2 (2D) or 4 (3D)
+    points, at most 16384 points, 1024 threads and 160 KiB of LDS; rows
+    inside one wavefront)."""
+    g2 = np.zeros(11, np.int32)
+    g3 = np.zeros(16, np.int32)
+    n2 = sum(im.im_nd2_geom(a, b, ip(g2)) or int(g2[0]) for a, b in nd2_shapes())
+    n3 = sum(im.im_nd3_geom(a, b, c, ip(g3)) or int(g3[0]) for a, b, c in nd3_shapes())
+    assert n3 == 100 and n2 > 50
+    assert not im.im_nd3_geom(4, 5, 5, ip(g3)) and g3[0] == 0  # 16 x 32 x 32: 196 KiB of LDS
+
+
+@pytest.mark.parametrize("L0,L1", nd2_shapes())
+def test_single_pass_2d_maps_reproduce_the_dft(im, L0, L1):
+    """Rows into their regions, the turn, columns read at stride RS0 and
+    stored X[k0][c]: the dataflow of the single-pass 2D kernel with each
+    line's transform taken as a DFT (the Stockham passes are checked
+    above), against the 2D DFT."""
+    g = np.zeros(11, np.int32)
+    im.im_nd2_geom(L0, L1, ip(g))
+    fits, E, TPA, AP, WG, TPT0, TPT1, RS1, RS0, ASZ, LDS = (int(v) for v in g)
+    if not fits:
+        return
+    N0, N1 = 1 << L0, 1 << L1
+    assert TPA == N0 * N1 >> E and TPT0 == N0 >> E and TPT1 == N1 >> E and TPT1 <= 64
+    assert WG == AP * TPA and LDS == AP * ASZ * 8 <= 160 * 1024
+    # rows: region r at r RS1 holds the row's exchanges; columns: line c at c RS0
+    assert RS1 >= im.im_region(L1, E) and N0 * RS1 <= ASZ
+    assert RS0 % 2 == 1 and RS0 >= im.im_region(L0, E) and (N1 - 1) * RS0 + im.im_region(L0, E) <= ASZ
+    turn = np.zeros(N0 * N1, np.int32)
+    im.im_nd2_turns(L0, L1, ip(turn))
+    assert len(np.unique(turn)) == N0 * N1 and turn.min() >= 0 and turn.max() < ASZ
+    x = np.random.default_rng(L0 * 16 + L1).standard_normal((N0, N1, 2)) @ np.array([1.0, 1j])
+    rows = np.fft.fft(x, axis=1)
+    lds = np.full(ASZ, np.nan + 0j)
+    lds[turn] = rows.reshape(-1)
+    cols = lds[np.arange(N1)[:, None] * RS0 + np.arange(N0)[None, :]]  # line c, point n
+    assert not np.isnan(cols).any()
+    out = np.fft.fft(cols, axis=1).T  # out[k0][c]
+    ref = np.fft.fft2(x)
+    assert np.linalg.norm(out - ref) <= 1e-12 * np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("L0,L1,L2", nd3_shapes())
+def test_single_pass_3d_maps_reproduce_the_dft(im, L0, L1, L2):
+    """Axis-2 rows, the turn to the axis-1 lines (i0, k2) at stride RS1, the
+    turn to the axis-0 lines (k1, k2) at stride RS0, stored X[k0][k1][k2]:
+    the dataflow of the single-pass 3D kernel with each line's transform
+    taken as a DFT, against the 3D DFT."""
+    g = np.zeros(16, np.int32)
+    im.im_nd3_geom(L0, L1, L2, ip(g))
+    fits, E, TPA, AP, WG, TPT0, TPT1, TPT2, RS2, RS1, RS0, A2, A1, A0, ASZ, LDS = (int(v) for v in g)
+    if not fits:
+        return
+    N0, N1, N2 = 1 << L0, 1 << L1, 1 << L2
+    assert E == min(L0, L1, L2, 4) and TPA == (N0 * N1 * N2) >> E and TPT2 <= 64
+    assert (TPT0, TPT1, TPT2) == (N0 >> E, N1 >> E, N2 >> E)
+    assert ASZ == max(A2, A1, A0) and LDS == AP * ASZ * 8 <= 160 * 1024 and WG == AP * TPA
+    assert RS2 >= im.im_region(L2, E) and A2 == N0 * N1 * RS2
+    for L, RS, lines, A in ((L1, RS1, N0 * N2, A1), (L0, RS0, N1 * N2, A0)):
+        assert RS % 2 == 1 and RS >= im.im_region(L, E) and (lines - 1) * RS + im.im_region(L, E) <= A
+    t21 = np.zeros(N0 * N1 * N2, np.int32)
+    t10 = np.zeros(N0 * N1 * N2, np.int32)
+    im.im_nd3_turns(L0, L1, L2, ip(t21), ip(t10))
+    for t in (t21, t10):
+        assert len(np.unique(t)) == t.size and t.min() >= 0 and t.max() < ASZ
+    x = np.random.default_rng(L0 * 256 + L1 * 16 + L2).standard_normal((N0, N1, N2, 2)) @ np.array([1.0, 1j])
+    rows = np.fft.fft(x, axis=2)  # rows[i0, i1, k2]
+    lds = np.full(ASZ, np.nan + 0j)
+    lds[t21] = rows.reshape(-1)
+    l1 = lds[np.arange(N0 * N2)[:, None] * RS1 + np.arange(N1)[None, :]]  # line (i0, k2), point i1
+    assert not np.isnan(l1).any()
+    y1 = np.fft.fft(l1, axis=1).reshape(N0, N2, N1).transpose(0, 2, 1)  # y1[i0, k1, k2]
+    lds = np.full(ASZ, np.nan + 0j)
+    lds[t10] = y1.reshape(-1)
+    l0 = lds[np.arange(N1 * N2)[:, None] * RS0 + np.arange(N0)[None, :]]  # line (k1, k2), point i0
+    assert not np.isnan(l0).any()
+    out = np.fft.fft(l0, axis=1).T.reshape(N0, N1, N2)  # stored at k0 N1 N2 + c
+    ref = np.fft.fftn(x)
+    assert np.linalg.norm(out - ref) <= 1e-12 * np.linalg.norm(ref)
