@@ -379,7 +379,7 @@ struct mifft_plan_s {
     const KernelNd2* nd2_same = nullptr;
     const KernelNd2* nd2_opp = nullptr;
     void* nd2_rows[2] = {nullptr, nullptr};  // column, row transforms
-    int64_t nd2_grid_cap = 0;                // persistent single-pass 2D kernel: the device's CUs
+    int64_t nd2_grid_cap = 0;                // persistent single-pass 2D kernel: its resident workgroups
     const KernelNd3* nd3_same = nullptr;     // single-pass 3D kernel (this sign / the opposite one)
     const KernelNd3* nd3_opp = nullptr;
     void* nd3_rows = nullptr;                // its twiddle rows, axes 0, 1, 2 back to back
@@ -948,11 +948,8 @@ fft_plan create_nd2(const int64_t* dims, int64_t batch, int sign)
     p->dims[1] = dims[1];
     p->nd2_same = k;
     p->nd2_opp = find_nd2(L0, L1, -sign);
-    if (k->persistent) {
-        int cus = 0;
-        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess)
-            p->nd2_grid_cap = cus;
-    }
+    if (k->slots)
+        p->nd2_grid_cap = k->slots();
     if (make_twiddles(p) != FFT_OK) {
         free_plan(p);
         return nullptr;

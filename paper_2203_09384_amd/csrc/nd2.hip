@@ -60,8 +60,13 @@ struct Nd2Rows {
 
 // Arrays whose exchanges take more than half of a CU's 160 KiB of LDS run
 // one workgroup per CU, which then has nothing to overlap its loads and
-// stores with.  Those run persistent (k_nd2p) when the twiddle rows fit in
-// the LDS left over.
+// stores with; arrays of one-thread rows (N1 = EPT) load with lanes a whole
+// row apart, few requests per cache line, and gain from the overlap too when
+// the one-shot grid leaves a CU at most 16 wavefronts.  Those run persistent
+// (k_nd2p) when the twiddle rows fit in the LDS left over: as many
+// workgroups as are resident at once walk the batch.  (Shapes with longer
+// rows at 12-16 wavefronts per CU measured slower persistent: 128 x 64
+// 226 -> 256 us, 16 x 256 187 -> 201.)
 template <int L0, int L1>
 constexpr bool nd2_persistent()
 {
@@ -69,8 +74,8 @@ constexpr bool nd2_persistent()
     using RW = Nd2Rows<L0, L1>;
     // 1024-point rows excluded: at 1024 threads their registers spill
     // (16 x 1024 measured 280 -> 348 us)
-    return Z::AP == 1 && 2 * Z::LDS > 160 * 1024 && Z::LDS + (RW::R0 + RW::R1) * 8 <= 160 * 1024 &&
-           Z::EPT % Sched<L0, Z::E>::NP == 0 && L1 < 10;
+    return Z::AP == 1 && (2 * Z::LDS > 160 * 1024 || (Z::TPT1 == 1 && (160 * 1024 / Z::LDS) * (Z::WG / 64) <= 16)) &&
+           Z::LDS + (RW::R0 + RW::R1) * 8 <= 160 * 1024 && Z::EPT % Sched<L0, Z::E>::NP == 0 && L1 < 10;
 }
 
 template <int L0, int L1, int S>
@@ -225,19 +230,31 @@ __global__ __launch_bounds__((Nd2Shape<L0, L1>::WG)) void k_nd2p(const cf* __res
     store();
 }
 
-int nd2_cus()
+template <int L0, int L1, int S>
+int nd2_slots()
 {
     static int cached[64] = {0};
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64)
         return 0;
     if (cached[dev] == 0) {
-        int cus = 0;
-        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        int cus = 0, per = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_nd2p<L0, L1, S>, Nd2Shape<L0, L1>::WG, 0) !=
+                hipSuccess)
             return 0;
-        cached[dev] = cus;
+        cached[dev] = cus * per;
     }
     return cached[dev];
+}
+
+template <int L0, int L1, int S>
+constexpr auto nd2_slots_fn()
+{
+    if constexpr (nd2_persistent<L0, L1>())
+        return &nd2_slots<L0, L1, S>;
+    else
+        return static_cast<int (*)()>(nullptr);
 }
 
 template <int L0, int L1, int S>
@@ -246,11 +263,13 @@ hipError_t launch_nd2(const void* in, void* out, const void* rows0, const void* 
 {
     using Z = Nd2Shape<L0, L1>;
     if constexpr (nd2_persistent<L0, L1>()) {
-        const int cus = nd2_cus();
-        const int64_t grid = cus > 0 && batch > cus ? cus : batch;  // one workgroup fills a CU's LDS
-        return launch_kernel((k_nd2p<L0, L1, S>), dim3((unsigned)grid), dim3(Z::WG), 0, stream,
-                             static_cast<const cf*>(in), static_cast<cf*>(out), static_cast<const cf*>(rows0),
-                             static_cast<const cf*>(rows1), batch, scale);
+        const int slots = nd2_slots<L0, L1, S>();
+        if (slots > 0) {
+            const int64_t grid = batch > slots ? slots : batch;
+            return launch_kernel((k_nd2p<L0, L1, S>), dim3((unsigned)grid), dim3(Z::WG), 0, stream,
+                                 static_cast<const cf*>(in), static_cast<cf*>(out), static_cast<const cf*>(rows0),
+                                 static_cast<const cf*>(rows1), batch, scale);
+        }
     }
     const int64_t grid = (batch + Z::AP - 1) / Z::AP;
     return launch_kernel((k_nd2<L0, L1, S>), dim3((unsigned)grid), dim3(Z::WG), 0, stream,
@@ -265,9 +284,10 @@ void add_nd2()
         using Z = Nd2Shape<L0, L1>;
         const int r0 = Z::TPT0 > 1 ? Layout2<L0, Z::E>::rows_total() : 0;
         const int r1 = Z::TPT1 > 1 ? Layout2<L1, Z::E>::rows_total() : 0;
-        constexpr bool P = nd2_persistent<L0, L1>();
-        register_nd2(KernelNd2{L0, L1, Z::E, -1, Z::AP, Z::WG, &launch_nd2<L0, L1, -1>, r0, r1, Z::LDS, P});
-        register_nd2(KernelNd2{L0, L1, Z::E, +1, Z::AP, Z::WG, &launch_nd2<L0, L1, +1>, r0, r1, Z::LDS, P});
+        register_nd2(KernelNd2{L0, L1, Z::E, -1, Z::AP, Z::WG, &launch_nd2<L0, L1, -1>, r0, r1, Z::LDS,
+                               nd2_slots_fn<L0, L1, -1>()});
+        register_nd2(KernelNd2{L0, L1, Z::E, +1, Z::AP, Z::WG, &launch_nd2<L0, L1, +1>, r0, r1, Z::LDS,
+                               nd2_slots_fn<L0, L1, +1>()});
     }
 }
 

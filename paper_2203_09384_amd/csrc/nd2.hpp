@@ -20,7 +20,9 @@ struct KernelNd2 {
     LaunchNd2 fn;
     int rows0, rows1;  // twiddle-row entries (float2)
     int lds_bytes;
-    bool persistent;   // one workgroup per CU walking the batch (grid: min(batch, CUs))
+    // persistent form: the workgroups resident on the current device at once
+    // (its grid; 0 if the query fails), nullptr for one workgroup per group
+    int (*slots)();
 };
 
 void register_nd2(const KernelNd2& k);

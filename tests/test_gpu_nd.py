@@ -148,10 +148,13 @@ def test_single_pass_full_size():
     assert per_array_relerr(to_cpu(back), x, 2) <= 2 * TOL
 
 
-@pytest.mark.parametrize("shape", [(128, 128), (64, 128), (256, 32), (32, 256)], ids=lambda s: "x".join(map(str, s)))
+@pytest.mark.parametrize("shape", [(128, 128), (64, 128), (256, 32), (32, 256), (256, 16)],
+                         ids=lambda s: "x".join(map(str, s)))
 def test_single_pass_persistent_every_array(shape):
-    """Arrays that fill more than half of a CU's LDS run one persistent
-    workgroup per CU (describe()'s grid is then below the batch): a batch of
+    """Arrays that fill more than half of a CU's LDS, or of one-thread rows
+    whose LDS leaves the one-shot grid at most 16 wavefronts per CU, run
+    persistent, as many workgroups as are resident at once walking the
+    batch (describe()'s grid is then below the batch): a batch of
     2.5x that grid plus 3, so workgroups take two or three arrays through
     the prefetching loop body and the last one after it.  Every array
     against the oracle, both signs."""
