@@ -16,7 +16,8 @@
 // (the tile's transform index is the fastest lane index); short ones are
 // staged through LDS so that their exchanges stay inside one wavefront.
 // w_N^j is built from a two-level FP32 table (w_N^{1024 a} and w_N^{b},
-// both from FP64 sincospi).
+// both from FP64 sincospi), copied into LDS where it fits at no occupancy
+// cost.
 #include "device_fft.hpp"
 #include "launch.hpp"
 #include "fourstep.hpp"
@@ -35,6 +36,15 @@ __device__ __forceinline__ cf big_twiddle(const cf* __restrict__ lo, const cf* _
         w.y = -w.y;
     return w;
 }
+
+// Both levels of the w_N table in LDS (lo 1024 entries, hi N / 1024; 10 KiB
+// at N = 2^18) where the column tile leaves room at no occupancy cost:
+// 512-point columns (N = 2^17, 2^18), two workgroups per CU either way.
+// MI355X, 2^26 elements: 2^17 519 -> 487 us, 2^18 525 -> 493.  At 256-point
+// columns (2^15, 2^16) it costs a workgroup per CU (4 -> 3) and was 1 %
+// slower; at 2^19, 2^20 the hi level (up to 8 KiB) does not fit beside two
+// 1024-point tiles.  The lookups stay gathers only there.
+constexpr bool tw_in_lds(int L) { return L == 17 || L == 18; }
 
 // Columns per pass-1 tile: 16 (whole 128-byte lines), or 8 for 1024-point
 // columns so that two workgroups fit one CU's LDS (MI355X, 2^26 elements:
@@ -61,7 +71,12 @@ __global__ __launch_bounds__(col_tile(L1)*((1 << L1) >> inner_e(L1))) void k_fou
     constexpr int EPT = 1 << E, TPT = N1 / EPT, WG = T * TPT, ST = stage_stride<L1, E>();
     constexpr bool DIRECT = col_direct(L1);
     static_assert(T == 16 || DIRECT, "8-column tiles load directly");
+    // both table levels in LDS (lo: 1024 entries, hi: N / 1024, back to back
+    // from tlo), so the per-point lookups are LDS reads, not gathers
+    constexpr bool TWL = tw_in_lds(L1 + L2);
+    constexpr int NTW = TWL ? 1024 + ((1 << (L1 + L2)) >> 10) : 1;
     __shared__ cf lds[T * ST];
+    __shared__ cf twl[NTW];
     const int tid = threadIdx.x;
     int64_t tile = blockIdx.x;
     if constexpr (T < 16) {
@@ -94,6 +109,11 @@ __global__ __launch_bounds__(col_tile(L1)*((1 << L1) >> inner_e(L1))) void k_fou
         for (int m = 0; m < EPT; m++)
             v[m] = my[t + m * TPT];
     }
+    if constexpr (TWL) {
+        for (int i = tid; i < NTW; i += WG)
+            twl[i] = tlo[i];
+        __syncthreads();
+    }
     TwRegs<L1, E> tws;
     unit_rows<L1, E>(tws);
     constexpr bool WAVE = DIRECT ? TPT * T <= 64 : TPT <= 64;
@@ -102,7 +122,7 @@ __global__ __launch_bounds__(col_tile(L1)*((1 << L1) >> inner_e(L1))) void k_fou
 #pragma unroll
     for (int m = 0; m < EPT; m++) {
         const unsigned k1 = t + m * TPT;
-        v[m] = cmul(v[m], big_twiddle<S>(tlo, thi, n2 * k1));
+        v[m] = cmul(v[m], TWL ? big_twiddle<S>(twl, twl + 1024, n2 * k1) : big_twiddle<S>(tlo, thi, n2 * k1));
     }
     if constexpr (DIRECT)
         __syncthreads();  // every transform's last exchange is read
@@ -168,7 +188,8 @@ void add_len()
     const FourStep fs{L, L1, L2, inner_e(L1), inner_e(L2), Layout2<L1, inner_e(L1)>::rows_total(),
                       Layout2<L2, inner_e(L2)>::rows_total(), &launch_fourstep<L1, L2, -1>,
                       &launch_fourstep<L1, L2, +1>,
-                      (int)(col_tile(L1) * stage_stride<L1, inner_e(L1)>() * sizeof(cf)),
+                      (int)((col_tile(L1) * stage_stride<L1, inner_e(L1)>() + (tw_in_lds(L) ? 1024 + (1 << (L - 10)) : 0)) *
+                            sizeof(cf)),
                       (int)(TILE * stage_stride<L2, inner_e(L2)>() * sizeof(cf)), col_tile(L1)};
     register_fourstep(fs);
 }
