@@ -16,8 +16,7 @@
 // (the tile's transform index is the fastest lane index); short ones are
 // staged through LDS so that their exchanges stay inside one wavefront.
 // w_N^j is built from a two-level FP32 table (w_N^{1024 a} and w_N^{b},
-// both from FP64 sincospi), copied into LDS where it fits at no occupancy
-// cost.
+// both from FP64 sincospi); the column pass reads it as three levels in LDS.
 #include "device_fft.hpp"
 #include "launch.hpp"
 #include "fourstep.hpp"
@@ -37,14 +36,16 @@ __device__ __forceinline__ cf big_twiddle(const cf* __restrict__ lo, const cf* _
     return w;
 }
 
-// Both levels of the w_N table in LDS (lo 1024 entries, hi N / 1024; 10 KiB
-// at N = 2^18) where the column tile leaves room at no occupancy cost:
-// 512-point columns (N = 2^17, 2^18), two workgroups per CU either way.
-// MI355X, 2^26 elements: 2^17 519 -> 487 us, 2^18 525 -> 493.  At 256-point
-// columns (2^15, 2^16) it costs a workgroup per CU (4 -> 3) and was 1 %
-// slower; at 2^19, 2^20 the hi level (up to 8 KiB) does not fit beside two
-// 1024-point tiles.  The lookups stay gathers only there.
-constexpr bool tw_in_lds(int L) { return L == 17 || L == 18; }
+// The w_N^{n2 k1} lookups are gathers (every lane its own entry); from the
+// cached two-level table they cost about a tenth of the four-step's time.
+// Each workgroup copies a three-level table into LDS instead (w_N^{1024 a},
+// w_N^{32 b}, w_N^{c} for j = 1024 a + 32 b + c: 64 + N / 1024 entries, at
+// most 8.5 KiB, taken from the two-level table), at one more complex product
+// per point and without losing a workgroup per CU.  MI355X, 2^26 elements:
+// 2^15 468 -> 428 us, 2^16 483 -> 440, 2^17 519 -> 478, 2^18 525 -> 485,
+// 2^19 552 -> 508, 2^20 567 -> 542.  (The two levels whole in LDS, 10 KiB at
+// 2^18, cost a workgroup per CU at 256-point columns.)
+constexpr bool tw3_in_lds(int L) { return L >= 15; }
 
 // Columns per pass-1 tile: 16 (whole 128-byte lines), or 8 for 1024-point
 // columns so that two workgroups fit one CU's LDS (MI355X, 2^26 elements:
@@ -71,10 +72,11 @@ __global__ __launch_bounds__(col_tile(L1)*((1 << L1) >> inner_e(L1))) void k_fou
     constexpr int EPT = 1 << E, TPT = N1 / EPT, WG = T * TPT, ST = stage_stride<L1, E>();
     constexpr bool DIRECT = col_direct(L1);
     static_assert(T == 16 || DIRECT, "8-column tiles load directly");
-    // both table levels in LDS (lo: 1024 entries, hi: N / 1024, back to back
-    // from tlo), so the per-point lookups are LDS reads, not gathers
-    constexpr bool TWL = tw_in_lds(L1 + L2);
-    constexpr int NTW = TWL ? 1024 + ((1 << (L1 + L2)) >> 10) : 1;
+    // the three-level table in LDS (tw3_in_lds): twl[c], twl[32 + b],
+    // twl[64 + a]
+    constexpr bool TW3 = tw3_in_lds(L1 + L2);
+    constexpr int NHI = (1 << (L1 + L2)) >> 10;
+    constexpr int NTW = TW3 ? 64 + NHI : 1;
     __shared__ cf lds[T * ST];
     __shared__ cf twl[NTW];
     const int tid = threadIdx.x;
@@ -109,9 +111,10 @@ __global__ __launch_bounds__(col_tile(L1)*((1 << L1) >> inner_e(L1))) void k_fou
         for (int m = 0; m < EPT; m++)
             v[m] = my[t + m * TPT];
     }
-    if constexpr (TWL) {
+    if constexpr (TW3) {
+        // twl: w_N^c (c < 32), w_N^{32 b} (b < 32), then w_N^{1024 a}
         for (int i = tid; i < NTW; i += WG)
-            twl[i] = tlo[i];
+            twl[i] = i < 32 ? tlo[i] : i < 64 ? tlo[32 * (i - 32)] : thi[i - 64];
         __syncthreads();
     }
     TwRegs<L1, E> tws;
@@ -122,7 +125,16 @@ __global__ __launch_bounds__(col_tile(L1)*((1 << L1) >> inner_e(L1))) void k_fou
 #pragma unroll
     for (int m = 0; m < EPT; m++) {
         const unsigned k1 = t + m * TPT;
-        v[m] = cmul(v[m], TWL ? big_twiddle<S>(twl, twl + 1024, n2 * k1) : big_twiddle<S>(tlo, thi, n2 * k1));
+        const unsigned j = n2 * k1;
+        cf w;
+        if constexpr (TW3) {
+            w = cmul(cmul(twl[64 + (j >> 10)], twl[32 + ((j >> 5) & 31u)]), twl[j & 31u]);
+            if constexpr (S > 0)
+                w.y = -w.y;
+        } else {
+            w = big_twiddle<S>(tlo, thi, j);
+        }
+        v[m] = cmul(v[m], w);
     }
     if constexpr (DIRECT)
         __syncthreads();  // every transform's last exchange is read
@@ -188,7 +200,8 @@ void add_len()
     const FourStep fs{L, L1, L2, inner_e(L1), inner_e(L2), Layout2<L1, inner_e(L1)>::rows_total(),
                       Layout2<L2, inner_e(L2)>::rows_total(), &launch_fourstep<L1, L2, -1>,
                       &launch_fourstep<L1, L2, +1>,
-                      (int)((col_tile(L1) * stage_stride<L1, inner_e(L1)>() + (tw_in_lds(L) ? 1024 + (1 << (L - 10)) : 0)) *
+                      (int)((col_tile(L1) * stage_stride<L1, inner_e(L1)>() +
+                             (tw3_in_lds(L) ? 64 + (1 << (L - 10)) : 0)) *
                             sizeof(cf)),
                       (int)(TILE * stage_stride<L2, inner_e(L2)>() * sizeof(cf)), col_tile(L1)};
     register_fourstep(fs);
