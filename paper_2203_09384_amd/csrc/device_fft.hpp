@@ -336,6 +336,18 @@ __device__ __forceinline__ void load_row(cf (&w)[1 << E], const cf* __restrict__
     constexpr int EPT = SC::EPT, NS = 1 << SC::log2ns(P), RS = EPT + PAD;
     static_assert(SC::log2r(P) == E, "twiddled passes have radix EPT");
     static_assert(PAD % 2 == 0, "rows stay 16-byte aligned");
+    if constexpr (idx::rows_entry_major(L)) {
+        // entry r of row k at rows_offset(P) + r NS + k: consecutive lanes,
+        // consecutive addresses
+        static_assert(PAD == 0, "entry-major rows are read from the table");
+        const cf* base = rows + Layout2<L, E>::rows_offset(P) + (t & (NS - 1));
+#pragma unroll
+        for (int r = 0; r < EPT; r++) {
+            const cf q = base[r * NS];
+            w[r] = cf{q.x, S > 0 ? -q.y : q.y};
+        }
+        return;
+    }
     const float4* r4 =
         reinterpret_cast<const float4*>(rows + Layout2<L, E>::rows_offset(P) / EPT * RS + (t & (NS - 1)) * RS);
 #pragma unroll
@@ -351,6 +363,7 @@ __device__ __forceinline__ void load_row(cf (&w)[1 << E], const cf* __restrict__
 template <int L, int E, int PAD>
 __device__ __forceinline__ void copy_rows_padded(cf* dst, const cf* __restrict__ src, int tid, int nthreads)
 {
+    static_assert(!idx::rows_entry_major(L), "row-major tables only");
     constexpr int EPT = 1 << E, TOT = Layout2<L, E>::rows_total();
     for (int i = tid; i < TOT; i += nthreads)
         dst[i / EPT * (EPT + PAD) + i % EPT] = src[i];
@@ -668,6 +681,7 @@ __host__ __device__ constexpr int padded_rows_prefix(int K)
 template <int L, int E, int PAD, int K>
 __device__ __forceinline__ void copy_rows_prefix_padded(cf* dst, const cf* __restrict__ src, int tid, int nthreads)
 {
+    static_assert(!idx::rows_entry_major(L), "row-major tables only");
     constexpr int EPT = 1 << E, TOT = Layout2<L, E>::rows_offset(K);
     for (int i = tid; i < TOT; i += nthreads)
         dst[i / EPT * (EPT + PAD) + i % EPT] = src[i];

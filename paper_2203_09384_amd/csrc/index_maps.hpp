@@ -73,6 +73,20 @@ MIFFT_HD constexpr RowEntry twiddle_row_entry(int L, int E, int i)
     return RowEntry{-1, 0, 0, 0, -1};
 }
 
+// Where entry r of row k of pass P is stored.  Row-major (rows_offset(P) +
+// k EPT + r) for transforms of up to 4096 points, whose kernels keep the
+// rows or share them across transforms; entry-major within each pass
+// (rows_offset(P) + r NS + k) from 8192 points up, whose kernels read every
+// pass's rows once per transform: there a lane's row-major row puts lanes a
+// whole row (EPT values) apart, entry-major puts consecutive k, i.e.
+// consecutive lanes, at consecutive addresses.
+MIFFT_HD constexpr bool rows_entry_major(int L) { return L >= 13; }
+MIFFT_HD constexpr int row_slot(int L, int E, int P, int k, int r)
+{
+    return rows_entry_major(L) ? rows_offset(L, E, P) + r * (1 << sched_log2ns(L, E, P)) + k
+                               : rows_offset(L, E, P) + (k << E) + r;
+}
+
 // ---------------------------------------------------------------- LDS exchanges
 // pad(d) = d + (d >> B): one spare slot every 2^B elements, B per exchange
 // (exchange P follows pass P) chosen so the writes of pass P and the reads

@@ -74,12 +74,13 @@ __global__ void k_twiddle_rows(const float2* __restrict__ tw, float2* __restrict
     const idx::RowEntry w = idx::twiddle_row_entry(L, E, i);
     if (w.pass < 0)
         return;
+    const int slot = idx::row_slot(L, E, w.pass, w.k, w.r);
     if (w.table >= 0) {
-        rows[i] = tw[w.table];
+        rows[slot] = tw[w.table];
     } else {
         double sn, cs;
         sincospi(2.0 * (double)(w.r * w.k) / (double)(1 << w.mlog2), &sn, &cs);
-        rows[i] = float2{(float)cs, (float)(-sn)};
+        rows[slot] = float2{(float)cs, (float)(-sn)};
     }
 }
 

@@ -40,6 +40,15 @@ void im_row_entries(int L, int E, int count, int* out)
 }
 
 int im_pad_bits(int L, int E, int P) { return pad_bits(L, E, P); }
+
+// out[i] = storage slot of row entry i (row-major numbering)
+void im_row_slots(int L, int E, int count, int* out)
+{
+    for (int i = 0; i < count; i++) {
+        const RowEntry w = twiddle_row_entry(L, E, i);
+        out[i] = w.pass < 0 ? -1 : row_slot(L, E, w.pass, w.k, w.r);
+    }
+}
 int im_pad_index(int B, int d) { return pad_index(B, d); }
 int im_region(int L, int E) { return region(L, E); }
 int im_pad_is_affine(int L, int E, int P, int B) { return pad_is_affine(L, E, P, B) ? 1 : 0; }

@@ -122,6 +122,29 @@ def test_twiddle_rows_stay_inside_the_table(im, L, E):
     assert np.all(t * (1 << mlog2[in_table]) == 2048 * (r[in_table] * k[in_table]))
 
 
+@pytest.mark.parametrize("L,E", schedules())
+def test_row_storage_is_a_permutation(im, L, E):
+    """Row entries are stored row-major up to 4096 points and entry-major
+    within each pass from 8192 up (the single-pass kernels of those lengths
+    read every pass's rows once per transform, consecutive lanes taking
+    consecutive rows): either way a permutation of the table that keeps
+    each pass inside its own region."""
+    n = im.im_rows_total(L, E)
+    if n == 0:
+        return
+    slots = np.zeros(n, np.int32)
+    im.im_row_slots(L, E, n, ip(slots))
+    assert np.array_equal(np.sort(slots), np.arange(n))
+    rows = row_entries(im, L, E)
+    p, r, k = rows[:, 0], rows[:, 1], rows[:, 2]
+    off = np.array([im.im_rows_offset(L, E, int(q)) for q in p])
+    ns = 1 << np.array([im.im_log2ns(L, E, int(q)) for q in p])
+    if L >= 13:
+        assert np.array_equal(slots, off + r * ns + k)
+    else:
+        assert np.array_equal(slots, np.arange(n))
+
+
 @pytest.mark.parametrize("L,E", [(L, E) for L in range(2, 15) for E in range(2, 5) if E < L])
 def test_padded_exchanges_are_affine_distinct_and_in_bounds(im, L, E):
     N, EPT = 1 << L, 1 << E
